@@ -1,0 +1,581 @@
+"""Pins of the FP64 CPU oracle against what the mathematics fixes.
+
+None of these tests re-types the oracle's formulas: each checks a closed
+form, an invariant, a special case or a brute-force property, chosen so that
+a dropped term, a wrong sign or index, or a transposed operand fails one of
+them.  Paper: Sec. 5.1.1 (Eqs. 1-3) and the references it cites for the
+velocity sets, TRT, Guo forcing and Smagorinsky closure.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1909_13772_amd import inputs
+
+
+# --------------------------------------------------------------------------
+# Velocity sets: isotropy conditions fix the weights (textbook D3Q19/D3Q27)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [19, 27])
+def test_lattice_isotropy(q):
+    c, w, opp = O.stencil(q)
+    assert c.shape == (q, 3)
+    assert len({tuple(v) for v in c}) == q
+    assert tuple(c[0]) == (0, 0, 0)
+    for i in range(q):
+        assert np.all(c[opp[i]] == -c[i])
+        if i % 2 == 1:
+            assert opp[i] == i + 1
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.abs(w @ c).max() < 1e-17
+    second = np.einsum("i,ia,ib->ab", w, c, c)
+    assert np.allclose(second, np.eye(3) / 3.0, atol=1e-15, rtol=0)
+    third = np.einsum("i,ia,ib,ic->abc", w, c, c, c)
+    assert np.abs(third).max() < 1e-17
+    fourth = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    d = np.eye(3)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9.0
+    assert np.allclose(fourth, iso, atol=1e-15, rtol=0)
+
+
+def test_lattice_order_and_weights_textbook():
+    c, w, _ = O.stencil(19)
+    assert [tuple(v) for v in c[:7]] == [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0),
+                                         (0, 0, 1), (0, 0, -1)]
+    assert w[0] == 1 / 3 and w[1] == 1 / 18 and w[7] == 1 / 36
+    c27, w27, _ = O.stencil(27)
+    assert np.all(c27[:19] == c)
+    assert w27[0] == 8 / 27 and w27[1] == 2 / 27 and w27[7] == 1 / 54 and w27[19] == 1 / 216
+    assert np.all(np.abs(c27[19:]).sum(1) == 3)
+
+
+# --------------------------------------------------------------------------
+# Equilibrium and forcing moments
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [19, 27])
+def test_equilibrium_moments(q):
+    c, w, _ = O.stencil(q)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        rho = 1.0 + rng.uniform(-0.05, 0.05)
+        u = rng.uniform(-0.1, 0.1, 3)
+        de = O.equilibrium(q, rho, u)
+        f = w + de
+        assert abs(de.sum() - (rho - 1.0)) < 1e-16
+        assert np.allclose(c.T @ de, rho * u, atol=1e-16, rtol=0)
+        P = np.einsum("i,ia,ib->ab", f, c, c)
+        assert np.allclose(P, rho * (np.eye(3) / 3.0 + np.outer(u, u)), atol=2e-16, rtol=0)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_guo_moments(q):
+    c, w, _ = O.stencil(q)
+    rng = np.random.default_rng(2)
+    u = rng.uniform(-0.1, 0.1, 3)
+    F = rng.uniform(-1e-3, 1e-3, 3)
+    Fi = O.guo(q, u, F)
+    scale = np.abs(F).max()
+    assert abs(Fi.sum()) < 1e-15 * scale
+    assert np.allclose(c.T @ Fi, F, atol=1e-15 * scale, rtol=0)
+    S = np.einsum("i,ia,ib->ab", Fi, c, c)
+    assert np.allclose(S, np.outer(u, F) + np.outer(F, u), atol=1e-15 * scale, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# Collision: conservation, relaxation of individual moments, reductions
+# --------------------------------------------------------------------------
+def _random_cell(q, rng, amp=1e-3):
+    c, w, _ = O.stencil(q)
+    de = O.equilibrium(q, 1.0 + rng.uniform(-0.01, 0.01), rng.uniform(-0.05, 0.05, 3))
+    return de + amp * rng.uniform(-1, 1, q) * w
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("coll", [O.SRT, O.TRT, O.MRT])
+def test_collision_conserves_mass_and_momentum(q, coll):
+    c, w, _ = O.stencil(q)
+    rng = np.random.default_rng(3 + q + coll)
+    F = tuple(rng.uniform(-1e-4, 1e-4, 3))
+    p = O.Params(q=q, collision=coll, tau=0.7, magic=0.1, omega_bulk=1.3, omega_higher=1.1, force=F)
+    for _ in range(5):
+        d = _random_cell(q, rng)
+        dp, rho, u, tau = O.collide_cell(p, d)
+        eps = 1e-14 * np.abs(d).max()
+        assert abs(dp.sum() - d.sum()) < eps
+        assert np.allclose(c.T @ dp, c.T @ d + np.array(F), atol=eps, rtol=0)
+        assert abs(rho - (1 + d.sum())) < 1e-16
+        assert np.allclose(rho * u, c.T @ d + 0.5 * np.array(F), atol=eps, rtol=0)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_mrt_relaxes_each_moment_class_at_its_rate(q):
+    """Without force, each raw moment's non-equilibrium part is scaled by
+    (1 - s): shear moments with 1/tau, the trace with omega_bulk, a third-order
+    moment with omega_higher.  Moments computed here directly from c."""
+    c, w, _ = O.stencil(q)
+    rng = np.random.default_rng(7)
+    tau, ob, oh = 0.7, 1.3, 0.6
+    p = O.Params(q=q, collision=O.MRT, tau=tau, omega_bulk=ob, omega_higher=oh)
+    d = _random_cell(q, rng, amp=1e-2)
+    dp, rho, u, _ = O.collide_cell(p, d)
+    de = O.equilibrium(q, rho, u)
+    x, y, z = c[:, 0], c[:, 1], c[:, 2]
+    checks = [(x * y, 1 / tau), (x * z, 1 / tau), (y * z, 1 / tau), (x * x - y * y, 1 / tau),
+              (x * x - z * z, 1 / tau), (x * x + y * y + z * z, ob), (x * x * y, oh), (x * z * z, oh),
+              (x * x * y * y, oh)]
+    for mono, s in checks:
+        before = mono @ (d - de)
+        after = mono @ (dp - de)
+        assert abs(after - (1 - s) * before) < 1e-15, (mono, s)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_mrt_with_equal_rates_is_srt(q):
+    rng = np.random.default_rng(11)
+    F = tuple(rng.uniform(-1e-4, 1e-4, 3))
+    tau = 0.83
+    srt = O.Params(q=q, collision=O.SRT, tau=tau, force=F)
+    mrt = O.Params(q=q, collision=O.MRT, tau=tau, omega_bulk=1 / tau, omega_higher=1 / tau, force=F)
+    for _ in range(5):
+        d = _random_cell(q, rng)
+        a = O.collide_cell(srt, d)[0]
+        b = O.collide_cell(mrt, d)[0]
+        assert np.abs(a - b).max() < 1e-13 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_trt_with_equal_times_is_srt(q):
+    """Lambda = (tau - 1/2)^2 makes tau- = tau+, which is SRT."""
+    rng = np.random.default_rng(12)
+    F = tuple(rng.uniform(-1e-4, 1e-4, 3))
+    tau = 0.77
+    srt = O.Params(q=q, collision=O.SRT, tau=tau, force=F)
+    trt = O.Params(q=q, collision=O.TRT, tau=tau, magic=(tau - 0.5) ** 2, force=F)
+    for _ in range(5):
+        d = _random_cell(q, rng)
+        a = O.collide_cell(srt, d)[0]
+        b = O.collide_cell(trt, d)[0]
+        assert np.abs(a - b).max() < 1e-15
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_trt_relaxes_symmetric_and_antisymmetric_parts(q):
+    c, w, opp = O.stencil(q)
+    rng = np.random.default_rng(13)
+    tau, lam = 0.9, 3.0 / 16.0
+    taum = 0.5 + lam / (tau - 0.5)
+    p = O.Params(q=q, collision=O.TRT, tau=tau, magic=lam)
+    d = _random_cell(q, rng, amp=1e-2)
+    dp, rho, u, _ = O.collide_cell(p, d)
+    de = O.equilibrium(q, rho, u)
+    n, npost = d - de, dp - de
+    sym, asym = 0.5 * (n + n[opp]), 0.5 * (n - n[opp])
+    sp, ap = 0.5 * (npost + npost[opp]), 0.5 * (npost - npost[opp])
+    eps = 1e-14 * np.abs(d).max()
+    assert np.abs(sp - (1 - 1 / tau) * sym).max() < eps
+    assert np.abs(ap - (1 - 1 / taum) * asym).max() < eps
+
+
+def test_mrt_matrix_rank_and_inverse():
+    for q in (19, 27):
+        M, Mi, kind = O.mrt_matrix(q)
+        assert np.linalg.matrix_rank(M) == q
+        assert np.abs(M @ Mi - np.eye(q)).max() < 1e-13
+        assert sorted(np.bincount(kind)) == sorted([4, 5, 1, q - 10])
+
+
+# --------------------------------------------------------------------------
+# Fixed points, streaming, symmetry
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("coll", [O.SRT, O.TRT, O.MRT])
+def test_rest_state_is_bitwise_fixed_point(coll):
+    q = 27 if coll == O.MRT else 19
+    shape = (12, 10, 8)
+    solid, _, _ = inputs.spheres(shape, seed=1, rmin=1.5, rmax=2.5, solid_fraction=0.1, clear_x=2)
+    rho, u = inputs.uniform_state(shape)
+    d = O.init(q, shape, rho, u, solid)
+    assert np.all(d == 0)
+    p = O.Params(q=q, collision=coll, tau=0.8, periodic=(0, 0, 1), pressure_axis=0)
+    out = O.run(p, shape, d, 6, solid)
+    assert np.all(out == 0)
+
+
+@pytest.mark.parametrize("coll", [O.SRT, O.TRT, O.MRT])
+def test_uniform_flow_is_fixed_point(coll):
+    q = 27 if coll == O.MRT else 19
+    shape = (6, 5, 4)
+    rho, u = inputs.uniform_state(shape, rho=1.01, u=(0.03, -0.02, 0.01))
+    d = O.init(q, shape, rho, u)
+    p = O.Params(q=q, collision=coll, tau=0.7, omega_bulk=1.2, omega_higher=1.1)
+    ulp = np.spacing(np.abs(d).max())
+    assert np.abs(O.run(p, shape, d, 1) - d).max() <= 4 * ulp
+    # rounding does not accumulate: the state stays within a few ulp
+    assert np.abs(O.run(p, shape, d, 50) - d).max() <= 16 * ulp
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_periodic_streaming_is_a_roll(q):
+    c, w, _ = O.stencil(q)
+    shape = (7, 5, 4)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(4)
+    post = rng.standard_normal((q, nx * ny * nz))
+    p = O.Params(q=q)
+    out = O.stream(p, shape, post)
+    for i in range(q):
+        g = post[i].reshape(nz, ny, nx)
+        exp = np.roll(g, shift=(c[i, 2], c[i, 1], c[i, 0]), axis=(0, 1, 2))
+        assert np.array_equal(out[i].reshape(nz, ny, nx), exp)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_wall_streaming_bounces_back(q):
+    """Walls in y: populations that would come from y = -1 or y = ny are the
+    cell's own opposite post-collision values; interior links are a roll."""
+    c, w, opp = O.stencil(q)
+    shape = (4, 6, 3)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(5)
+    post = rng.standard_normal((q, nx * ny * nz))
+    p = O.Params(q=q, periodic=(1, 0, 1))
+    out = O.stream(p, shape, post)
+    for i in range(q):
+        g = post[i].reshape(nz, ny, nx)
+        exp = np.roll(g, shift=(c[i, 2], c[i, 1], c[i, 0]), axis=(0, 1, 2))
+        own = post[opp[i]].reshape(nz, ny, nx)
+        if c[i, 1] == 1:
+            exp[:, 0, :] = own[:, 0, :]
+        if c[i, 1] == -1:
+            exp[:, ny - 1, :] = own[:, ny - 1, :]
+        assert np.array_equal(out[i].reshape(nz, ny, nx), exp), i
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_streaming_with_walls_and_solids_is_a_permutation(q):
+    shape = (10, 9, 8)
+    nx, ny, nz = shape
+    solid, _, _ = inputs.spheres(shape, seed=3, rmin=1.5, rmax=3.0, solid_fraction=0.2, clear_x=0,
+                                 periodic=(1, 0, 1))
+    fl = solid.reshape(-1) == 0
+    rng = np.random.default_rng(6)
+    post = rng.standard_normal((q, nx * ny * nz))
+    post[:, ~fl] = 0.0
+    p = O.Params(q=q, periodic=(1, 0, 1))
+    out = O.stream(p, shape, post, solid)
+    assert np.array_equal(np.sort(post[:, fl].ravel()), np.sort(out[:, fl].ravel()))
+
+
+def _run_moments(p, shape, rho, u, steps, solid=None):
+    d = O.init(p.q, shape, rho, u, solid)
+    d = O.run(p, shape, d, steps, solid)
+    return O.moments(p.q, p.force, shape, d, solid)
+
+
+@pytest.mark.parametrize("coll", [O.SRT, O.TRT, O.MRT])
+def test_rotation_about_z_commutes_with_the_update(coll):
+    """Rotating the initial state by 90 degrees about z rotates the result.
+    np.rot90 over the (y, x) axes maps the cell (x, y) to (y, n-1-x), i.e.
+    vectors (v_x, v_y) -> (v_y, -v_x)."""
+    q = 27 if coll == O.MRT else 19
+    n, nz = 8, 4
+    shape = (n, n, nz)
+    rho, u = inputs.random_state(shape, seed=9)
+    F = (2e-5, -1e-5, 3e-6)
+    p = O.Params(q=q, collision=coll, tau=0.74, omega_bulk=1.2, omega_higher=0.9, force=F)
+    r0, u0, _ = _run_moments(p, shape, rho, u, 3)
+    rot = lambda a: np.rot90(a, k=1, axes=(1, 2))  # noqa: E731  (z, y, x) arrays
+    rho_r = rot(rho)
+    u_r = np.stack([rot(u[1]), -rot(u[0]), rot(u[2])])
+    p_r = O.Params(q=q, collision=coll, tau=0.74, omega_bulk=1.2, omega_higher=0.9,
+                   force=(F[1], -F[0], F[2]))
+    r1, u1, _ = _run_moments(p_r, shape, np.ascontiguousarray(rho_r), np.ascontiguousarray(u_r), 3)
+    r0 = r0.reshape(nz, n, n)
+    u0 = u0.reshape(3, nz, n, n)
+    assert np.abs(r1.reshape(nz, n, n) - rot(r0)).max() < 1e-14
+    u1 = u1.reshape(3, nz, n, n)
+    assert np.abs(u1[0] - rot(u0[1])).max() < 1e-14
+    assert np.abs(u1[1] + rot(u0[0])).max() < 1e-14
+    assert np.abs(u1[2] - rot(u0[2])).max() < 1e-14
+
+
+def test_integer_shift_commutes_bitwise():
+    shape = (8, 6, 5)
+    rho, u = inputs.random_state(shape, seed=10)
+    p = O.Params(q=19, collision=O.TRT, tau=0.9)
+    r0, u0, _ = _run_moments(p, shape, rho, u, 4)
+    sh = (2, 3, 1)  # (z, y, x)
+    rho_s = np.roll(rho, sh, axis=(0, 1, 2))
+    u_s = np.roll(u, sh, axis=(1, 2, 3))
+    r1, u1, _ = _run_moments(p, shape, rho_s, u_s, 4)
+    assert np.array_equal(r1.reshape(5, 6, 8), np.roll(r0.reshape(5, 6, 8), sh, axis=(0, 1, 2)))
+    assert np.array_equal(u1.reshape(3, 5, 6, 8), np.roll(u0.reshape(3, 5, 6, 8), sh, axis=(1, 2, 3)))
+
+
+@pytest.mark.parametrize("q,coll", [(19, O.SRT), (19, O.TRT), (27, O.MRT)])
+def test_mass_conserved_with_walls_and_spheres(q, coll):
+    shape = (12, 10, 9)
+    solid, _, _ = inputs.spheres(shape, seed=2, rmin=1.5, rmax=2.5, solid_fraction=0.15, clear_x=0,
+                                 periodic=(1, 0, 1))
+    rho, u = inputs.random_state(shape, seed=3)
+    p = O.Params(q=q, collision=coll, tau=0.66, periodic=(1, 0, 1), force=(1e-5, 0, 0))
+    d0 = O.init(q, shape, rho, u, solid)
+    _, _, t0 = O.moments(q, p.force, shape, d0, solid)
+    d1 = O.run(p, shape, d0, 20, solid)
+    _, _, t1 = O.moments(q, p.force, shape, d1, solid)
+    assert abs(t1[0] - t0[0]) < 1e-12
+    assert t1[6] == t0[6]
+
+
+# --------------------------------------------------------------------------
+# Physics: Taylor-Green decay, Poiseuille (steady and transient), pressure
+# --------------------------------------------------------------------------
+def _energy(q, shape, d):
+    rho, u, tot = O.moments(q, (0, 0, 0), shape, d)
+    return tot[4]
+
+
+def test_taylor_green_decay_32():
+    """z-invariant TGV, tau = 0.8 (nu = 0.1), k = 2 pi / 32: E(t) = E(0) exp(-4 nu k^2 t)."""
+    n, steps, tau = 32, 100, 0.8
+    rho, u = inputs.taylor_green(n, 0.01, nz=2)
+    shape = (n, n, 2)
+    d0 = O.init(19, shape, rho, u)
+    p = O.Params(q=19, collision=O.SRT, tau=tau)
+    d1 = O.run(p, shape, d0, steps)
+    ratio = _energy(19, shape, d1) / _energy(19, shape, d0)
+    k = 2 * math.pi / n
+    nu = (tau - 0.5) / 3
+    exact = math.exp(-4 * nu * k * k * steps)
+    assert abs(exact - 0.2139) < 5e-4
+    assert abs(ratio - exact) < 0.02 * exact
+
+
+def test_taylor_green_second_order_convergence():
+    """Diffusive scaling (u0 ~ 1/n, t ~ n^2): the velocity error falls ~4x per doubling."""
+    tau = 0.8
+    nu = (tau - 0.5) / 3
+    errs = []
+    for n in (16, 32, 64):
+        u0 = 0.02 * 16 / n
+        steps = int(50 * (n / 16) ** 2)
+        rho, u = inputs.taylor_green(n, u0, nz=1)
+        shape = (n, n, 1)
+        d = O.run(O.Params(q=19, collision=O.SRT, tau=tau), shape, O.init(19, shape, rho, u), steps)
+        _, uu, _ = O.moments(19, (0, 0, 0), shape, d)
+        k = 2 * math.pi / n
+        decay = math.exp(-2 * nu * k * k * steps)
+        ex = u[0].reshape(-1) * decay
+        errs.append(np.linalg.norm(uu[0] - ex) / np.linalg.norm(ex))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, errs
+
+
+def test_trt_magic_poiseuille_is_exact():
+    """TRT with Lambda = 3/16, half-way bounce-back and Guo force reproduces
+    the parabola u(s) = g s (H - s) / (2 nu), s = y + 1/2, exactly."""
+    H, tau, g = 16, 0.8, 1e-5
+    shape = (1, H, 1)
+    rho, u = inputs.uniform_state(shape)
+    p = O.Params(q=19, collision=O.TRT, tau=tau, magic=3 / 16, force=(g, 0, 0), periodic=(1, 0, 1))
+    d = O.run(p, shape, O.init(19, shape, rho, u), 12000)
+    r, uu, _ = O.moments(19, p.force, shape, d)
+    nu = (tau - 0.5) / 3
+    s = np.arange(H) + 0.5
+    # body force density g with rho ~ 1: exact profile uses rho * u = g s (H - s) / (2 nu rho)
+    exact = g * s * (H - s) / (2 * nu)
+    assert np.abs(uu[0] * r - exact).max() < 1e-10 * exact.max()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_srt_poiseuille_has_tau_dependent_slip(q):
+    """SRT with half-way bounce-back is not exact at tau != 1 (known viscosity-
+    dependent wall slip); the oracle must show that error, with the sign
+    flipping across tau^2 ~ 3/16-ish.  Guards against a silently 'exact' SRT."""
+    H, g = 16, 1e-5
+    shape = (1, H, 1)
+    rho, u = inputs.uniform_state(shape)
+    errs = []
+    for tau in (0.6, 1.5):
+        p = O.Params(q=q, collision=O.SRT, tau=tau, force=(g, 0, 0), periodic=(1, 0, 1))
+        d = O.run(p, shape, O.init(q, shape, rho, u), 30000 if tau < 1 else 8000)
+        r, uu, _ = O.moments(q, p.force, shape, d)
+        nu = (tau - 0.5) / 3
+        s = np.arange(H) + 0.5
+        exact = g * s * (H - s) / (2 * nu)
+        errs.append((uu[0] * r - exact).mean() / exact.max())
+    assert abs(errs[1]) > 1e-4
+
+
+def test_transient_poiseuille_series_256():
+    """Start-up channel flow (H = 256, tau = 0.8, g = 1e-6) at t = 2000 against
+    the Fourier-series solution of the diffusion equation."""
+    H, tau, g, T = 256, 0.8, 1e-6, 2000
+    shape = (1, H, 1)
+    rho, u = inputs.uniform_state(shape)
+    p = O.Params(q=19, collision=O.TRT, tau=tau, magic=3 / 16, force=(g, 0, 0), periodic=(1, 0, 1))
+    d = O.run(p, shape, O.init(19, shape, rho, u), T)
+    r, uu, _ = O.moments(19, p.force, shape, d)
+    nu = (tau - 0.5) / 3
+    s = np.arange(H) + 0.5
+    ser = g * s * (H - s) / (2 * nu)
+    for n in range(1, 4000, 2):
+        ser -= 4 * g * H * H / (nu * math.pi ** 3 * n ** 3) * np.sin(n * math.pi * s / H) * \
+            math.exp(-n * n * math.pi ** 2 * nu * T / (H * H))
+    umax = ser.max()
+    assert 1.9e-3 < umax < 2.1e-3
+    assert np.abs(uu[0] - ser).max() < 1e-2 * umax
+
+
+def test_pressure_boundaries_drive_flow_from_high_to_low_density():
+    """Anti-bounce-back density faces on x, walls on y: at steady state the
+    flux is the same through every x-plane, flow runs from rho_in to rho_out,
+    the linear density profile extrapolates to rho_in at x = -1/2 and to
+    rho_out at x = nx - 1/2, and the mean velocity matches plane Poiseuille
+    flow driven by the gradient c_s^2 d(rho)/dx."""
+    nx, H, tau = 48, 8, 0.8
+    shape = (nx, H, 1)
+    rin, rout = 1.001, 0.999
+    p = O.Params(q=19, collision=O.SRT, tau=tau, periodic=(0, 0, 1), pressure_axis=0, rho_in=rin,
+                 rho_out=rout)
+    rho, u = inputs.uniform_state(shape)
+    d = O.run(p, shape, O.init(19, shape, rho, u), 30000)
+    r, uu, _ = O.moments(19, p.force, shape, d)
+    r = r.reshape(1, H, nx)[0]
+    ux = uu[0].reshape(1, H, nx)[0]
+    flux = (r * ux).sum(0)
+    assert flux.min() > 0
+    assert (flux.max() - flux.min()) < 1e-8 * flux.mean()
+    rbar = r.mean(0)
+    xs = np.arange(nx)
+    mid = slice(nx // 4, 3 * nx // 4)
+    a, b = np.polyfit(xs[mid], rbar[mid], 1)
+    drop = rin - rout
+    assert abs((a * -0.5 + b) - rin) < 0.05 * drop
+    assert abs((a * (nx - 0.5) + b) - rout) < 0.05 * drop
+    nu = (tau - 0.5) / 3
+    umean_exact = H * H / (12 * nu) * (-a / 3.0)
+    assert abs(ux.mean() - umean_exact) < 0.05 * umean_exact
+
+
+# --------------------------------------------------------------------------
+# Closures
+# --------------------------------------------------------------------------
+def test_smagorinsky_zero_constant_is_plain_srt_bitwise():
+    rng = np.random.default_rng(21)
+    shape = (6, 5, 4)
+    rho, u = inputs.random_state(shape, seed=4)
+    d = O.init(19, shape, rho, u)
+    d = O.run(O.Params(q=19, tau=0.7), shape, d, 1)  # non-equilibrium content
+    a = O.run(O.Params(q=19, tau=0.7), shape, d, 3)
+    b = O.run(O.Params(q=19, tau=0.7, closure=O.CLOSURE_SMAG, cs_smag=0.0), shape, d, 3)
+    assert np.array_equal(a, b)
+    del rng
+
+
+def test_smagorinsky_tau_solves_its_quadratic():
+    c, w, _ = O.stencil(19)
+    rng = np.random.default_rng(22)
+    tau0, cs = 0.5075, 0.1
+    p = O.Params(q=19, tau=tau0, closure=O.CLOSURE_SMAG, cs_smag=cs)
+    for _ in range(5):
+        d = _random_cell(19, rng, amp=5e-2)
+        _, rho, u, tau = O.collide_cell(p, d)
+        de = O.equilibrium(19, rho, u)
+        Pi = np.einsum("i,ia,ib->ab", d - de, c, c)
+        Q = float((Pi * Pi).sum())
+        resid = tau * tau - tau0 * tau - 9 * math.sqrt(2) * cs * cs * math.sqrt(Q) / (2 * rho)
+        assert abs(resid) < 1e-14
+        assert tau > tau0
+
+
+def test_bf16_rounding_known_values():
+    assert O.bf16_round(1.0) == 1.0
+    assert O.bf16_round(1 + 2 ** -8) == 1.0  # tie -> even
+    assert O.bf16_round(1 + 3 * 2 ** -8) == 1 + 2 ** -6  # tie -> even (up)
+    assert O.bf16_round(1 + 2 ** -8 + 2 ** -20) == 1 + 2 ** -7
+    assert O.bf16_round(-3.0) == -3.0
+    assert O.bf16_round(2.0 ** -130) == 2.0 ** -130  # subnormal kept (no flush)
+
+
+def test_gelu_and_softplus_special_values():
+    assert O.gelu(0.0) == 0.0
+    for z in (0.3, 1.7, 4.0):
+        assert abs(O.gelu(z) - O.gelu(-z) - z) < 1e-15
+    assert abs(O.gelu(40.0) - 40.0) < 1e-12 and abs(O.gelu(-40.0)) < 1e-12
+    assert abs(O.gelu(1.0) - 0.5 * (1 + 0.6826894921370859)) < 1e-15  # erf(1/sqrt2) = P(|Z|<1)
+    assert O.softplus(0.0) == math.log(2.0)
+    assert abs(O.softplus(-50.0)) < 1e-21
+
+
+def test_mlp_zero_last_layer_gives_tau0_plus_ln2():
+    P = inputs.mlp_params(5).astype(np.float64)
+    P[O.MLP_OFF_W3:O.MLP_OFF_W3 + O.MLP_H] = 0.0
+    P[O.MLP_OFF_B3] = 0.0
+    rng = np.random.default_rng(23)
+    p = O.Params(q=19, tau=0.6, closure=O.CLOSURE_MLP, cs_smag=0.1, mlp=P)
+    for _ in range(3):
+        d = _random_cell(19, rng, amp=1e-2)
+        tau = O.collide_cell(p, d)[3]
+        assert tau == 0.6 + math.log(2.0)
+
+
+def test_mlp_structured_weights_select_one_path():
+    """W1 has a single 1 at (row 3, col 5), W2 a single 1 at (row 0, col 3),
+    w3 = e_0: o = gelu(gelu(bf16(x_5))) exactly (pins row = output, col = input)."""
+    P = np.zeros(O.MLP_NPARAM)
+    P[O.MLP_OFF_ISTD:O.MLP_OFF_ISTD + 7] = 1.0
+    P[O.MLP_OFF_W1 + 3 * 7 + 5] = 1.0
+    P[O.MLP_OFF_W2 + 0 * 32 + 3] = 1.0
+    P[O.MLP_OFF_W3 + 0] = 1.0
+    raw = np.zeros((4, 7))
+    raw[:, 5] = [0.25, -1.5, 2.0, 0.75]
+    raw[:, 2] = 5.0  # must not leak into the output
+    o, flag = O.mlp_forward(P, raw)
+    for s in range(4):
+        exp = O.bf16_round(O.gelu(O.bf16_round(O.gelu(raw[s, 5]))))
+        assert o[s] == exp
+    assert not flag.any()
+    raw[0, 1] = 9.0  # outside |x| <= 8 -> fallback flagged
+    assert O.mlp_forward(P, raw)[1][0] == 1
+
+
+def test_mlp_backward_matches_finite_differences():
+    rng = np.random.default_rng(24)
+    P = inputs.mlp_params(7, mean=rng.uniform(-0.1, 0.1, 7), inv_std=rng.uniform(0.5, 2, 7)).astype(np.float64)
+    raw = rng.uniform(-1, 1, (64, 7))
+    t = rng.uniform(0.0, 0.2, 64)
+    O.mlp_set_rounding(False)
+    try:
+        g, L0 = O.mlp_backward(P, raw, t, 3.0)
+        idx = list(range(O.MLP_OFF_W1, O.MLP_NPARAM, 17)) + [O.MLP_OFF_B3, O.MLP_OFF_W3 + 31]
+        for k in idx:
+            h = 1e-6
+            Pp, Pm = P.copy(), P.copy()
+            Pp[k] += h
+            Pm[k] -= h
+            Lp = O.mlp_backward(Pp, raw, t, 3.0)[1]
+            Lm = O.mlp_backward(Pm, raw, t, 3.0)[1]
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - g[k]) < 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
+        assert np.all(g[:14] == 0)
+    finally:
+        O.mlp_set_rounding(True)
+
+
+# --------------------------------------------------------------------------
+# Reductions
+# --------------------------------------------------------------------------
+def test_totals_match_fsum():
+    shape = (9, 8, 7)
+    rho, u = inputs.random_state(shape, seed=31)
+    d = O.init(19, shape, rho, u)
+    r, uu, tot = O.moments(19, (0, 0, 0), shape, d)
+    ex_mass = math.fsum(r)
+    assert abs(tot[0] - ex_mass) <= np.spacing(ex_mass)
+    ex_px = math.fsum(r * uu[0])
+    assert abs(tot[1] - ex_px) <= 2 * np.spacing(abs(ex_px))
+    assert tot[6] == 9 * 8 * 7
+    assert tot[5] == np.sqrt((uu ** 2).sum(0)).max()
