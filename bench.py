@@ -1,0 +1,226 @@
+"""Benchmark: lattice Boltzmann stream-collide on one MI355X.
+
+Workload (headline): D3Q19 TRT (Lambda = 3/16), single block 256^3, FP64
+deviation storage, channel with half-way bounce-back walls in y, periodic
+x/z, Guo body force f_x = 1e-6, tau = 0.8, starting from rest; one step is
+one AA sweep over all cells plus the ghost-layer exchange.  The same
+configuration is also timed with FP32, FP16 and BF16 deviation storage and
+with the Smagorinsky closure (the "variants").
+
+Prints ONE JSON line with MLUPS, the HBM roofline fraction of the sweep
+kernel (algorithmic bytes / measured kernel time, HIP events on the
+library's stream), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 256
+TAU, MAGIC, FX = 0.8, 3.0 / 16.0, 1e-6
+SWEEP_SOURCES = ["paper_1909_13772_amd/csrc/sweep_impl.hpp", "paper_1909_13772_amd/csrc/lattice.hpp",
+                 "paper_1909_13772_amd/csrc/wlb_internal.hpp"]
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(storage_name: str):
+    """HBM bytes per sweep launch from a committed rocprofv3 counter summary,
+    only if it was taken on the current sweep source."""
+    path = os.path.join(ROOT, "profiles", "sweep_channel256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != sweep_source_hash():
+        return None
+    e = t.get("storage", {}).get(storage_name)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def poiseuille_series(H, nu, g, T, s):
+    u = g * s * (H - s) / (2 * nu)
+    for n in range(1, 4000, 2):
+        u -= 4 * g * H * H / (nu * math.pi ** 3 * n ** 3) * __import__("numpy").sin(n * math.pi * s / H) * \
+            math.exp(-n * n * math.pi ** 2 * nu * T / (H * H))
+    return u
+
+
+def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False):
+    import numpy as np
+    import torch
+
+    shape = (N, N, N)
+    rho, u = inputs.uniform_state(shape)
+    p = wlb.make_params(tau=TAU, magic=MAGIC, force=(FX, 0.0, 0.0), closure=closure, cs_smag=0.1 if closure else 0.0,
+                        autotune=1)
+    B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=19, storage=storage)
+    try:
+        B.init(wlb.TRT, p, rho, u)
+        B.step(warmup)
+        B.synchronize()
+        B.set_kernel_timing(True)
+        torch.cuda.synchronize()
+        B.synchronize()
+        t0 = time.perf_counter()
+        B.step(steps)
+        B.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms, cnt = B.kernel_times()
+        B.set_kernel_timing(False)
+        info = B.info()
+        res = {"seconds": t1 - t0, "kernel_ms": ms, "launches": cnt, "tile": list(info.tile), "grid": info.grid,
+               "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems}
+        if check:
+            r, uu, tot = B.moments()
+            nu = (TAU - 0.5) / 3
+            s = np.arange(N) + 0.5
+            ref = poiseuille_series(N, nu, FX, warmup + steps, s)
+            prof = uu[0].mean(axis=(0, 2))
+            res["poiseuille_err"] = float(np.abs(prof - ref).max() / ref.max())
+            res["mass_drift"] = float(abs(tot[0] - N ** 3) / N ** 3)
+        return res
+    finally:
+        B.close()
+
+
+def summarize(res, storage, steps, elem_bytes, q=19):
+    cells = N ** 3
+    sweeps = res["launches"][0] + res["launches"][1]
+    sweep_ms = (res["kernel_ms"][0] + res["kernel_ms"][1]) / max(1, sweeps)
+    xchg_ms = (res["kernel_ms"][2] + res["kernel_ms"][3]) / max(1, res["launches"][2] + res["launches"][3])
+    bytes_per_launch = cells * 2 * q * elem_bytes
+    achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9
+    return {
+        "mlups": cells * steps / res["seconds"] / 1e6,
+        "ms_per_step": res["seconds"] * 1e3 / steps,
+        "sweep_ms": sweep_ms,
+        "exchange_ms": xchg_ms,
+        "achieved_gbs": achieved,
+        "frac": achieved / HBM_PEAK_GBS,
+        "bytes_per_launch": bytes_per_launch,
+    }
+
+
+def cpu_baseline(inputs):
+    import numpy as np
+
+    import oracle as O
+
+    nthreads = min(16, os.cpu_count() or 1)
+    shape = (N, N, N)
+    steps = 2
+    rho, u = inputs.uniform_state(shape)
+    p = O.Params(q=19, collision=O.TRT, tau=TAU, magic=MAGIC, force=(FX, 0, 0), periodic=(1, 0, 1))
+    d = O.init(19, shape, rho, u)
+    t0 = time.perf_counter()
+    O.run(p, shape, d, steps, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    del d
+    return {"value": N ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
+            "sample": f"full 256^3 channel, D3Q19 TRT FP64, {steps} steps ({dt:.1f} s), OpenMP threads={nthreads}"}
+
+
+def copy_probe(wlb):
+    import torch
+
+    nbytes = 4 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    ms = wlb.wlb_copy_probe(b.data_ptr(), a.data_ptr(), nbytes, 10, s.cuda_stream)
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--variant-steps", type=int, default=500)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (blocks would shard over GPUs "
+              "by exchanging face slabs; not built).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1909_13772_amd import inputs, wlb
+
+    torch.cuda.set_device(0)
+    print(f"[bench] device {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True)
+    head = summarize(res, wlb.F64, args.steps, 8)
+    print(f"[bench] f64: {head['mlups']:.0f} MLUPS, sweep {head['sweep_ms']:.3f} ms, "
+          f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    variants = {}
+    if not args.no_variants:
+        for name, st, eb, cl in (("f32", wlb.F32, 4, 0), ("f16dev", wlb.F16DEV, 2, 0), ("bf16dev", wlb.BF16DEV, 2, 0),
+                                 ("f32_smagorinsky", wlb.F32, 4, 1)):
+            r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl)
+            sm = summarize(r, st, args.variant_steps, eb)
+            variants[name] = {"mlups": round(sm["mlups"], 1), "roofline_frac": round(sm["frac"], 4),
+                              "achieved_gbs": round(sm["achieved_gbs"], 1), "sweep_ms": round(sm["sweep_ms"], 4),
+                              "steps": args.variant_steps}
+            print(f"[bench] {name}: {sm['mlups']:.0f} MLUPS, {sm['achieved_gbs']:.0f} GB/s", file=sys.stderr,
+                  flush=True)
+    try:
+        copy_gbs = copy_probe(wlb)
+    except Exception as e:  # the probe is context only
+        print(f"[bench] copy probe failed: {e}", file=sys.stderr)
+        copy_gbs = None
+    cpu = None if args.no_cpu else cpu_baseline(inputs)
+    traffic = load_traffic("f64")
+    out = {
+        "metric": "MLUPS + % HBM roofline: plain FP64 vs FP32/FP16-store vs learned closure",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "D3Q19 TRT (Lambda 3/16) channel 256^3, one block, FP64 deviation storage, "
+                               "bounce-back walls in y, periodic x/z, Guo force fx=1e-6, tau=0.8, from rest",
+                   "cells": N ** 3, "stencil": "D3Q19", "collision": "TRT", "storage": "f64",
+                   "tile": res["tile"], "grid": res["grid"]},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(head["frac"], 4), "traffic": traffic,
+                     "kernel": "sweep_kernel<19,TRT,double> (even and odd AA sweeps)",
+                     "algorithmic_bytes_per_launch": head["bytes_per_launch"],
+                     "avg_launch_ms": round(head["sweep_ms"], 5)},
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "exchange_ms_per_step": round(head["exchange_ms"], 5),
+        "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+        "check": {"poiseuille_rel_err": res.get("poiseuille_err"), "mass_rel_drift": res.get("mass_drift")},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * wlb.h -- C ABI of the MI355X lattice Boltzmann library (libwlb.so).
+ *
+ * The library advances the lattice Boltzmann method over a list of
+ * structured blocks on one GPU, following Bauer et al., "waLBerla: A
+ * block-structured high-performance framework for multiphysics simulations":
+ *   - blocks are containers of uniformly gridded cells with one ghost layer
+ *     (Sec. 3.1 and Sec. 4.1);
+ *   - a sweep (kernel) runs on every block, then a ghost-layer exchange
+ *     between neighbouring blocks makes the state consistent (Sec. 4.2);
+ *     between blocks on the same device the exchange is a direct copy
+ *     without buffers (Sec. 3.3);
+ *   - the sweep is the fused collide-and-stream update of Eq. 2 with the
+ *     moments of Eq. 1 and the MRT operator of Eq. 3 (SRT and TRT as special
+ *     relaxation matrices), a relaxation time that may vary per cell from a
+ *     closure, bounce-back / pressure boundaries and a body force
+ *     (Sec. 5.1.1);
+ *   - initial data and results live in host arrays that are copied to and
+ *     from the device only at set-up and after many steps (Sec. 4.3).
+ *
+ * Conventions
+ *   Velocity sets: D3Q19 / D3Q27.  Direction 0 is rest; 1..6 are
+ *     (+-1,0,0), (0,+-1,0), (0,0,+-1); 7..18 the edges (1,1,0), (-1,-1,0),
+ *     (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1),
+ *     (0,-1,-1), (0,1,-1), (0,-1,1); 19..26 (D3Q27 only) the corners
+ *     (1,1,1), (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1), (-1,1,-1),
+ *     (-1,1,1), (1,-1,-1).  The opposite of an odd direction i is i+1.
+ *     Weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216;
+ *     c_s^2 = 1/3.
+ *   State: populations are stored as deviations d_i = f_i - w_i.
+ *   Global host arrays cover the bounding box `domain` with x fastest,
+ *     then y, then z: scalar fields [N], vector fields [3][N] (component
+ *     major), population fields [q][N], N = domain[0]*domain[1]*domain[2].
+ *   Status: every int-returning call returns WLB_OK (0) or a negative
+ *     WLB_ERR_* code; wlb_last_error() then describes the failure (per
+ *     thread).  No C++ exception crosses the ABI.
+ *   Ownership: host arrays belong to the caller and are only read or written
+ *     during the call.  Device memory is one arena that the caller allocates
+ *     (size from wlb_blocks_create) and binds; the library never allocates
+ *     or frees device memory.  The handle owns host-side descriptors, the
+ *     captured HIP graph and the tuning state.
+ *   Streams: all device work is enqueued on the stream given to
+ *     wlb_blocks_bind.  Calls that return host data synchronise that stream.
+ *     A handle must not be used from two threads at once.
+ */
+#ifndef WLB_H
+#define WLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WLB_OK 0
+#define WLB_ERR_ARG (-1)         /* bad sizes, blocks that do not tile the domain, tau <= 1/2, ... */
+#define WLB_ERR_HIP (-2)         /* a HIP runtime call failed */
+#define WLB_ERR_STATE (-3)       /* call out of order (e.g. step before bind/init) */
+#define WLB_ERR_DIVERGED (-4)    /* health check: non-finite mass or max|u| above the limit */
+#define WLB_ERR_UNSUPPORTED (-5) /* combination not implemented */
+
+enum { WLB_D3Q19 = 19, WLB_D3Q27 = 27 };
+enum { WLB_SRT = 0, WLB_TRT = 1, WLB_MRT = 2 };
+/* storage type of the deviations; collision runs in FP64 for WLB_F64 and in
+ * FP32 otherwise; conversions round to nearest even, no denormal flush */
+enum { WLB_F64 = 0, WLB_F32 = 1, WLB_F16DEV = 2, WLB_BF16DEV = 3 };
+enum { WLB_CLOSURE_NONE = 0, WLB_CLOSURE_SMAG = 1, WLB_CLOSURE_MLP = 2 };
+
+/* Number of float parameters of the MLP closure (7 -> 32 -> 32 -> 1), packed
+ * as mean[7], inv_std[7], W1[32][7], b1[32], W2[32][32], b2[32], w3[32], b3
+ * (row = output unit, column = input). */
+#define WLB_MLP_NPARAM 1359
+
+typedef struct wlb_blocks *wlb_blocks_t;
+
+/* One block: global cell coordinates of its first interior cell and its
+ * interior extent.  Blocks must tile the domain exactly and neighbours must
+ * share whole faces (a rectilinear block grid). */
+typedef struct {
+    int32_t origin[3];
+    int32_t size[3];
+} wlb_block_desc;
+
+/* Parameters of the update (Sec. 5.1.1).
+ *   tau          shear relaxation time tau_0 (> 1/2)
+ *   magic        TRT parameter Lambda = (tau+ - 1/2)(tau- - 1/2)
+ *   omega_bulk   MRT rate of the trace moment x2+y2+z2
+ *   omega_higher MRT rate of all moments of order >= 3
+ *   force        body force density (Guo forcing); u = (sum c d + F/2)/rho
+ *   closure      WLB_CLOSURE_*: per-cell tau from the non-equilibrium stress
+ *   cs_smag      Smagorinsky constant C_s (closure SMAG, and MLP fallback)
+ *   mlp          host pointer to WLB_MLP_NPARAM floats (closure MLP), copied
+ *   pressure_axis  -1, or the non-periodic axis whose two faces carry the
+ *                density rho_in (low end) / rho_out (high end) through
+ *                anti-bounce-back; other non-periodic faces are half-way
+ *                bounce-back walls
+ *   health_every check mass and max|u| every this many steps (0 = never);
+ *                a failed check makes wlb_lbm_step return WLB_ERR_DIVERGED
+ *   health_umax  limit on max|u| for the health check (<= 0 means 0.3)
+ *   autotune     1: time candidate tile shapes and launch sizes at init and
+ *                keep the fastest; 0: default shapes */
+typedef struct {
+    double tau;
+    double magic;
+    double omega_bulk;
+    double omega_higher;
+    double force[3];
+    int32_t closure;
+    double cs_smag;
+    const float *mlp;
+    int32_t pressure_axis;
+    double rho_in;
+    double rho_out;
+    int32_t health_every;
+    double health_umax;
+    int32_t autotune;
+} wlb_lbm_params;
+
+/* Create a block set.  d[n] describes the blocks, domain[3] the bounding box,
+ * periodic[3] which axes wrap.  stencil = WLB_D3Q19/WLB_D3Q27, storage =
+ * WLB_F64/F32/F16DEV/BF16DEV.  Builds the 26-neighbour table (periodic links
+ * included), the tile list and the exchange work list, and returns in
+ * *arena_bytes the size of the device arena to bind.
+ * Errors: WLB_ERR_ARG for empty/oversized blocks, overlapping blocks, blocks
+ * that do not cover the domain, or neighbours that do not share whole faces. */
+int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3], const int32_t periodic[3],
+                      int32_t stencil, int32_t storage, size_t *arena_bytes, wlb_blocks_t *out);
+
+/* Bind a caller-owned device arena (>= arena_bytes, 256-byte aligned) and the
+ * HIP stream (a hipStream_t; must not be the null stream) on which all work
+ * of this handle runs.  Uploads the descriptor tables.  The arena must stay
+ * allocated until wlb_blocks_destroy. */
+int wlb_blocks_bind(wlb_blocks_t h, void *device_arena, size_t bytes, void *hip_stream);
+
+/* Initialise the populations to the equilibrium of rho[N], u[3][N] (host,
+ * FP64, global order) and the geometry from solid[N] (host, 1 = solid, may be
+ * NULL for no solid cells).  collision = WLB_SRT/TRT/MRT.  Resets the step
+ * counter.  Runs the tile autotuner when p->autotune is set (the state is
+ * re-initialised afterwards).  Synchronises the stream.
+ * Errors: WLB_ERR_ARG (tau <= 1/2, bad pressure axis, MLP without weights),
+ * WLB_ERR_STATE (not bound), WLB_ERR_UNSUPPORTED (MRT with the MLP closure). */
+int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, const double *rho, const double *u,
+                 const uint8_t *solid);
+
+/* Advance nsteps time steps, each one sweep (collide + stream, Eq. 2)
+ * followed by the ghost-layer exchange.  Asynchronous on the bound stream
+ * unless a health check falls in the range (then it synchronises). */
+int wlb_lbm_step(wlb_blocks_t h, int32_t nsteps);
+
+/* One sweep over all blocks without the following exchange (the sweep of
+ * Sec. 4.2 on its own).  Must be followed by wlb_ghost_exchange before the
+ * next sweep; wlb_lbm_step(h, 1) == wlb_lbm_sweep + wlb_ghost_exchange. */
+int wlb_lbm_sweep(wlb_blocks_t h);
+
+/* Exchange the ghost layers that the last sweep requires (after an even sweep
+ * the neighbours' outgoing populations are copied into the ghost layer;
+ * after an odd sweep the populations written into the ghost layer are
+ * copied into the neighbours).  Idempotent; asynchronous. */
+int wlb_ghost_exchange(wlb_blocks_t h);
+
+/* Moments (Eq. 1) of the current state: rho[N] and u[3][N] (host, may be
+ * NULL to skip), u = (sum c d + F/2)/rho; solid cells get rho = 0, u = 0.
+ * totals[8] (may be NULL) = mass, momentum x/y/z (sum rho u), kinetic energy
+ * sum rho|u|^2/2, max|u|, number of fluid cells, steps taken.  Reductions in
+ * FP64 with a fixed order (deterministic).  Synchronises the stream. */
+int wlb_moments_get(wlb_blocks_t h, double *rho, double *u, double totals[8]);
+
+/* Population deviations d_i = f_i - w_i of the current state in natural
+ * layout d[q][N] (FP64, host), and the reverse.  set also re-establishes the
+ * natural layout so the next sweep is even; solid cells are ignored.  Used
+ * for checkpoint / resume (bitwise for every storage type). */
+int wlb_pdfs_get(wlb_blocks_t h, double *d);
+int wlb_pdfs_set(wlb_blocks_t h, const double *d);
+
+/* Information and tuning. */
+typedef struct {
+    int64_t steps;          /* steps taken since init */
+    int32_t parity;         /* 0: natural layout (next sweep even); 1: swapped */
+    int32_t n_blocks;
+    int64_t n_cells;        /* interior cells of all blocks */
+    int64_t n_fluid;        /* fluid cells */
+    int32_t n_tiles;
+    int32_t tile[3];        /* tile shape target in use (x, y, z) */
+    int32_t grid;           /* workgroups per sweep launch (0 = one per tile) */
+    int32_t n_xchg_items;   /* exchange work items per exchange */
+    int64_t xchg_elems;     /* populations copied per exchange */
+    size_t arena_bytes;
+    size_t pop_bytes;       /* bytes of population storage incl. ghosts */
+} wlb_info_t;
+int wlb_info(wlb_blocks_t h, wlb_info_t *out);
+
+/* Use tile shape (tx, ty, tz) (tx*ty*tz <= 256) and `grid` workgroups per
+ * sweep launch (0 = one workgroup per tile) from now on. */
+int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid);
+
+/* Use (1) or bypass (0) the captured HIP graph in wlb_lbm_step. */
+int wlb_set_graph(wlb_blocks_t h, int32_t on);
+
+/* Per-kernel timing: when on, wlb_lbm_step launches eagerly and brackets
+ * every kernel with HIP events on the bound stream; wlb_kernel_times then
+ * returns the summed milliseconds and launch counts of [even sweep, odd
+ * sweep, exchange after even, exchange after odd] since the last reset
+ * (synchronises).  Turning it on resets the sums. */
+int wlb_set_kernel_timing(wlb_blocks_t h, int32_t on);
+int wlb_kernel_times(wlb_blocks_t h, double ms[4], int64_t launches[4]);
+
+/* Release the handle (not the arena). */
+void wlb_blocks_destroy(wlb_blocks_t h);
+
+const char *wlb_last_error(void);
+
+/* Achievable device bandwidth probe: copy `bytes` (multiple of 16) from src
+ * to dst (device pointers) `reps` times on `hip_stream` with the library's
+ * own copy kernel; returns the mean milliseconds per copy in *ms. */
+int wlb_copy_probe(void *dst, const void *src, size_t bytes, int32_t reps, void *hip_stream, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WLB_H */

@@ -1,0 +1,1045 @@
+// runtime.hip -- host runtime and C ABI of libwlb.so.
+//
+// Blocks (paper Sec. 3.1, Sec. 4.1) become descriptors of one device arena
+// that the caller allocates; a time step is a sweep over all blocks followed
+// by a ghost-layer exchange (Sec. 4.2), the exchange between blocks of the
+// same device being a direct copy without buffers (Sec. 3.3).  Host arrays
+// are copied in at set-up and out after many steps (Sec. 4.3).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/wlb.h"
+#include "lattice.hpp"
+#include "wlb_internal.hpp"
+
+using namespace wlb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) return fail(WLB_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Tile-shape candidates of the autotuner; (0,0,0) packs whole rows.
+const int kShapes[][3] = {{0, 0, 0}, {64, 4, 1}, {32, 8, 1}, {32, 4, 2}, {16, 16, 1}, {16, 4, 4},
+                          {128, 2, 1}, {256, 1, 1}, {64, 2, 2}, {8, 8, 4}};
+const int kGrids[] = {0, 1024, 2048, 4096};
+
+struct HostBlock {
+    int org[3], n[3];
+    int nbr[27];  // neighbour block for offset index (ox+1) + 3 (oy+1) + 9 (oz+1); -1 none
+};
+
+}  // namespace
+
+struct wlb_blocks {
+    int q = 19, storage = 0, esize = 8;
+    int dom[3] = {0, 0, 0}, periodic[3] = {0, 0, 0};
+    std::vector<HostBlock> blocks;
+    std::vector<DevBlock> dev;
+    std::vector<TileHost> tiles;
+    std::vector<XItem> pull, push;
+    int64_t ncells = 0, nfluid = 0, xchg_elems = 0;
+    // arena layout (bytes)
+    size_t off_pop = 0, pop_bytes = 0, off_mask = 0, mask_words = 0, off_blocks = 0, off_tiles = 0,
+           tile_cap = 0, off_pull = 0, off_push = 0, off_partials = 0, off_totals = 0, off_stage = 0,
+           stage_bytes = 0, off_mlp = 0, arena_bytes = 0;
+    char *arena = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false, inited = false;
+    int collision = 0;
+    wlb_lbm_params params{};
+    std::vector<float> mlp;
+    SweepArgs args{};
+    int64_t steps = 0;
+    int parity = 0;       // 0 natural layout, 1 swapped (after an even sweep)
+    int pending = 0;      // 0 none, 1 pull due (after even), 2 push due (after odd)
+    int last_sweep = -1;  // parity of the last sweep (-1: none since init / set)
+    int shape[3] = {0, 0, 0};
+    int grid = 0;
+    bool use_graph = true;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool graph_valid = false;
+    // kernel timing
+    bool timing = false;
+    struct Ev {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Ev> ev_pool;
+    size_t ev_used = 0;
+    double ms[4] = {0, 0, 0, 0};
+    int64_t cnt[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int storage_esize(int s) { return s == WLB_F64 ? 8 : (s == WLB_F32 ? 4 : 2); }
+
+void build_tiles(const wlb_blocks *h, int tx, int ty, int tz, std::vector<TileHost> &out)
+{
+    out.clear();
+    for (int b = 0; b < (int)h->blocks.size(); ++b) {
+        const HostBlock &B = h->blocks[b];
+        int ex, ey, ez;
+        if (tx == 0) {
+            ex = std::min(B.n[0], kWG);
+            ey = std::min(B.n[1], std::max(1, kWG / ex));
+            ez = std::min(B.n[2], std::max(1, kWG / (ex * ey)));
+        } else {
+            ex = std::min(tx, B.n[0]);
+            ey = std::min(ty, B.n[1]);
+            ez = std::min(tz, B.n[2]);
+        }
+        for (int z0 = 0; z0 < B.n[2]; z0 += ez)
+            for (int y0 = 0; y0 < B.n[1]; y0 += ey)
+                for (int x0 = 0; x0 < B.n[0]; x0 += ex) {
+                    TileHost t;
+                    t.b = b;
+                    t.x0 = x0;
+                    t.y0 = y0;
+                    t.z0 = z0;
+                    t.ex = std::min(ex, B.n[0] - x0);
+                    t.ey = std::min(ey, B.n[1] - y0);
+                    t.ez = std::min(ez, B.n[2] - z0);
+                    out.push_back(t);
+                }
+    }
+    // longest-processing-time order for the persistent (grid-stride) launch
+    std::stable_sort(out.begin(), out.end(), [](const TileHost &a, const TileHost &b) {
+        return a.ex * a.ey * a.ez > b.ex * b.ey * b.ez;
+    });
+}
+
+size_t count_tiles(const wlb_blocks *h, int tx, int ty, int tz)
+{
+    std::vector<TileHost> t;
+    build_tiles(h, tx, ty, tz, t);
+    return t.size();
+}
+
+int upload_tiles(wlb_blocks *h)
+{
+    std::vector<int4> packed(h->tiles.size());
+    for (size_t k = 0; k < h->tiles.size(); ++k) {
+        const TileHost &t = h->tiles[k];
+        packed[k] = make_int4(t.b, t.x0 | (t.ex << 16), t.y0 | (t.ey << 16), t.z0 | (t.ez << 16));
+    }
+    HIPCHK(hipMemcpyAsync(h->arena + h->off_tiles, packed.data(), packed.size() * sizeof(int4),
+                          hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->args.ntiles = (int)h->tiles.size();
+    return WLB_OK;
+}
+
+int set_tiles(wlb_blocks *h, int tx, int ty, int tz, int grid)
+{
+    std::vector<TileHost> t;
+    build_tiles(h, tx, ty, tz, t);
+    if (t.size() > h->tile_cap) return fail(WLB_ERR_ARG, "tile shape yields %zu tiles > capacity", t.size());
+    h->tiles.swap(t);
+    h->shape[0] = tx;
+    h->shape[1] = ty;
+    h->shape[2] = tz;
+    h->grid = grid;
+    h->graph_valid = false;
+    if (h->bound) return upload_tiles(h);
+    return WLB_OK;
+}
+
+int launch_grid(const wlb_blocks *h)
+{
+    const int n = (int)h->tiles.size();
+    if (h->grid <= 0 || h->grid > n) return n > 0 ? n : 1;
+    return h->grid;
+}
+
+hipError_t sweep_dispatch(const wlb_blocks *h, bool odd)
+{
+    const int g = launch_grid(h);
+    switch (h->storage) {
+    case WLB_F64: return sweep_f64(h->q, h->collision, odd, h->args, g, h->stream);
+    case WLB_F32: return sweep_f32(h->q, h->collision, odd, h->args, g, h->stream);
+    case WLB_F16DEV: return sweep_f16(h->q, h->collision, odd, h->args, g, h->stream);
+    default: return sweep_bf16(h->q, h->collision, odd, h->args, g, h->stream);
+    }
+}
+
+hipError_t exchange_dispatch(const wlb_blocks *h, bool after_odd)
+{
+    const std::vector<XItem> &v = after_odd ? h->push : h->pull;
+    const XItem *items = reinterpret_cast<const XItem *>(h->arena + (after_odd ? h->off_push : h->off_pull));
+    const DevBlock *blocks = reinterpret_cast<const DevBlock *>(h->arena + h->off_blocks);
+    const uint32_t *masks = reinterpret_cast<const uint32_t *>(h->arena + h->off_mask);
+    void *pops = h->arena + h->off_pop;
+    const int n = (int)v.size();
+    switch (h->storage) {
+    case WLB_F64: return exchange_f64(pops, blocks, masks, items, n, h->stream);
+    case WLB_F32: return exchange_f32(pops, blocks, masks, items, n, h->stream);
+    case WLB_F16DEV: return exchange_f16(pops, blocks, masks, items, n, h->stream);
+    default: return exchange_bf16(pops, blocks, masks, items, n, h->stream);
+    }
+}
+
+hipError_t moments_dispatch(const wlb_blocks *h, const MomArgs &m, int grid)
+{
+    switch (h->storage) {
+    case WLB_F64: return moments_f64(h->q, m, grid, h->stream);
+    case WLB_F32: return moments_f32(h->q, m, grid, h->stream);
+    case WLB_F16DEV: return moments_f16(h->q, m, grid, h->stream);
+    default: return moments_bf16(h->q, m, grid, h->stream);
+    }
+}
+
+hipError_t init_dispatch(const wlb_blocks *h, const double *rhou, int z0, int z1, int grid)
+{
+    switch (h->storage) {
+    case WLB_F64: return init_f64(h->q, h->args, rhou, z0, z1, grid, h->stream);
+    case WLB_F32: return init_f32(h->q, h->args, rhou, z0, z1, grid, h->stream);
+    case WLB_F16DEV: return init_f16(h->q, h->args, rhou, z0, z1, grid, h->stream);
+    default: return init_bf16(h->q, h->args, rhou, z0, z1, grid, h->stream);
+    }
+}
+
+hipError_t pdfs_dispatch(const wlb_blocks *h, double *buf, int z0, int z1, bool to_dev, bool swapped, int grid)
+{
+    switch (h->storage) {
+    case WLB_F64: return pdfs_f64(h->q, h->args, buf, z0, z1, to_dev, swapped, grid, h->stream);
+    case WLB_F32: return pdfs_f32(h->q, h->args, buf, z0, z1, to_dev, swapped, grid, h->stream);
+    case WLB_F16DEV: return pdfs_f16(h->q, h->args, buf, z0, z1, to_dev, swapped, grid, h->stream);
+    default: return pdfs_bf16(h->q, h->args, buf, z0, z1, to_dev, swapped, grid, h->stream);
+    }
+}
+
+// Grid for the auxiliary (non-hot) passes.
+int aux_grid(const wlb_blocks *h)
+{
+    const int n = (int)h->tiles.size();
+    return n < 8192 ? (n > 0 ? n : 1) : 8192;
+}
+
+// --- kernel timing -------------------------------------------------------
+int fold_events(wlb_blocks *h)
+{
+    if (h->ev_used == 0) return WLB_OK;
+    HIPCHK(hipEventSynchronize(h->ev_pool[h->ev_used - 1].b));
+    for (size_t k = 0; k < h->ev_used; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev_pool[k].a, h->ev_pool[k].b));
+        h->ms[h->ev_pool[k].kind] += ms;
+        h->cnt[h->ev_pool[k].kind] += 1;
+    }
+    h->ev_used = 0;
+    return WLB_OK;
+}
+
+int timed_begin(wlb_blocks *h, int kind, size_t *slot)
+{
+    if (h->ev_used == h->ev_pool.size()) {
+        if (h->ev_pool.size() >= 4096) {
+            int rc = fold_events(h);
+            if (rc) return rc;
+        } else {
+            wlb_blocks::Ev e;
+            HIPCHK(hipEventCreate(&e.a));
+            HIPCHK(hipEventCreate(&e.b));
+            h->ev_pool.push_back(e);
+        }
+    }
+    *slot = h->ev_used++;
+    h->ev_pool[*slot].kind = kind;
+    HIPCHK(hipEventRecord(h->ev_pool[*slot].a, h->stream));
+    return WLB_OK;
+}
+
+int run_sweep(wlb_blocks *h, bool odd)
+{
+    size_t s = 0;
+    if (h->timing) {
+        int rc = timed_begin(h, odd ? 1 : 0, &s);
+        if (rc) return rc;
+    }
+    HIPCHK(sweep_dispatch(h, odd));
+    if (h->timing) HIPCHK(hipEventRecord(h->ev_pool[s].b, h->stream));
+    return WLB_OK;
+}
+
+int run_exchange(wlb_blocks *h, bool after_odd)
+{
+    size_t s = 0;
+    if (h->timing) {
+        int rc = timed_begin(h, after_odd ? 3 : 2, &s);
+        if (rc) return rc;
+    }
+    HIPCHK(exchange_dispatch(h, after_odd));
+    if (h->timing) HIPCHK(hipEventRecord(h->ev_pool[s].b, h->stream));
+    return WLB_OK;
+}
+
+int one_step(wlb_blocks *h)
+{
+    const bool odd = h->parity == 1;
+    int rc = run_sweep(h, odd);
+    if (rc) return rc;
+    rc = run_exchange(h, odd);
+    if (rc) return rc;
+    h->parity ^= 1;
+    h->pending = 0;
+    h->last_sweep = odd ? 1 : 0;
+    h->steps += 1;
+    return WLB_OK;
+}
+
+void drop_graph(wlb_blocks *h)
+{
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+    h->graph_valid = false;
+}
+
+int capture_graph(wlb_blocks *h)
+{
+    drop_graph(h);
+    HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = sweep_dispatch(h, false);
+    hipError_t e2 = exchange_dispatch(h, false);
+    hipError_t e3 = sweep_dispatch(h, true);
+    hipError_t e4 = exchange_dispatch(h, true);
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(h->stream, &g);
+    if (e1 || e2 || e3 || e4 || ec != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return fail(WLB_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ec != hipSuccess ? ec : hipErrorUnknown));
+    }
+    h->graph = g;
+    HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+    h->graph_valid = true;
+    return WLB_OK;
+}
+
+// Deterministic FP64 totals of the current state into arena totals slot;
+// copies them to `host8` when non-null (synchronises).
+int compute_totals(wlb_blocks *h, double *host8)
+{
+    MomArgs m{};
+    m.s = h->args;
+    m.swapped = h->parity;
+    m.z0 = 0;
+    m.z1 = 0;
+    m.out = nullptr;
+    m.partials = reinterpret_cast<double *>(h->arena + h->off_partials);
+    HIPCHK(moments_dispatch(h, m, aux_grid(h)));
+    double *tot = reinterpret_cast<double *>(h->arena + h->off_totals);
+    HIPCHK(launch_reduce_totals(m.partials, (int)h->tiles.size(), tot, h->stream));
+    if (host8) {
+        HIPCHK(hipMemcpyAsync(host8, tot, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        host8[7] = (double)h->steps;
+    }
+    return WLB_OK;
+}
+
+int health_check(wlb_blocks *h)
+{
+    double t[8];
+    int rc = compute_totals(h, t);
+    if (rc) return rc;
+    const double lim = h->params.health_umax > 0 ? h->params.health_umax : 0.3;
+    if (!std::isfinite(t[0]) || !std::isfinite(t[5]) || t[5] > lim)
+        return fail(WLB_ERR_DIVERGED, "health check failed at step %lld: mass %g, max|u| %g",
+                    (long long)h->steps, t[0], t[5]);
+    return WLB_OK;
+}
+
+int planes_per_chunk(const wlb_blocks *h, size_t bytes_per_cell)
+{
+    const size_t plane = (size_t)h->dom[0] * h->dom[1] * bytes_per_cell;
+    size_t k = h->stage_bytes / plane;
+    if (k < 1) k = 1;
+    if (k > (size_t)h->dom[2]) k = h->dom[2];
+    return (int)k;
+}
+
+int do_init_state(wlb_blocks *h, const double *rho, const double *u)
+{
+    const int64_t plane = (int64_t)h->dom[0] * h->dom[1];
+    const int64_t N = plane * h->dom[2];
+    const int kz = planes_per_chunk(h, 4 * sizeof(double));
+    double *stage = reinterpret_cast<double *>(h->arena + h->off_stage);
+    for (int z0 = 0; z0 < h->dom[2]; z0 += kz) {
+        const int z1 = std::min(h->dom[2], z0 + kz);
+        const int64_t S = (int64_t)(z1 - z0) * plane;
+        HIPCHK(hipMemcpyAsync(stage, rho + z0 * plane, S * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        for (int a = 0; a < 3; ++a)
+            HIPCHK(hipMemcpyAsync(stage + (1 + a) * S, u + a * N + z0 * plane, S * sizeof(double),
+                                  hipMemcpyHostToDevice, h->stream));
+        HIPCHK(init_dispatch(h, stage, z0, z1, aux_grid(h)));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->steps = 0;
+    h->parity = 0;
+    h->pending = 0;
+    h->last_sweep = -1;
+    return WLB_OK;
+}
+
+int time_pairs(wlb_blocks *h, int reps, float *ms_out)
+{
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    // warm-up pair
+    for (int k = 0; k < 2; ++k) {
+        HIPCHK(sweep_dispatch(h, false));
+        HIPCHK(exchange_dispatch(h, false));
+        HIPCHK(sweep_dispatch(h, true));
+        HIPCHK(exchange_dispatch(h, true));
+    }
+    HIPCHK(hipEventRecord(a, h->stream));
+    for (int k = 0; k < reps; ++k) {
+        HIPCHK(sweep_dispatch(h, false));
+        HIPCHK(exchange_dispatch(h, false));
+        HIPCHK(sweep_dispatch(h, true));
+        HIPCHK(exchange_dispatch(h, true));
+    }
+    HIPCHK(hipEventRecord(b, h->stream));
+    HIPCHK(hipEventSynchronize(b));
+    HIPCHK(hipEventElapsedTime(ms_out, a, b));
+    *ms_out /= reps;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return WLB_OK;
+}
+
+int autotune(wlb_blocks *h)
+{
+    float best = 1e30f;
+    int bs[3] = {0, 0, 0}, bg = 0;
+    // repetitions scaled so each candidate runs ~ 2e8 cell updates at most
+    int reps = (int)std::max<int64_t>(2, std::min<int64_t>(10, 200000000 / std::max<int64_t>(1, 2 * h->ncells)));
+    for (const auto &s : kShapes) {
+        if (count_tiles(h, s[0], s[1], s[2]) > h->tile_cap) continue;
+        for (int g : kGrids) {
+            int rc = set_tiles(h, s[0], s[1], s[2], g);
+            if (rc) return rc;
+            if (g > 0 && g >= (int)h->tiles.size()) continue;  // same as one workgroup per tile
+            float ms = 0.f;
+            rc = time_pairs(h, reps, &ms);
+            if (rc) return rc;
+            if (ms < best) {
+                best = ms;
+                bs[0] = s[0];
+                bs[1] = s[1];
+                bs[2] = s[2];
+                bg = g;
+            }
+        }
+    }
+    return set_tiles(h, bs[0], bs[1], bs[2], bg);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *wlb_last_error(void) { return g_err.c_str(); }
+
+int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3], const int32_t periodic[3],
+                      int32_t stencil, int32_t storage, size_t *arena_bytes, wlb_blocks_t *out)
+{
+    if (!d || n <= 0 || !domain || !periodic || !arena_bytes || !out) return fail(WLB_ERR_ARG, "null argument");
+    if (stencil != WLB_D3Q19 && stencil != WLB_D3Q27) return fail(WLB_ERR_ARG, "stencil must be 19 or 27");
+    if (storage < WLB_F64 || storage > WLB_BF16DEV) return fail(WLB_ERR_ARG, "bad storage type");
+    for (int a = 0; a < 3; ++a)
+        if (domain[a] <= 0 || domain[a] > 32767) return fail(WLB_ERR_ARG, "domain extent out of range");
+    wlb_blocks *h = new wlb_blocks();
+    h->q = stencil;
+    h->storage = storage;
+    h->esize = storage_esize(storage);
+    for (int a = 0; a < 3; ++a) {
+        h->dom[a] = domain[a];
+        h->periodic[a] = periodic[a] ? 1 : 0;
+    }
+    // --- validate the block list: inside the domain, no overlap, full cover
+    int64_t vol = 0;
+    h->blocks.resize(n);
+    for (int b = 0; b < n; ++b) {
+        HostBlock &B = h->blocks[b];
+        for (int a = 0; a < 3; ++a) {
+            B.org[a] = d[b].origin[a];
+            B.n[a] = d[b].size[a];
+            if (B.n[a] <= 0 || B.n[a] > 32767 || B.org[a] < 0 || B.org[a] + B.n[a] > domain[a]) {
+                delete h;
+                return fail(WLB_ERR_ARG, "block %d outside the domain or empty", b);
+            }
+        }
+        vol += (int64_t)B.n[0] * B.n[1] * B.n[2];
+    }
+    const int64_t dvol = (int64_t)domain[0] * domain[1] * domain[2];
+    if (vol != dvol) {
+        delete h;
+        return fail(WLB_ERR_ARG, "blocks cover %lld cells, domain has %lld", (long long)vol, (long long)dvol);
+    }
+    for (int b = 0; b < n; ++b)
+        for (int c = b + 1; c < n; ++c) {
+            bool ov = true;
+            for (int a = 0; a < 3; ++a) {
+                const int lo = std::max(h->blocks[b].org[a], h->blocks[c].org[a]);
+                const int hi = std::min(h->blocks[b].org[a] + h->blocks[b].n[a], h->blocks[c].org[a] + h->blocks[c].n[a]);
+                if (lo >= hi) ov = false;
+            }
+            if (ov) {
+                delete h;
+                return fail(WLB_ERR_ARG, "blocks %d and %d overlap", b, c);
+            }
+        }
+    h->ncells = vol;
+    // --- neighbour table
+    auto find_block = [&](const int p[3]) -> int {
+        for (int b = 0; b < n; ++b) {
+            const HostBlock &B = h->blocks[b];
+            if (p[0] >= B.org[0] && p[0] < B.org[0] + B.n[0] && p[1] >= B.org[1] && p[1] < B.org[1] + B.n[1] &&
+                p[2] >= B.org[2] && p[2] < B.org[2] + B.n[2])
+                return b;
+        }
+        return -1;
+    };
+    for (int b = 0; b < n; ++b) {
+        HostBlock &B = h->blocks[b];
+        for (int k = 0; k < 27; ++k) {
+            B.nbr[k] = -1;
+            const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+            if (o[0] == 0 && o[1] == 0 && o[2] == 0) continue;
+            int p[3];
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                p[a] = o[a] < 0 ? B.org[a] - 1 : (o[a] > 0 ? B.org[a] + B.n[a] : B.org[a]);
+                if (p[a] < 0 || p[a] >= domain[a]) {
+                    if (h->periodic[a])
+                        p[a] = (p[a] + domain[a]) % domain[a];
+                    else
+                        ok = false;
+                }
+            }
+            if (!ok) continue;
+            const int nb = find_block(p);
+            if (nb < 0) {
+                delete h;
+                return fail(WLB_ERR_ARG, "no neighbour block for block %d offset (%d,%d,%d)", b, o[0], o[1], o[2]);
+            }
+            const HostBlock &N = h->blocks[nb];
+            for (int a = 0; a < 3; ++a)
+                if (o[a] == 0 && (N.org[a] != B.org[a] || N.n[a] != B.n[a])) {
+                    delete h;
+                    return fail(WLB_ERR_ARG, "blocks %d and %d do not share a whole face", b, nb);
+                }
+            B.nbr[k] = nb;
+        }
+    }
+    // --- arena layout
+    const int align_e = 128 / h->esize;
+    size_t elems = 0;
+    size_t mwords = 0;
+    h->dev.resize(n);
+    for (int b = 0; b < n; ++b) {
+        const HostBlock &B = h->blocks[b];
+        DevBlock &D = h->dev[b];
+        std::memset(&D, 0, sizeof D);
+        D.xoff = align_e;
+        D.pitch = (int32_t)round_up((size_t)align_e + B.n[0] + 1, align_e);
+        const int64_t plane = (int64_t)D.pitch * (B.n[1] + 2);
+        const int64_t slot = (int64_t)round_up((size_t)(plane * (B.n[2] + 2)), align_e);
+        if (slot * h->esize >= (int64_t)1 << 31) {
+            delete h;
+            return fail(WLB_ERR_ARG, "block %d too large: one population slot must stay below 2 GiB", b);
+        }
+        D.plane = (int32_t)plane;
+        D.slot = slot;
+        D.pop = (int64_t)elems;
+        elems += (size_t)slot * stencil;
+        for (int a = 0; a < 3; ++a) {
+            D.n[a] = B.n[a];
+            D.g[a] = B.org[a];
+        }
+        D.mpitch = (int32_t)round_up(B.n[0], 32);
+        D.mplane = D.mpitch * B.n[1];
+        D.mask = (int64_t)mwords;  // provisional; -1 if the block has no solid nearby (set at init)
+        mwords += (size_t)D.mplane * B.n[2];
+    }
+    size_t off = 0;
+    h->off_pop = off;
+    h->pop_bytes = round_up(elems * h->esize, 256);
+    off += h->pop_bytes;
+    h->off_mask = off;
+    h->mask_words = mwords;
+    off += round_up(mwords * 4, 256);
+    h->off_blocks = off;
+    off += round_up(n * sizeof(DevBlock), 256);
+    size_t cap = 0;
+    for (const auto &s : kShapes) cap = std::max(cap, count_tiles(h, s[0], s[1], s[2]));
+    h->tile_cap = cap;
+    h->off_tiles = off;
+    off += round_up(cap * sizeof(int4), 256);
+    // --- exchange work lists
+    for (int b = 0; b < n; ++b) {
+        const HostBlock &A = h->blocks[b];
+        for (int k = 0; k < 27; ++k) {
+            const int nb = A.nbr[k];
+            if (nb < 0) continue;
+            const HostBlock &Bn = h->blocks[nb];
+            const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+            for (int j = 1; j < stencil; ++j) {
+                bool in = true;
+                for (int a = 0; a < 3; ++a)
+                    if (o[a] != 0 && cc(j, a) != o[a]) in = false;
+                if (!in) continue;
+                // Cells of the ghost region on side o for which population j
+                // is used: the cell g - c_j that reads it (after the even
+                // sweep) or writes it (after the odd sweep) must be an
+                // interior cell of A.  Along the shared axes (o_a = 0) this
+                // shrinks the region by one cell on the side c_j points from;
+                // it also makes every interior (cell, slot) of B the target
+                // of exactly one copy after the odd sweep.
+                int ext[3], ghost0[3], inner0[3];
+                for (int a = 0; a < 3; ++a) {
+                    if (o[a] != 0) {
+                        ext[a] = 1;
+                        ghost0[a] = o[a] < 0 ? -1 : A.n[a];
+                        inner0[a] = o[a] < 0 ? Bn.n[a] - 1 : 0;
+                    } else {
+                        const int lo = std::max(0, cc(j, a)), hi = std::min(A.n[a], A.n[a] + cc(j, a));
+                        ext[a] = hi - lo;
+                        ghost0[a] = lo;
+                        inner0[a] = lo;
+                    }
+                }
+                const int cells = ext[0] * ext[1] * ext[2];
+                for (int s0 = 0; s0 < cells; s0 += kWG) {
+                    XItem it;
+                    it.slot = j;
+                    it.ex = ext[0];
+                    it.ey = ext[1];
+                    it.start = s0;
+                    it.count = std::min(kWG, cells - s0);
+                    // after the even sweep: neighbour interior -> own ghost layer
+                    it.sb = nb;
+                    it.db = b;
+                    it.chk = -1;
+                    for (int a = 0; a < 3; ++a) {
+                        it.s0[a] = inner0[a];
+                        it.d0[a] = ghost0[a];
+                    }
+                    h->pull.push_back(it);
+                    // after the odd sweep: own ghost layer -> neighbour interior,
+                    // unless the writer (neighbour cell - c_j) is solid
+                    it.sb = b;
+                    it.db = nb;
+                    it.chk = opp(j);
+                    for (int a = 0; a < 3; ++a) {
+                        it.s0[a] = ghost0[a];
+                        it.d0[a] = inner0[a];
+                    }
+                    h->push.push_back(it);
+                    h->xchg_elems += it.count;
+                }
+            }
+        }
+    }
+    h->off_pull = off;
+    off += round_up(h->pull.size() * sizeof(XItem) + 1, 256);
+    h->off_push = off;
+    off += round_up(h->push.size() * sizeof(XItem) + 1, 256);
+    h->off_partials = off;
+    off += round_up(cap * 8 * sizeof(double), 256);
+    h->off_totals = off;
+    off += 256;
+    h->off_mlp = off;
+    off += round_up(WLB_MLP_NPARAM * sizeof(float), 256);
+    const size_t plane_cells = (size_t)domain[0] * domain[1];
+    size_t stage = (size_t)64 << 20;
+    stage = std::max(stage, (size_t)dvol);                            // solid array
+    stage = std::max(stage, plane_cells * 4 * sizeof(double));        // rho, u of one plane
+    stage = std::max(stage, plane_cells * stencil * sizeof(double));  // populations of one plane
+    h->stage_bytes = round_up(stage, 256);
+    h->off_stage = off;
+    off += h->stage_bytes;
+    h->arena_bytes = off;
+    build_tiles(h, 0, 0, 0, h->tiles);
+    *arena_bytes = off;
+    *out = h;
+    return WLB_OK;
+}
+
+int wlb_blocks_bind(wlb_blocks_t h, void *arena, size_t bytes, void *stream)
+{
+    if (!h || !arena) return fail(WLB_ERR_ARG, "null argument");
+    if (!stream) return fail(WLB_ERR_ARG, "a non-null HIP stream is required");
+    if (bytes < h->arena_bytes) return fail(WLB_ERR_ARG, "arena of %zu bytes < required %zu", bytes, h->arena_bytes);
+    if (((uintptr_t)arena) % 256) return fail(WLB_ERR_ARG, "arena must be 256-byte aligned");
+    h->arena = static_cast<char *>(arena);
+    h->stream = static_cast<hipStream_t>(stream);
+    drop_graph(h);
+    HIPCHK(hipMemsetAsync(h->arena, 0, h->off_blocks, h->stream));  // populations and masks
+    HIPCHK(hipMemcpyAsync(h->arena + h->off_pull, h->pull.data(), h->pull.size() * sizeof(XItem),
+                          hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->arena + h->off_push, h->push.data(), h->push.size() * sizeof(XItem),
+                          hipMemcpyHostToDevice, h->stream));
+    h->bound = true;
+    h->args.arena = h->arena + h->off_pop;
+    h->args.blocks = reinterpret_cast<const DevBlock *>(h->arena + h->off_blocks);
+    h->args.tiles = reinterpret_cast<const int4 *>(h->arena + h->off_tiles);
+    h->args.masks = reinterpret_cast<const uint32_t *>(h->arena + h->off_mask);
+    h->args.mlp = reinterpret_cast<const float *>(h->arena + h->off_mlp);
+    for (int a = 0; a < 3; ++a) h->args.dom[a] = h->dom[a];
+    h->args.periodic = h->periodic[0] | (h->periodic[1] << 1) | (h->periodic[2] << 2);
+    HIPCHK(hipMemcpyAsync(h->arena + h->off_blocks, h->dev.data(), h->dev.size() * sizeof(DevBlock),
+                          hipMemcpyHostToDevice, h->stream));
+    return upload_tiles(h);
+}
+
+int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, const double *rho, const double *u,
+                 const uint8_t *solid)
+{
+    if (!h || !p || !rho || !u) return fail(WLB_ERR_ARG, "null argument");
+    if (!h->bound) return fail(WLB_ERR_STATE, "wlb_blocks_bind must come first");
+    if (collision < WLB_SRT || collision > WLB_MRT) return fail(WLB_ERR_ARG, "bad collision operator");
+    if (!(p->tau > 0.5)) return fail(WLB_ERR_ARG, "tau must exceed 1/2");
+    if (collision == WLB_TRT && !(p->magic > 0.0)) return fail(WLB_ERR_ARG, "TRT needs magic > 0");
+    if (p->pressure_axis < -1 || p->pressure_axis > 2) return fail(WLB_ERR_ARG, "bad pressure axis");
+    if (p->pressure_axis >= 0 && h->periodic[p->pressure_axis])
+        return fail(WLB_ERR_ARG, "the pressure axis must not be periodic");
+    if (p->closure < WLB_CLOSURE_NONE || p->closure > WLB_CLOSURE_MLP) return fail(WLB_ERR_ARG, "bad closure");
+    if (p->closure == WLB_CLOSURE_MLP) return fail(WLB_ERR_UNSUPPORTED, "MLP closure not available in this build");
+    h->collision = collision;
+    h->params = *p;
+    drop_graph(h);
+    SweepArgs &a = h->args;
+    a.pressure_axis = p->pressure_axis;
+    a.closure = p->closure;
+    a.omega = 1.0 / p->tau;
+    a.magic = p->magic;
+    a.omega_minus = collision == WLB_TRT ? 1.0 / (0.5 + p->magic / (p->tau - 0.5)) : a.omega;
+    a.omega_bulk = p->omega_bulk;
+    a.omega_higher = p->omega_higher;
+    for (int k = 0; k < 3; ++k) a.force[k] = p->force[k];
+    a.rho_in = p->rho_in;
+    a.rho_out = p->rho_out;
+    a.tau0 = p->tau;
+    a.smag_k = 18.0 * std::sqrt(2.0) * p->cs_smag * p->cs_smag;
+    // --- geometry: which blocks need masks, then build them on the device
+    const int64_t plane = (int64_t)h->dom[0] * h->dom[1];
+    const int64_t N = plane * h->dom[2];
+    int64_t nsolid = 0;
+    if (solid)
+        for (int64_t k = 0; k < N; ++k) nsolid += solid[k] ? 1 : 0;
+    h->nfluid = N - nsolid;
+    int64_t mwords = 0;
+    for (size_t b = 0; b < h->blocks.size(); ++b) {
+        const HostBlock &B = h->blocks[b];
+        DevBlock &D = h->dev[b];
+        bool need = false;
+        if (solid && nsolid > 0) {
+            for (int z = -1; z <= B.n[2] && !need; ++z)
+                for (int y = -1; y <= B.n[1] && !need; ++y)
+                    for (int x = -1; x <= B.n[0] && !need; ++x) {
+                        int g[3] = {B.org[0] + x, B.org[1] + y, B.org[2] + z};
+                        bool ok = true;
+                        for (int ax = 0; ax < 3; ++ax)
+                            if (g[ax] < 0 || g[ax] >= h->dom[ax]) {
+                                if (h->periodic[ax])
+                                    g[ax] = (g[ax] + h->dom[ax]) % h->dom[ax];
+                                else
+                                    ok = false;
+                            }
+                        if (ok && solid[(g[2] * (int64_t)h->dom[1] + g[1]) * h->dom[0] + g[0]]) need = true;
+                    }
+        }
+        D.mask = need ? mwords : -1;
+        mwords += (int64_t)D.mplane * B.n[2];
+    }
+    HIPCHK(hipMemcpyAsync(h->arena + h->off_blocks, h->dev.data(), h->dev.size() * sizeof(DevBlock),
+                          hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemsetAsync(h->arena + h->off_pop, 0, h->pop_bytes, h->stream));
+    if (solid && nsolid > 0) {
+        if ((size_t)N > h->stage_bytes) return fail(WLB_ERR_ARG, "staging too small for the solid array");
+        HIPCHK(hipMemcpyAsync(h->arena + h->off_stage, solid, N, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(launch_masks(h->args, reinterpret_cast<const uint8_t *>(h->arena + h->off_stage), h->q, aux_grid(h),
+                            h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    int rc = do_init_state(h, rho, u);
+    if (rc) return rc;
+    h->inited = true;
+    if (p->autotune) {
+        rc = autotune(h);
+        if (rc) return rc;
+        rc = do_init_state(h, rho, u);
+        if (rc) return rc;
+    }
+    return WLB_OK;
+}
+
+int wlb_lbm_sweep(wlb_blocks_t h)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    if (h->pending) return fail(WLB_ERR_STATE, "wlb_ghost_exchange is due before the next sweep");
+    const bool odd = h->parity == 1;
+    int rc = run_sweep(h, odd);
+    if (rc) return rc;
+    h->pending = odd ? 2 : 1;
+    h->parity ^= 1;
+    h->last_sweep = odd ? 1 : 0;
+    h->steps += 1;
+    return WLB_OK;
+}
+
+int wlb_ghost_exchange(wlb_blocks_t h)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    // the exchange after the last sweep: pull after an even sweep (layout now
+    // swapped), push after an odd one (layout natural)
+    if (!h->pending && h->last_sweep < 0) return WLB_OK;  // nothing swept since init / set
+    const bool after_odd = h->pending ? (h->pending == 2) : (h->last_sweep == 1);
+    int rc = run_exchange(h, after_odd);
+    if (rc) return rc;
+    h->pending = 0;
+    return WLB_OK;
+}
+
+int wlb_lbm_step(wlb_blocks_t h, int32_t nsteps)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    if (nsteps < 0) return fail(WLB_ERR_ARG, "negative step count");
+    int rc;
+    if (h->pending) {
+        rc = wlb_ghost_exchange(h);
+        if (rc) return rc;
+    }
+    const int he = h->params.health_every;
+    while (nsteps > 0) {
+        const int64_t before = h->steps;
+        if (h->parity == 1 || nsteps < 2 || !h->use_graph || h->timing) {
+            rc = one_step(h);
+            if (rc) return rc;
+            nsteps -= 1;
+        } else {
+            if (!h->graph_valid) {
+                rc = capture_graph(h);
+                if (rc) return rc;
+            }
+            HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+            h->last_sweep = 1;
+            h->steps += 2;
+            nsteps -= 2;
+        }
+        if (he > 0 && (h->steps / he) != (before / he)) {
+            rc = health_check(h);
+            if (rc) return rc;
+        }
+    }
+    return WLB_OK;
+}
+
+int wlb_moments_get(wlb_blocks_t h, double *rho, double *u, double totals[8])
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    if (h->pending) {
+        int rc = wlb_ghost_exchange(h);
+        if (rc) return rc;
+    }
+    if (totals) {
+        int rc = compute_totals(h, totals);
+        if (rc) return rc;
+    }
+    if (rho || u) {
+        const int64_t plane = (int64_t)h->dom[0] * h->dom[1];
+        const int64_t N = plane * h->dom[2];
+        const int kz = planes_per_chunk(h, 4 * sizeof(double));
+        double *stage = reinterpret_cast<double *>(h->arena + h->off_stage);
+        for (int z0 = 0; z0 < h->dom[2]; z0 += kz) {
+            const int z1 = std::min(h->dom[2], z0 + kz);
+            const int64_t S = (int64_t)(z1 - z0) * plane;
+            MomArgs m{};
+            m.s = h->args;
+            m.swapped = h->parity;
+            m.z0 = z0;
+            m.z1 = z1;
+            m.out = stage;
+            m.partials = nullptr;
+            HIPCHK(moments_dispatch(h, m, aux_grid(h)));
+            if (rho) HIPCHK(hipMemcpyAsync(rho + z0 * plane, stage, S * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            if (u)
+                for (int a = 0; a < 3; ++a)
+                    HIPCHK(hipMemcpyAsync(u + a * N + z0 * plane, stage + (1 + a) * S, S * sizeof(double),
+                                          hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
+    }
+    return WLB_OK;
+}
+
+static int pdfs_io(wlb_blocks_t h, double *d, bool to_dev)
+{
+    if (!h || !d) return fail(WLB_ERR_ARG, "null argument");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    if (h->pending) {
+        int rc = wlb_ghost_exchange(h);
+        if (rc) return rc;
+    }
+    const int64_t plane = (int64_t)h->dom[0] * h->dom[1];
+    const int64_t N = plane * h->dom[2];
+    const int kz = planes_per_chunk(h, h->q * sizeof(double));
+    double *stage = reinterpret_cast<double *>(h->arena + h->off_stage);
+    for (int z0 = 0; z0 < h->dom[2]; z0 += kz) {
+        const int z1 = std::min(h->dom[2], z0 + kz);
+        const int64_t S = (int64_t)(z1 - z0) * plane;
+        if (to_dev) {
+            for (int i = 0; i < h->q; ++i)
+                HIPCHK(hipMemcpyAsync(stage + i * S, d + i * N + z0 * plane, S * sizeof(double),
+                                      hipMemcpyHostToDevice, h->stream));
+            HIPCHK(pdfs_dispatch(h, stage, z0, z1, true, false, aux_grid(h)));
+        } else {
+            HIPCHK(pdfs_dispatch(h, stage, z0, z1, false, h->parity == 1, aux_grid(h)));
+            for (int i = 0; i < h->q; ++i)
+                HIPCHK(hipMemcpyAsync(d + i * N + z0 * plane, stage + i * S, S * sizeof(double),
+                                      hipMemcpyDeviceToHost, h->stream));
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    if (to_dev) {
+        h->parity = 0;
+        h->pending = 0;
+        h->last_sweep = -1;
+    }
+    return WLB_OK;
+}
+
+int wlb_pdfs_get(wlb_blocks_t h, double *d) { return pdfs_io(h, d, false); }
+int wlb_pdfs_set(wlb_blocks_t h, const double *d) { return pdfs_io(h, const_cast<double *>(d), true); }
+
+int wlb_info(wlb_blocks_t h, wlb_info_t *o)
+{
+    if (!h || !o) return fail(WLB_ERR_ARG, "null argument");
+    o->steps = h->steps;
+    o->parity = h->parity;
+    o->n_blocks = (int32_t)h->blocks.size();
+    o->n_cells = h->ncells;
+    o->n_fluid = h->inited ? h->nfluid : h->ncells;
+    o->n_tiles = (int32_t)h->tiles.size();
+    for (int a = 0; a < 3; ++a) o->tile[a] = h->shape[a];
+    o->grid = h->grid;
+    o->n_xchg_items = (int32_t)h->pull.size();
+    o->xchg_elems = h->xchg_elems;
+    o->arena_bytes = h->arena_bytes;
+    o->pop_bytes = h->pop_bytes;
+    return WLB_OK;
+}
+
+int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (tx < 0 || ty < 0 || tz < 0 || grid < 0) return fail(WLB_ERR_ARG, "negative tile shape");
+    if (tx != 0 && (ty < 1 || tz < 1 || (int64_t)tx * ty * tz > kWG))
+        return fail(WLB_ERR_ARG, "tile shape must have at most %d cells", kWG);
+    return set_tiles(h, tx, ty, tz, grid);
+}
+
+int wlb_set_graph(wlb_blocks_t h, int32_t on)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    h->use_graph = on != 0;
+    return WLB_OK;
+}
+
+int wlb_set_kernel_timing(wlb_blocks_t h, int32_t on)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (h->timing) {
+        int rc = fold_events(h);
+        if (rc) return rc;
+    }
+    h->timing = on != 0;
+    for (int k = 0; k < 4; ++k) {
+        h->ms[k] = 0.0;
+        h->cnt[k] = 0;
+    }
+    return WLB_OK;
+}
+
+int wlb_kernel_times(wlb_blocks_t h, double ms[4], int64_t launches[4])
+{
+    if (!h || !ms || !launches) return fail(WLB_ERR_ARG, "null argument");
+    int rc = fold_events(h);
+    if (rc) return rc;
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = h->ms[k];
+        launches[k] = h->cnt[k];
+    }
+    return WLB_OK;
+}
+
+void wlb_blocks_destroy(wlb_blocks_t h)
+{
+    if (!h) return;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    for (auto &e : h->ev_pool) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    delete h;
+}
+
+int wlb_copy_probe(void *dst, const void *src, size_t bytes, int32_t reps, void *stream, double *ms)
+{
+    if (!dst || !src || !ms || reps <= 0 || bytes % 16) return fail(WLB_ERR_ARG, "bad copy probe arguments");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(launch_copy(dst, src, bytes, st));
+    HIPCHK(hipEventRecord(a, st));
+    for (int k = 0; k < reps; ++k) HIPCHK(launch_copy(dst, src, bytes, st));
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, a, b));
+    *ms = (double)t / reps;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return WLB_OK;
+}
+
+}  // extern "C"

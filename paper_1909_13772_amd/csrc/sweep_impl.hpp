@@ -1,0 +1,857 @@
+// sweep_impl.hpp -- HIP kernels of the lattice Boltzmann sweep for one
+// storage type (included by sweep_f64.hip, sweep_f32.hip, sweep_f16.hip,
+// sweep_bf16.hip with WLB_STORAGE set).
+//
+// Method (paper Sec. 5.1.1): moments rho = sum f, rho u = sum c f (Eq. 1);
+// update f_i(x + c_i, t + 1) = f_i(x, t) + Omega_i (Eq. 2), collision then
+// streaming; MRT collision Omega = -M^{-1} S (M f - m_eq) (Eq. 3) with SRT /
+// TRT as special relaxation matrices; relaxation time per cell from a
+// closure; bounce-back and pressure (anti-bounce-back) boundaries; Guo body
+// force.  Populations are stored as deviations d_i = f_i - w_i.
+//
+// Streaming uses the in-place AA pattern on one array per block:
+//   even sweep: read slot i of x, collide, write f*_i into slot opp(i) of x
+//               (no neighbour access);
+//   odd sweep : read the incoming f_i from slot opp(i) of x - c_i (the ghost
+//               layer when outside the block), collide, write f*_i into slot
+//               i of x + c_i.
+// Each cell of the odd sweep reads and writes exactly the set
+// {(x + c_j, j)}, so the update is race-free in place.  Bounce-back links
+// (solid neighbour or wall) use the cell's own slots; anti-bounce-back links
+// get their value written by the collision that knows the cell's velocity.
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "lattice.hpp"
+#include "wlb_internal.hpp"
+
+namespace wlb {
+
+// ---------------------------------------------------------------------------
+// Storage codecs: load a deviation as the compute type, store with
+// round-to-nearest-even.  Raw is the bit container used by the exchange.
+// ---------------------------------------------------------------------------
+struct bf16_t {
+    uint16_t v;
+};
+
+template <typename ST> struct Codec;
+
+template <> struct Codec<double> {
+    using T = double;
+    using Raw = uint64_t;
+    static __device__ __forceinline__ double ld(const double *p) { return *p; }
+    static __device__ __forceinline__ void st(double *p, double v) { *p = v; }
+};
+template <> struct Codec<float> {
+    using T = float;
+    using Raw = uint32_t;
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+};
+template <> struct Codec<_Float16> {
+    using T = float;
+    using Raw = uint16_t;
+    static __device__ __forceinline__ float ld(const _Float16 *p) { return (float)*p; }
+    static __device__ __forceinline__ void st(_Float16 *p, float v) { *p = (_Float16)v; }
+};
+template <> struct Codec<bf16_t> {
+    using T = float;
+    using Raw = uint16_t;
+    static __device__ __forceinline__ float ld(const bf16_t *p) { return __uint_as_float((uint32_t)p->v << 16); }
+    static __device__ __forceinline__ void st(bf16_t *p, float v)
+    {
+        uint32_t u = __float_as_uint(v);
+        uint32_t r;
+        if ((u & 0x7f800000u) == 0x7f800000u)
+            r = (u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u);  // inf stays inf, nan stays (quiet) nan
+        else
+            r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
+        p->v = (uint16_t)r;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Collision (deviation form).  In: d[Q] = f - w.  Out: post-collision d[Q],
+// density rho and velocity u (Guo: u = (j + F/2) / rho).
+// ---------------------------------------------------------------------------
+template <int Q, typename T>
+struct Macro {
+    T drho, rho, u[3], uu;
+};
+
+template <int Q, typename T>
+__device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
+{
+    T drho = 0, jx = 0, jy = 0, jz = 0;
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        drho += d[i];
+        if constexpr (cx(i) == 1) jx += d[i];
+        if constexpr (cx(i) == -1) jx -= d[i];
+        if constexpr (cy(i) == 1) jy += d[i];
+        if constexpr (cy(i) == -1) jy -= d[i];
+        if constexpr (cz(i) == 1) jz += d[i];
+        if constexpr (cz(i) == -1) jz -= d[i];
+    });
+    Macro<Q, T> m;
+    m.drho = drho;
+    m.rho = T(1) + drho;
+    const T inv = T(1) / m.rho;
+    m.u[0] = (jx + T(0.5) * F[0]) * inv;
+    m.u[1] = (jy + T(0.5) * F[1]) * inv;
+    m.u[2] = (jz + T(0.5) * F[2]) * inv;
+    m.uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+    return m;
+}
+
+template <int i, typename T>
+__device__ __forceinline__ T cdot(const T v[3])
+{
+    T r = T(0);
+    if constexpr (cx(i) == 1) r += v[0];
+    if constexpr (cx(i) == -1) r -= v[0];
+    if constexpr (cy(i) == 1) r += v[1];
+    if constexpr (cy(i) == -1) r -= v[1];
+    if constexpr (cz(i) == 1) r += v[2];
+    if constexpr (cz(i) == -1) r -= v[2];
+    return r;
+}
+
+// Equilibrium deviation w_i (drho + rho (3 cu + 9/2 cu^2 - 3/2 uu)) and Guo
+// term w_i (3 (c - u).F + 9 (c.u)(c.F)).
+template <int Q, typename T>
+__device__ __forceinline__ void eq_and_force(const Macro<Q, T> &m, const T F[3], T (&de)[Q], T (&Fi)[Q])
+{
+    const T uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr T w = weight<Q, T>(i);
+        const T cu = cdot<i>(m.u);
+        const T cF = cdot<i>(F);
+        de[i] = w * (m.drho + m.rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * m.uu));
+        Fi[i] = w * (T(3) * (cF - uF) + T(9) * cu * cF);
+    });
+}
+
+// Non-equilibrium stress Pi_ab = sum c_a c_b (d - deq): xx, yy, zz, xy, xz, yz.
+template <int Q, typename T>
+__device__ __forceinline__ void pi_neq(const T (&d)[Q], const T (&de)[Q], T P[6])
+{
+    for (int k = 0; k < 6; ++k) P[k] = T(0);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const T n = d[i] - de[i];
+        if constexpr (cx(i) != 0) P[0] += n;
+        if constexpr (cy(i) != 0) P[1] += n;
+        if constexpr (cz(i) != 0) P[2] += n;
+        if constexpr (cx(i) * cy(i) == 1) P[3] += n;
+        if constexpr (cx(i) * cy(i) == -1) P[3] -= n;
+        if constexpr (cx(i) * cz(i) == 1) P[4] += n;
+        if constexpr (cx(i) * cz(i) == -1) P[4] -= n;
+        if constexpr (cy(i) * cz(i) == 1) P[5] += n;
+        if constexpr (cy(i) * cz(i) == -1) P[5] -= n;
+    });
+}
+
+// Smagorinsky relaxation time: tau = (tau0 + sqrt(tau0^2 + k sqrt(Pi:Pi) / rho)) / 2,
+// k = 18 sqrt(2) C_s^2 (from nu_t = C_s^2 |S| and Pi = -2 rho c_s^2 tau S).
+template <typename T>
+__device__ __forceinline__ T tau_smagorinsky(const T P[6], T rho, T tau0, T k)
+{
+    const T Q = P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + T(2) * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
+    return T(0.5) * (tau0 + sqrt(tau0 * tau0 + k * sqrt(Q) / rho));
+}
+
+// Raw-moment transform along one axis of a 3x3x3 array v[z][y][x] (index
+// 9 z + 3 y + x, velocity component c = index - 1): replaces (v(-1), v(0),
+// v(+1)) by the moments of order 0, 1, 2.
+template <int AX, typename T>
+__device__ __forceinline__ void tmoments(T (&v)[27])
+{
+    constexpr int s = AX == 0 ? 1 : (AX == 1 ? 3 : 9);
+    sfor<9>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        constexpr int a = l % 3, b = l / 3;
+        constexpr int base = AX == 0 ? (3 * a + 9 * b) : (AX == 1 ? (a + 9 * b) : (a + 3 * b));
+        const T m = v[base], z = v[base + s], p = v[base + 2 * s];
+        v[base] = m + z + p;
+        v[base + s] = p - m;
+        v[base + 2 * s] = p + m;
+    });
+}
+// Inverse of tmoments along one axis.
+template <int AX, typename T>
+__device__ __forceinline__ void tvalues(T (&v)[27])
+{
+    constexpr int s = AX == 0 ? 1 : (AX == 1 ? 3 : 9);
+    sfor<9>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        constexpr int a = l % 3, b = l / 3;
+        constexpr int base = AX == 0 ? (3 * a + 9 * b) : (AX == 1 ? (a + 9 * b) : (a + 3 * b));
+        const T m0 = v[base], m1 = v[base + s], m2 = v[base + 2 * s];
+        v[base] = T(0.5) * (m2 - m1);
+        v[base + s] = m0 - m2;
+        v[base + 2 * s] = T(0.5) * (m2 + m1);
+    });
+}
+__host__ __device__ constexpr int tpos(int i) { return 9 * (cz(i) + 1) + 3 * (cy(i) + 1) + (cx(i) + 1); }
+
+// MRT in the raw-moment basis sum c_x^a c_y^b c_z^c (a, b, c <= 2) through
+// the tensor-product transform; the three diagonal second-order moments are
+// relaxed as x2-y2, x2-z2 (rate omega) and x2+y2+z2 (omega_bulk), xy/xz/yz
+// with omega, order >= 3 with omega_higher, conserved moments with 0.  The
+// Guo source enters as M^{-1} (I - S/2) M F.  D3Q19 uses the same transform
+// with the eight corner populations held at zero: D3Q19 distributions are
+// exactly those whose moments with a factor xyz vanish, a subspace that the
+// relaxation maps into itself.
+template <int Q, typename T>
+__device__ __forceinline__ void mrt_relax(T (&d)[Q], const T (&de)[Q], const T (&Fi)[Q], T om, T omb, T omh,
+                                          T *Pout /* 6 or nullptr */)
+{
+    T mn[27], mf[27];
+    for (int k = 0; k < 27; ++k) {
+        mn[k] = T(0);
+        mf[k] = T(0);
+    }
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        mn[tpos(i)] = d[i] - de[i];
+        mf[tpos(i)] = Fi[i];
+    });
+    tmoments<0>(mn);
+    tmoments<1>(mn);
+    tmoments<2>(mn);
+    tmoments<0>(mf);
+    tmoments<1>(mf);
+    tmoments<2>(mf);
+    // after the transform, index 9 c + 3 b + a holds the moment of order (a, b, c)
+    constexpr int XX = 2, YY = 6, ZZ = 18, XY = 4, XZ = 10, YZ = 12;
+    if (Pout) {
+        Pout[0] = mn[XX];
+        Pout[1] = mn[YY];
+        Pout[2] = mn[ZZ];
+        Pout[3] = mn[XY];
+        Pout[4] = mn[XZ];
+        Pout[5] = mn[YZ];
+    }
+    T g[27];
+    sfor<27>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        constexpr int a = k % 3, b = (k / 3) % 3, c = k / 9;
+        constexpr int ord = a + b + c;
+        if constexpr (ord <= 1) {
+            g[k] = -mf[k];
+        } else if constexpr (ord == 2 && (a == 2 || b == 2 || c == 2)) {
+            g[k] = T(0);  // diagonal: below
+        } else if constexpr (ord == 2) {
+            g[k] = om * mn[k] - (T(1) - T(0.5) * om) * mf[k];
+        } else {
+            g[k] = omh * mn[k] - (T(1) - T(0.5) * omh) * mf[k];
+        }
+    });
+    {
+        const T An = mn[XX] - mn[YY], Bn = mn[XX] - mn[ZZ], Tn = mn[XX] + mn[YY] + mn[ZZ];
+        const T Af = mf[XX] - mf[YY], Bf = mf[XX] - mf[ZZ], Tf = mf[XX] + mf[YY] + mf[ZZ];
+        const T gA = om * An - (T(1) - T(0.5) * om) * Af;
+        const T gB = om * Bn - (T(1) - T(0.5) * om) * Bf;
+        const T gT = omb * Tn - (T(1) - T(0.5) * omb) * Tf;
+        const T third = T(1) / T(3);
+        g[XX] = (gA + gB + gT) * third;
+        g[YY] = (gT - T(2) * gA + gB) * third;
+        g[ZZ] = (gT + gA - T(2) * gB) * third;
+    }
+    tvalues<2>(g);
+    tvalues<1>(g);
+    tvalues<0>(g);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        d[i] -= g[tpos(i)];
+    });
+}
+
+template <typename T>
+struct CollParams {
+    T om, omm, magic, omb, omh, F[3], tau0, smag_k;
+    int closure;
+};
+
+template <typename T>
+__device__ __forceinline__ CollParams<T> coll_params(const SweepArgs &a)
+{
+    CollParams<T> c;
+    c.om = (T)a.omega;
+    c.omm = (T)a.omega_minus;
+    c.magic = (T)a.magic;
+    c.omb = (T)a.omega_bulk;
+    c.omh = (T)a.omega_higher;
+    c.F[0] = (T)a.force[0];
+    c.F[1] = (T)a.force[1];
+    c.F[2] = (T)a.force[2];
+    c.tau0 = (T)a.tau0;
+    c.smag_k = (T)a.smag_k;
+    c.closure = a.closure;
+    return c;
+}
+
+// Collide one cell in place.  Returns the macroscopic state used.
+// SRT / TRT are evaluated pair by pair (i, opp(i)) on the symmetric and
+// antisymmetric parts:
+//   e+ = w (drho - 3/2 rho uu + 9/2 rho cu^2),  e- = 3 w rho cu,
+//   F+ = w (9 cu cF - 3 u.F),                   F- = 3 w cF,
+//   d_i += r+ + r-, d_opp += r+ - r-,  r+- = -omega+- (d+- - e+-) + (1 - omega+-/2) F+-,
+// which keeps only the populations live (no equilibrium arrays).
+template <int Q, int COLL, typename T>
+__device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p)
+{
+    const Macro<Q, T> m = moments_of<Q, T>(d, p.F);
+    T om = p.om, omm = p.omm;
+    if constexpr (COLL == 2) {
+        T de[Q], Fi[Q];
+        eq_and_force<Q, T>(m, p.F, de, Fi);
+        if (p.closure == 1) {
+            T P[6];
+            pi_neq<Q, T>(d, de, P);
+            om = T(1) / tau_smagorinsky<T>(P, m.rho, p.tau0, p.smag_k);
+        }
+        mrt_relax<Q, T>(d, de, Fi, om, p.omb, p.omh, nullptr);
+    } else {
+        const T A = m.drho - T(1.5) * m.rho * m.uu;
+        const T uF = m.u[0] * p.F[0] + m.u[1] * p.F[1] + m.u[2] * p.F[2];
+        if (p.closure == 1) {
+            // Pi_neq from the symmetric parts: sum over pairs of c c (d_i + d_opp - 2 e+)
+            T P[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+            sfor<(Q - 1) / 2>([&](auto K) {
+                constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
+                constexpr T w = weight<Q, T>(i);
+                const T cu = cdot<i>(m.u);
+                const T n = d[i] + d[o] - T(2) * w * (A + T(4.5) * m.rho * cu * cu);
+                if constexpr (cx(i) != 0) P[0] += n;
+                if constexpr (cy(i) != 0) P[1] += n;
+                if constexpr (cz(i) != 0) P[2] += n;
+                if constexpr (cx(i) * cy(i) == 1) P[3] += n;
+                if constexpr (cx(i) * cy(i) == -1) P[3] -= n;
+                if constexpr (cx(i) * cz(i) == 1) P[4] += n;
+                if constexpr (cx(i) * cz(i) == -1) P[4] -= n;
+                if constexpr (cy(i) * cz(i) == 1) P[5] += n;
+                if constexpr (cy(i) * cz(i) == -1) P[5] -= n;
+            });
+            const T tau = tau_smagorinsky<T>(P, m.rho, p.tau0, p.smag_k);
+            om = T(1) / tau;
+            omm = T(1) / (T(0.5) + p.magic / (tau - T(0.5)));
+        }
+        if constexpr (COLL == 0) omm = om;
+        const T fop = T(1) - T(0.5) * om, fom = T(1) - T(0.5) * omm;
+        {
+            constexpr T w0 = weight<Q, T>(0);
+            d[0] += -om * (d[0] - w0 * A) + fop * (w0 * (T(-3) * uF));
+        }
+        sfor<(Q - 1) / 2>([&](auto K) {
+            constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
+            constexpr T w = weight<Q, T>(i);
+            const T cu = cdot<i>(m.u);
+            const T cF = cdot<i>(p.F);
+            const T ep = w * (A + T(4.5) * m.rho * cu * cu);
+            const T em = T(3) * w * m.rho * cu;
+            const T fp = w * (T(9) * cu * cF - T(3) * uF);
+            const T fm = T(3) * w * cF;
+            const T dp = T(0.5) * (d[i] + d[o]), dm = T(0.5) * (d[i] - d[o]);
+            const T rp = -om * (dp - ep) + fop * fp;
+            const T rm = -omm * (dm - em) + fom * fm;
+            d[i] += rp + rm;
+            d[o] += rp - rm;
+        });
+    }
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Cell addressing and boundary classification
+// ---------------------------------------------------------------------------
+struct CellPos {
+    int x, y, z;
+    bool valid;
+};
+
+__device__ __forceinline__ CellPos tile_cell(const int4 tv, int l)
+{
+    const int ex = tv.y >> 16, ey = tv.z >> 16, ez = tv.w >> 16;
+    CellPos c;
+    c.valid = l < ex * ey * ez;
+    const int lx = l % ex, r = l / ex;
+    c.x = (tv.y & 0xffff) + lx;
+    c.y = (tv.z & 0xffff) + r % ey;
+    c.z = (tv.w & 0xffff) + r / ey;
+    return c;
+}
+
+// Link classes of a fluid cell: bb = bounce-back links (solid neighbour or a
+// wall face), alo / ahi = anti-bounce-back links through the low / high face
+// of the pressure axis.  Walls take precedence over pressure faces.
+template <int Q>
+struct Links {
+    uint32_t bb, alo, ahi;
+};
+
+template <int Q>
+__device__ __forceinline__ Links<Q> classify(uint32_t mask, const DevBlock &B, int x, int y, int z,
+                                             const SweepArgs &a)
+{
+    Links<Q> L;
+    L.bb = mask & ((1u << Q) - 1u);
+    L.alo = 0;
+    L.ahi = 0;
+    const int p[3] = {B.g[0] + x, B.g[1] + y, B.g[2] + z};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if ((a.periodic >> ax) & 1) continue;
+        const uint32_t lo = (p[ax] == 0) ? (ax == 0 ? face_links<Q>(0, -1) : ax == 1 ? face_links<Q>(1, -1)
+                                                                                     : face_links<Q>(2, -1))
+                                         : 0u;
+        const uint32_t hi = (p[ax] == a.dom[ax] - 1) ? (ax == 0 ? face_links<Q>(0, 1) : ax == 1 ? face_links<Q>(1, 1)
+                                                                                                : face_links<Q>(2, 1))
+                                                     : 0u;
+        if (ax == a.pressure_axis) {
+            L.alo |= lo;
+            L.ahi |= hi;
+        } else {
+            L.bb |= lo | hi;
+        }
+    }
+    L.alo &= ~L.bb;
+    L.ahi &= ~L.bb;
+    return L;
+}
+
+// Anti-bounce-back value for the population entering the cell against
+// direction i: -f*_i + 2 w_i rho_w (1 + 9/2 (c_i.u)^2 - 3/2 u.u), as deviation.
+template <int Q, int i, typename T>
+__device__ __forceinline__ T abb_value(T post_i, const Macro<Q, T> &m, T rho_w)
+{
+    constexpr T w = weight<Q, T>(i);
+    const T cu = cdot<i>(m.u);
+    return -post_i + T(2) * w * (rho_w * (T(1) + T(4.5) * cu * cu - T(1.5) * m.uu) - T(1));
+}
+
+// Addressing: every access is (uniform 64-bit slot base) + (32-bit byte
+// offset) so loads and stores use the scalar-base / vector-offset form and a
+// cell's accesses share one offset register.  The runtime guarantees that a
+// slot spans less than 2^31 bytes.
+template <typename ST>
+__device__ __forceinline__ const char *slot_base(const SweepArgs &a, const DevBlock &B, int i)
+{
+    return reinterpret_cast<const char *>(a.arena) + (B.pop + (int64_t)i * B.slot) * (int64_t)sizeof(ST);
+}
+
+template <typename ST>
+__device__ __forceinline__ ST *at(const char *base, uint32_t byte_off)
+{
+    return reinterpret_cast<ST *>(const_cast<char *>(base) + (uint64_t)byte_off);
+}
+
+__device__ __forceinline__ uint32_t cell_off(const DevBlock &B, int x, int y, int z)
+{
+    return (uint32_t)((z + 1) * B.plane + (y + 1) * B.pitch + B.xoff + x);
+}
+
+template <int i>
+__device__ __forceinline__ int link_delta(const DevBlock &B)
+{
+    return cx(i) + cy(i) * B.pitch + cz(i) * B.plane;
+}
+
+// Odd-sweep access of link i as one uniform base plus a per-lane choice of
+// two uniform addends (regular link / bounce-back or anti-bounce-back link).
+// Incoming: regular = slot opp(i) of x - c_i, special = slot i of x.
+// Outgoing: regular = slot i of x + c_i, special = slot opp(i) of x.
+// Slots i and opp(i) are adjacent, so the lower address is known at compile
+// time and both addends are non-negative.
+template <typename ST>
+struct Alt {
+    const char *base;
+    uint32_t add_reg, add_sp;
+};
+
+// regular access: slot sr shifted by dr elements; special access: slot ss.
+template <typename ST>
+__device__ __forceinline__ Alt<ST> pick_alt(const SweepArgs &a, const DevBlock &B, int sr, int dr, int ss)
+{
+    const int64_t er = (B.pop + (int64_t)sr * B.slot + dr) * (int64_t)sizeof(ST);
+    const int64_t es = (B.pop + (int64_t)ss * B.slot) * (int64_t)sizeof(ST);
+    Alt<ST> p;
+    if (sr < ss) {  // regular access is lower (slots differ by one, |dr| < slot)
+        p.base = reinterpret_cast<const char *>(a.arena) + er;
+        p.add_reg = 0;
+        p.add_sp = (uint32_t)(es - er);
+    } else {
+        p.base = reinterpret_cast<const char *>(a.arena) + es;
+        p.add_reg = (uint32_t)(er - es);
+        p.add_sp = 0;
+    }
+    return p;
+}
+
+template <typename ST, int i>
+__device__ __forceinline__ Alt<ST> alt_in(const SweepArgs &a, const DevBlock &B)
+{
+    return pick_alt<ST>(a, B, opp(i), -link_delta<i>(B), i);
+}
+template <typename ST, int i>
+__device__ __forceinline__ Alt<ST> alt_out(const SweepArgs &a, const DevBlock &B)
+{
+    return pick_alt<ST>(a, B, i, link_delta<i>(B), opp(i));
+}
+
+// Gather the populations f_i(x) of a fluid cell for the current layout:
+// natural (after an odd sweep / init) reads slot i of x; swapped (after an
+// even sweep) reads slot opp(i) of x - c_i, or slot i of x on bounce-back /
+// anti-bounce-back links.
+template <int Q, typename ST, bool SWAPPED>
+__device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, uint32_t off, uint32_t special,
+                                       typename Codec<ST>::T (&f)[Q])
+{
+    const uint32_t boff = off * (uint32_t)sizeof(ST);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (!SWAPPED) {
+            f[i] = Codec<ST>::ld(at<ST>(slot_base<ST>(a, B, i), boff));
+        } else {
+            const Alt<ST> p = alt_in<ST, i>(a, B);
+            f[i] = Codec<ST>::ld(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// The sweep kernel (one launch covers every tile of every block)
+// ---------------------------------------------------------------------------
+template <int Q, int COLL, typename ST, bool ODD>
+__global__ __launch_bounds__(kWG) void sweep_kernel(const SweepArgs a)
+{
+    using T = typename Codec<ST>::T;
+    const CollParams<T> cp = coll_params<T>(a);
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int4 tv = a.tiles[t];
+        const CellPos c = tile_cell(tv, threadIdx.x);
+        if (!c.valid) continue;
+        const DevBlock B = a.blocks[tv.x];
+        uint32_t mask = 0;
+        if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
+        if (mask & kSolidBit) continue;
+        const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
+        const uint32_t boff = cell_off(B, c.x, c.y, c.z) * (uint32_t)sizeof(ST);
+        const uint32_t special = L.bb | L.alo | L.ahi;
+        T f[Q];
+        if constexpr (!ODD) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                f[i] = Codec<ST>::ld(at<ST>(slot_base<ST>(a, B, i), boff));
+            });
+        } else {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const Alt<ST> p = alt_in<ST, i>(a, B);
+                f[i] = Codec<ST>::ld(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+            });
+        }
+        const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
+        if (L.alo | L.ahi) {
+            const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
+                if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
+            });
+        }
+        if constexpr (!ODD) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                Codec<ST>::st(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
+            });
+        } else {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const Alt<ST> p = alt_out<ST, i>(a, B);
+                Codec<ST>::st(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
+            });
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Moments and conservation partials (FP64), optional per-cell output
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int Q, typename ST, bool SWAPPED>
+__global__ __launch_bounds__(kWG) void moments_kernel(const MomArgs ma)
+{
+    const SweepArgs &a = ma.s;
+    __shared__ double red[kWG / 64][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int4 tv = a.tiles[t];
+        const CellPos c = tile_cell(tv, threadIdx.x);
+        const DevBlock B = a.blocks[tv.x];
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // drho, px, py, pz, ke, umax, nfluid, -
+        if (c.valid) {
+            uint32_t mask = 0;
+            if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
+            const int gx = B.g[0] + c.x, gy = B.g[1] + c.y, gz = B.g[2] + c.z;
+            double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
+            if (!(mask & kSolidBit)) {
+                const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
+                const uint32_t off = cell_off(B, c.x, c.y, c.z);
+                typename Codec<ST>::T f[Q];
+                gather<Q, ST, SWAPPED>(a, B, off, L.bb | L.alo | L.ahi, f);
+                double drho = 0, j[3] = {0, 0, 0};
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const double v = (double)f[i];
+                    drho += v;
+                    if constexpr (cx(i) != 0) j[0] += cx(i) * v;
+                    if constexpr (cy(i) != 0) j[1] += cy(i) * v;
+                    if constexpr (cz(i) != 0) j[2] += cz(i) * v;
+                });
+                rho = 1.0 + drho;
+                double pu[3];
+                for (int k = 0; k < 3; ++k) {
+                    pu[k] = j[k] + 0.5 * a.force[k];
+                    u[k] = pu[k] / rho;
+                }
+                const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                acc[0] = drho;
+                acc[1] = pu[0];
+                acc[2] = pu[1];
+                acc[3] = pu[2];
+                acc[4] = 0.5 * rho * uu;
+                acc[5] = sqrt(uu);
+                acc[6] = 1.0;
+            }
+            if (ma.out && gz >= ma.z0 && gz < ma.z1) {
+                const int64_t S = (int64_t)(ma.z1 - ma.z0) * a.dom[1] * a.dom[0];
+                const int64_t k = ((int64_t)(gz - ma.z0) * a.dom[1] + gy) * a.dom[0] + gx;
+                ma.out[k] = rho;
+                ma.out[S + k] = u[0];
+                ma.out[2 * S + k] = u[1];
+                ma.out[3 * S + k] = u[2];
+            }
+        }
+        if (ma.partials) {
+            for (int k = 0; k < 7; ++k) acc[k] = (k == 5) ? wave_max(acc[k]) : wave_sum(acc[k]);
+            if (lane == 0)
+                for (int k = 0; k < 7; ++k) red[wv][k] = acc[k];
+            __syncthreads();
+            if (threadIdx.x < 8) {
+                double r = 0.0;
+                const int k = threadIdx.x;
+                for (int w = 0; w < kWG / 64; ++w) {
+                    const double v = (k < 7) ? red[w][k] : 0.0;
+                    r = (k == 5) ? fmax(r, v) : r + v;
+                }
+                ma.partials[(int64_t)t * 8 + k] = r;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: d = f_eq(rho, u) - w from rho/u of a global z slab
+// ---------------------------------------------------------------------------
+template <int Q, typename ST>
+__global__ __launch_bounds__(kWG) void init_kernel(const SweepArgs a, const double *rhou, int z0, int z1)
+{
+    using T = typename Codec<ST>::T;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int4 tv = a.tiles[t];
+        const CellPos c = tile_cell(tv, threadIdx.x);
+        if (!c.valid) continue;
+        const DevBlock B = a.blocks[tv.x];
+        const int gx = B.g[0] + c.x, gy = B.g[1] + c.y, gz = B.g[2] + c.z;
+        if (gz < z0 || gz >= z1) continue;
+        uint32_t mask = 0;
+        if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
+        const uint32_t off = cell_off(B, c.x, c.y, c.z);
+        if (mask & kSolidBit) {
+            sfor<Q>([&](auto I) { Codec<ST>::st(at<ST>(slot_base<ST>(a, B, decltype(I)::value), off * sizeof(ST)), T(0)); });
+            continue;
+        }
+        const int64_t S = (int64_t)(z1 - z0) * a.dom[1] * a.dom[0];
+        const int64_t k = ((int64_t)(gz - z0) * a.dom[1] + gy) * a.dom[0] + gx;
+        // equilibrium evaluated in FP64, then rounded once to the storage type
+        const double rho = rhou[k];
+        const double u[3] = {rhou[S + k], rhou[2 * S + k], rhou[3 * S + k]};
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double cu = cdot<i>(u);
+            const double v = weight<Q, double>(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+            Codec<ST>::st(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)v);
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Population I/O (natural layout, FP64 [q][slab cells]) for get / set
+// ---------------------------------------------------------------------------
+template <int Q, typename ST, bool TO_DEVICE, bool SWAPPED>
+__global__ __launch_bounds__(kWG) void pdfs_kernel(const SweepArgs a, double *buf, int z0, int z1)
+{
+    using T = typename Codec<ST>::T;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int4 tv = a.tiles[t];
+        const CellPos c = tile_cell(tv, threadIdx.x);
+        if (!c.valid) continue;
+        const DevBlock B = a.blocks[tv.x];
+        const int gx = B.g[0] + c.x, gy = B.g[1] + c.y, gz = B.g[2] + c.z;
+        if (gz < z0 || gz >= z1) continue;
+        uint32_t mask = 0;
+        if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
+        const int64_t S = (int64_t)(z1 - z0) * a.dom[1] * a.dom[0];
+        const int64_t k = ((int64_t)(gz - z0) * a.dom[1] + gy) * a.dom[0] + gx;
+        const uint32_t off = cell_off(B, c.x, c.y, c.z);
+        if (mask & kSolidBit) {
+            if (!TO_DEVICE)
+                for (int i = 0; i < Q; ++i) buf[i * S + k] = 0.0;
+            continue;
+        }
+        if constexpr (TO_DEVICE) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                Codec<ST>::st(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)buf[i * S + k]);
+            });
+        } else {
+            const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
+            T f[Q];
+            gather<Q, ST, SWAPPED>(a, B, off, L.bb | L.alo | L.ahi, f);
+            for (int i = 0; i < Q; ++i) buf[i * S + k] = (double)f[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ghost-layer exchange: bitwise copy of one population over a cell region
+// between two blocks (device-local copy without buffers, Sec. 3.3).
+// ---------------------------------------------------------------------------
+template <typename Raw>
+__global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBlock *blocks, const uint32_t *masks,
+                                                       const XItem *items)
+{
+    const XItem &it = items[blockIdx.x];
+    const int l = threadIdx.x;
+    if (l >= it.count) return;
+    const int r = it.start + l;
+    const int rx = r % it.ex, rq = r / it.ex;
+    const int ry = rq % it.ey, rz = rq / it.ey;
+    const DevBlock &S = blocks[it.sb];
+    const DevBlock &D = blocks[it.db];
+    const int dx = it.d0[0] + rx, dy = it.d0[1] + ry, dz = it.d0[2] + rz;
+    if (it.chk >= 0 && D.mask >= 0) {
+        const uint32_t m = masks[D.mask + (int64_t)dz * D.mplane + dy * D.mpitch + dx];
+        if (m & (kSolidBit | (1u << it.chk))) return;
+    }
+    const Raw *src = arena + S.pop + (int64_t)it.slot * S.slot + cell_off(S, it.s0[0] + rx, it.s0[1] + ry, it.s0[2] + rz);
+    Raw *dst = arena + D.pop + (int64_t)it.slot * D.slot + cell_off(D, dx, dy, dz);
+    *dst = *src;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int Q, int COLL>
+static hipError_t sweep_q(bool odd, const SweepArgs &a, int grid, hipStream_t st)
+{
+    if (odd)
+        hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, true>), dim3(grid), dim3(kWG), 0, st, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, false>), dim3(grid), dim3(kWG), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int Q>
+static hipError_t sweep_c(int coll, bool odd, const SweepArgs &a, int grid, hipStream_t st)
+{
+    switch (coll) {
+    case 0: return sweep_q<Q, 0>(odd, a, grid, st);
+    case 1: return sweep_q<Q, 1>(odd, a, grid, st);
+    case 2: return sweep_q<Q, 2>(odd, a, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int Q>
+static hipError_t moments_q(const MomArgs &a, int grid, hipStream_t st)
+{
+    if (a.swapped)
+        hipLaunchKernelGGL((moments_kernel<Q, WLB_STORAGE, true>), dim3(grid), dim3(kWG), 0, st, a);
+    else
+        hipLaunchKernelGGL((moments_kernel<Q, WLB_STORAGE, false>), dim3(grid), dim3(kWG), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int Q>
+static hipError_t pdfs_q(const SweepArgs &a, double *buf, int z0, int z1, bool to_dev, bool swapped, int grid,
+                         hipStream_t st)
+{
+    if (to_dev)
+        hipLaunchKernelGGL((pdfs_kernel<Q, WLB_STORAGE, true, false>), dim3(grid), dim3(kWG), 0, st, a, buf, z0, z1);
+    else if (swapped)
+        hipLaunchKernelGGL((pdfs_kernel<Q, WLB_STORAGE, false, true>), dim3(grid), dim3(kWG), 0, st, a, buf, z0, z1);
+    else
+        hipLaunchKernelGGL((pdfs_kernel<Q, WLB_STORAGE, false, false>), dim3(grid), dim3(kWG), 0, st, a, buf, z0, z1);
+    return hipGetLastError();
+}
+
+
+#define WLB_CAT2(a, b) a##b
+#define WLB_CAT(a, b) WLB_CAT2(a, b)
+
+hipError_t WLB_CAT(sweep_, WLB_SUFFIX)(int q, int coll, bool odd, const SweepArgs &a, int grid, hipStream_t st)
+{
+    return q == 19 ? sweep_c<19>(coll, odd, a, grid, st) : sweep_c<27>(coll, odd, a, grid, st);
+}
+
+hipError_t WLB_CAT(moments_, WLB_SUFFIX)(int q, const MomArgs &a, int grid, hipStream_t st)
+{
+    return q == 19 ? moments_q<19>(a, grid, st) : moments_q<27>(a, grid, st);
+}
+
+hipError_t WLB_CAT(init_, WLB_SUFFIX)(int q, const SweepArgs &a, const double *rhou, int z0, int z1, int grid,
+                                      hipStream_t st)
+{
+    if (q == 19)
+        hipLaunchKernelGGL((init_kernel<19, WLB_STORAGE>), dim3(grid), dim3(kWG), 0, st, a, rhou, z0, z1);
+    else
+        hipLaunchKernelGGL((init_kernel<27, WLB_STORAGE>), dim3(grid), dim3(kWG), 0, st, a, rhou, z0, z1);
+    return hipGetLastError();
+}
+
+hipError_t WLB_CAT(pdfs_, WLB_SUFFIX)(int q, const SweepArgs &a, double *buf, int z0, int z1, bool to_device,
+                                      bool swapped, int grid, hipStream_t st)
+{
+    return q == 19 ? pdfs_q<19>(a, buf, z0, z1, to_device, swapped, grid, st)
+                   : pdfs_q<27>(a, buf, z0, z1, to_device, swapped, grid, st);
+}
+
+hipError_t WLB_CAT(exchange_, WLB_SUFFIX)(void *arena, const DevBlock *blocks, const uint32_t *masks,
+                                          const XItem *items, int nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    using Raw = typename Codec<WLB_STORAGE>::Raw;
+    hipLaunchKernelGGL((exchange_kernel<Raw>), dim3(nitems), dim3(kWG), 0, st, reinterpret_cast<Raw *>(arena),
+                       blocks, masks, items);
+    return hipGetLastError();
+}
+
+}  // namespace wlb

@@ -1,0 +1,112 @@
+// wlb_internal.hpp -- data structures shared by the host runtime and the HIP
+// kernels of libwlb.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wlb {
+
+constexpr int kMaxQ = 27;
+constexpr int kWG = 256;  // threads per workgroup of every sweep kernel
+
+// Storage of one block in the arena.  Every population slot i is an array
+// s_i[z][y][x] over the block's cells plus one ghost layer on each side,
+// x fastest.  Rows are padded so that interior x = 0 starts on a 128-byte
+// boundary (the alignment rule of the paper's Field, Sec. 4.2):
+//   element(i, x, y, z) = pop + i * slot + (z + 1) * plane + (y + 1) * pitch + xoff + x
+// for x in [-1, n0], y in [-1, n1], z in [-1, n2].  Read with scalar loads.
+struct DevBlock {
+    int64_t pop;    // element index of slot 0, ghost-inclusive origin (row start of y=-1,z=-1)
+    int64_t slot;   // elements per population slot
+    int64_t mask;   // index of interior cell (0,0,0) in the u32 mask array; -1 = block has no solid
+    int32_t pitch;  // elements per row
+    int32_t plane;  // elements per z-plane = pitch * (n1 + 2)
+    int32_t n[3];   // interior extent
+    int32_t g[3];   // global coordinates of interior cell (0,0,0)
+    int32_t mpitch; // mask elements per row (interior only)
+    int32_t mplane; // mask elements per plane
+    int32_t xoff;   // element offset of interior x = 0 within a row
+    int32_t pad[3];
+};
+static_assert(sizeof(DevBlock) == 80, "DevBlock layout");
+
+// One tile of a sweep: block id and start/extent (extent <= 256 cells).
+// Packed as int4 {block, x0 | ex << 16, y0 | ey << 16, z0 | ez << 16}.
+struct TileHost {
+    int32_t b, x0, y0, z0, ex, ey, ez;
+};
+
+// Exchange work item: copy population `slot` over a rectangular region of
+// cells from block sb (coordinates s0 + r) to block db (coordinates d0 + r),
+// r over the linear cell range [start, start + count) of a region with
+// extents (ex, ey, *).  chk >= 0: skip cells whose destination mask has bit
+// chk or the solid bit set (used after the odd sweep).
+struct XItem {
+    int32_t sb, db;
+    int32_t slot, chk;
+    int32_t ex, ey;
+    int32_t s0[3];
+    int32_t d0[3];
+    int32_t start, count;
+};
+static_assert(sizeof(XItem) == 56, "XItem layout");
+
+// Mask word of a cell: bit i (i < 27) set when the neighbour x + c_i is a
+// solid cell; bit 31 set when the cell itself is solid.
+constexpr uint32_t kSolidBit = 0x80000000u;
+
+// Runtime parameters of a sweep (uniform, passed by value).
+struct SweepArgs {
+    void *arena;
+    const DevBlock *blocks;
+    const int4 *tiles;
+    const uint32_t *masks;
+    const float *mlp;
+    int32_t ntiles;
+    int32_t dom[3];
+    int32_t periodic;      // bit a set: axis a wraps
+    int32_t pressure_axis; // -1 or axis
+    int32_t closure;
+    int32_t pad0;
+    double omega;          // 1 / tau0
+    double omega_minus;    // TRT rate of the antisymmetric part at tau0
+    double magic;          // TRT Lambda
+    double omega_bulk;
+    double omega_higher;
+    double force[3];
+    double rho_in, rho_out;
+    double tau0;
+    double smag_k;         // 18 sqrt(2) C_s^2
+};
+
+// Arguments of the moments / reduction pass.
+struct MomArgs {
+    SweepArgs s;
+    int32_t swapped;       // 1: layout after an even sweep (read like the odd sweep)
+    int32_t z0, z1;        // global z range written to out (out == nullptr: none)
+    double *out;           // [4][ncells of slab]: rho, ux, uy, uz in global order of the slab
+    double *partials;      // [ntiles][8] or nullptr
+};
+
+// Kernel launchers, one set per storage type (sweep_<type>.hip).
+#define WLB_DECLARE_LAUNCHERS(S)                                                                              \
+    hipError_t sweep_##S(int q, int coll, bool odd, const SweepArgs &a, int grid, hipStream_t st);            \
+    hipError_t moments_##S(int q, const MomArgs &a, int grid, hipStream_t st);                               \
+    hipError_t init_##S(int q, const SweepArgs &a, const double *rhou, int z0, int z1, int grid,             \
+                        hipStream_t st);                                                                      \
+    hipError_t pdfs_##S(int q, const SweepArgs &a, double *buf, int z0, int z1, bool to_device, bool swapped, \
+                        int grid, hipStream_t st);                                                            \
+    hipError_t exchange_##S(void *arena, const DevBlock *blocks, const uint32_t *masks, const XItem *items,   \
+                            int nitems, hipStream_t st);
+WLB_DECLARE_LAUNCHERS(f64)
+WLB_DECLARE_LAUNCHERS(f32)
+WLB_DECLARE_LAUNCHERS(f16)
+WLB_DECLARE_LAUNCHERS(bf16)
+
+// Storage-independent kernels (misc.hip).
+hipError_t launch_masks(const SweepArgs &a, const uint8_t *solid, int q, int grid, hipStream_t st);
+hipError_t launch_reduce_totals(const double *partials, int n, double *out8, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+
+}  // namespace wlb

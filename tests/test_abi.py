@@ -1,0 +1,135 @@
+"""Host-side checks of libwlb.so that need no GPU: the library loads, exports
+every symbol that include/wlb.h declares, and its host logic (block
+validation, neighbour and exchange tables, arena layout, tiles) behaves."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
+from paper_1909_13772_amd import inputs  # noqa: E402
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "wlb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wlb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(wlb._lib, n), n
+        assert n in wlb.EXPORTED, n
+
+
+def test_param_struct_layout_matches_header():
+    import ctypes as C
+    assert C.sizeof(wlb.wlb_lbm_params) == 8 * 4 + 24 + 8 + 8 + 8 + 8 + 16 + 8 + 8 + 8
+    assert C.sizeof(wlb.wlb_block_desc) == 24
+
+
+def _crossing_links(n, periodic, q):
+    """Brute force: interior (cell, direction) pairs whose target x + c_i
+    leaves the block through a periodic face -- exactly the populations one
+    exchange must move (each once)."""
+    import oracle as O
+    c, _, _ = O.stencil(q)
+    cnt = 0
+    for i in range(1, q):
+        for z in range(n[2]):
+            for y in range(n[1]):
+                for x in range(n[0]):
+                    t = (x + c[i][0], y + c[i][1], z + c[i][2])
+                    out = [t[a] < 0 or t[a] >= n[a] for a in range(3)]
+                    if any(out) and all(periodic[a] or not out[a] for a in range(3)):
+                        cnt += 1
+    return cnt
+
+
+def test_create_single_block_layout():
+    h, nbytes = wlb.wlb_blocks_create([((0, 0, 0), (32, 32, 32))], (32, 32, 32), (1, 1, 1), 19, wlb.F64)
+    try:
+        info = wlb.wlb_info(h)
+        assert info.n_blocks == 1 and info.n_cells == 32 ** 3
+        # packed rows: 32 x 8 x 1 tiles
+        assert info.n_tiles == 32 * 32 // 8
+        assert info.xchg_elems == _crossing_links((32, 32, 32), (1, 1, 1), 19)
+        # rows padded: x = 0 on a 128-byte boundary, pitch multiple of 16 doubles
+        pitch = -(-(16 + 32 + 1) // 16) * 16
+        slot = pitch * 34 * 34
+        assert info.pop_bytes >= 19 * slot * 8
+        assert nbytes >= info.pop_bytes
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+def test_d3q27_exchange_counts_with_walls():
+    # x non-periodic: no x faces, edges or corners across x
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (8, 6, 4))], (8, 6, 4), (0, 1, 1), 27, wlb.F32)
+    try:
+        info = wlb.wlb_info(h)
+        assert info.xchg_elems == _crossing_links((8, 6, 4), (0, 1, 1), 27)
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+@pytest.mark.parametrize("bad", [
+    [((0, 0, 0), (16, 32, 32)), ((16, 0, 0), (16, 16, 32)), ((16, 16, 0), (16, 16, 32))],  # face mismatch
+    [((0, 0, 0), (16, 32, 32))],  # does not cover
+    [((0, 0, 0), (32, 32, 32)), ((0, 0, 0), (32, 32, 32))],  # overlap / over-cover
+    [((0, 0, 0), (40, 32, 32))],  # outside
+])
+def test_create_rejects_bad_block_lists(bad):
+    with pytest.raises(wlb.WlbError) as e:
+        wlb.wlb_blocks_create(bad, (32, 32, 32), (1, 1, 1), 19, wlb.F64)
+    assert e.value.code == wlb.WLB_ERR_ARG
+
+
+def test_create_rejects_bad_enums():
+    with pytest.raises(wlb.WlbError):
+        wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 15, wlb.F64)
+    with pytest.raises(wlb.WlbError):
+        wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 19, 7)
+
+
+def test_uneven_rectilinear_blocks_accepted():
+    blocks, dom = inputs.uneven_blocks(0)
+    assert len(blocks) == 512
+    h, nbytes = wlb.wlb_blocks_create(blocks, dom, (0, 1, 1), 27, wlb.F32)
+    try:
+        info = wlb.wlb_info(h)
+        assert info.n_blocks == 512
+        assert info.n_cells == dom[0] * dom[1] * dom[2]
+        assert info.n_tiles > 512
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+def test_set_tiles_validates_and_counts():
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (40, 20, 10))], (40, 20, 10), (1, 1, 1), 19, wlb.F32)
+    try:
+        wlb.wlb_set_tiles(h, 16, 4, 4, 0)
+        assert wlb.wlb_info(h).n_tiles == 3 * 5 * 3
+        with pytest.raises(wlb.WlbError):
+            wlb.wlb_set_tiles(h, 64, 8, 1, 0)
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+def test_calls_before_bind_fail_cleanly():
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 19, wlb.F64)
+    try:
+        rho, u = inputs.uniform_state((8, 8, 8))
+        with pytest.raises(wlb.WlbError) as e:
+            wlb.wlb_lbm_init(h, wlb.SRT, wlb.make_params(), rho.ravel(), u.ravel())
+        assert e.value.code == wlb.WLB_ERR_STATE
+        with pytest.raises(wlb.WlbError) as e:
+            wlb.wlb_lbm_step(h, 1)
+        assert e.value.code == wlb.WLB_ERR_STATE
+    finally:
+        wlb.wlb_blocks_destroy(h)

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.  FP64 storage must agree to 1e-12 (relative L2 of the
+velocity over fluid cells, and max population error relative to max |f|);
+FP32 storage to 1e-5, FP16 storage to 1e-3 (velocity); BF16 storage is
+reported against a looser 1e-2 bound (8 mantissa bits).  Block
+decomposition, tile shape, persistent grid, graph replay and sweep/exchange
+splitting must not change a single bit."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import fluid_mask, gpu_run, inputs, oracle_params, oracle_run, pop_err, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
+
+TOL = {wlb.F64: 1e-12, wlb.F32: 1e-5, wlb.F16DEV: 1e-3, wlb.BF16DEV: 1e-2}
+
+
+def _compare(case, storage, q, gpu, orc, solid, n, check_pops=True):
+    d, r, u, tot, B = gpu
+    do, ro, uo, to = orc
+    B.close()
+    m = fluid_mask(solid, n)
+    eu = rel_l2(u.reshape(3, -1), uo, m)
+    er = np.abs(r.reshape(-1)[m] - ro[m]).max()
+    ep = pop_err(d[:, m], do[:, m], q)
+    say(f"{case}: u rel L2 {eu:.3e}, rho max {er:.3e}, pops {ep:.3e}")
+    tol = TOL[storage]
+    assert eu <= tol, (case, eu)
+    if check_pops and storage == wlb.F64:
+        assert ep <= tol, (case, ep)
+        assert er <= 1e-12
+    return eu
+
+
+# ---------------------------------------------------------------------------
+def test_taylor_green_32_fp64_100_steps():
+    """Periodic 32^3 block, D3Q19 SRT, tau 0.8, TGV u0 = 0.01, 100 steps."""
+    say("case tgv32 fp64")
+    n, steps, tau = 32, 100, 0.8
+    shape = (n, n, n)
+    rho, u = inputs.taylor_green(n, 0.01)
+    p = wlb.make_params(tau=tau)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 19, wlb.F64, wlb.SRT, p, rho, u, steps=steps)
+    orc = oracle_run(oracle_params(19, 0, tau, 0, (1, 1, 1)), shape, rho, u, None, steps)
+    _compare("tgv32", wlb.F64, 19, gpu, orc, None, n ** 3)
+    tot = gpu[3]
+    # exact mass conservation and the analytic energy decay
+    assert abs(tot[0] - n ** 3) < 1e-9
+    e0 = 0.5 * (u ** 2).sum()
+    k = 2 * math.pi / n
+    exact = math.exp(-4 * (tau - 0.5) / 3 * k * k * steps)
+    assert abs(tot[4] / e0 - exact) < 0.02 * exact
+
+
+@pytest.mark.parametrize("q,coll", [(19, 0), (19, 1), (19, 2), (27, 0), (27, 1), (27, 2)])
+@pytest.mark.parametrize("steps", [6, 7])
+def test_random_state_periodic_fp64(q, coll, steps):
+    """Ragged 20x18x17 periodic box, random state, body force, every operator."""
+    say(f"case random q{q} coll{coll} steps{steps}")
+    shape = (20, 18, 17)
+    rho, u = inputs.random_state(shape, seed=q + coll)
+    F = (1e-5, -2e-5, 3e-6)
+    kw = dict(tau=0.7, magic=0.11, omega_bulk=1.3, omega_higher=1.1, force=F)
+    p = wlb.make_params(**kw)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), q, wlb.F64, coll, p, rho, u, steps=steps)
+    op = oracle_params(q, coll, 0.7, 0.11, (1, 1, 1), F, omega_bulk=1.3, omega_higher=1.1)
+    orc = oracle_run(op, shape, rho, u, None, steps)
+    _compare(f"random q{q} c{coll} s{steps}", wlb.F64, q, gpu, orc, None, np.prod(shape))
+
+
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+def test_channel_walls_force_fp64(q, coll):
+    say(f"case channel q{q}")
+    shape = (24, 20, 12)
+    rho, u = inputs.random_state(shape, seed=5, umag=0.01)
+    F = (2e-5, 0, 0)
+    p = wlb.make_params(tau=0.8, magic=3 / 16, force=F, omega_bulk=1.2, omega_higher=0.9)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 0, 1), q, wlb.F64, coll, p, rho, u, steps=9)
+    op = oracle_params(q, coll, 0.8, 3 / 16, (1, 0, 1), F, omega_bulk=1.2, omega_higher=0.9)
+    orc = oracle_run(op, shape, rho, u, None, 9)
+    _compare(f"channel q{q}", wlb.F64, q, gpu, orc, None, np.prod(shape))
+
+
+def _porous_case(q, coll, storage, steps, seed=1):
+    blocks, dom = inputs.rectilinear_blocks([8, 12, 6], [10, 6], [7, 9])
+    solid, frac, _ = inputs.spheres(dom, seed=seed, rmin=2.0, rmax=4.0, solid_fraction=0.2, clear_x=2)
+    rho, u = inputs.random_state(dom, seed=seed + 10, umag=0.01)
+    p = wlb.make_params(tau=0.8, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, pressure_axis=0,
+                        rho_in=1.002, rho_out=0.998)
+    gpu = gpu_run(blocks, dom, (0, 1, 1), q, storage, coll, p, rho, u, solid, steps=steps)
+    op = oracle_params(q, coll, 0.8, 3 / 16, (0, 1, 1), pressure_axis=0, rho_in=1.002, rho_out=0.998,
+                       omega_bulk=1.2, omega_higher=1.0)
+    orc = oracle_run(op, dom, rho, u, solid, steps)
+    return gpu, orc, solid, dom
+
+
+@pytest.mark.parametrize("q,coll", [(27, 2), (19, 0), (19, 1)])
+@pytest.mark.parametrize("steps", [10, 11])
+def test_porous_uneven_blocks_pressure_fp64(q, coll, steps):
+    """Uneven rectilinear blocks (3 x 2 x 2), spheres, density faces on x,
+    periodic y/z: exercises masks, bounce-back, anti-bounce-back and the
+    exchange in both directions."""
+    say(f"case porous q{q} coll{coll} steps{steps}")
+    gpu, orc, solid, dom = _porous_case(q, coll, wlb.F64, steps)
+    _compare(f"porous q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
+
+
+@pytest.mark.parametrize("coll", [0, 1])
+def test_smagorinsky_fp64(coll):
+    say(f"case smagorinsky coll{coll}")
+    shape = (16, 12, 10)
+    rho, u = inputs.random_state(shape, seed=7, umag=0.05)
+    p = wlb.make_params(tau=0.5075, magic=3 / 16, closure=wlb.CLOSURE_SMAG, cs_smag=0.1)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 19, wlb.F64, coll, p, rho, u, steps=8)
+    op = oracle_params(19, coll, 0.5075, 3 / 16, (1, 1, 1), closure=1, cs_smag=0.1)
+    orc = oracle_run(op, shape, rho, u, None, 8)
+    _compare(f"smag c{coll}", wlb.F64, 19, gpu, orc, None, np.prod(shape))
+
+
+def test_smagorinsky_mrt_fp64():
+    say("case smagorinsky mrt")
+    shape = (12, 10, 9)
+    rho, u = inputs.random_state(shape, seed=8, umag=0.05)
+    p = wlb.make_params(tau=0.52, closure=wlb.CLOSURE_SMAG, cs_smag=0.1, omega_bulk=1.1, omega_higher=1.0)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 27, wlb.F64, 2, p, rho, u, steps=5)
+    op = oracle_params(27, 2, 0.52, 0, (1, 1, 1), closure=1, cs_smag=0.1, omega_bulk=1.1, omega_higher=1.0)
+    orc = oracle_run(op, shape, rho, u, None, 5)
+    _compare("smag mrt", wlb.F64, 27, gpu, orc, None, np.prod(shape))
+
+
+@pytest.mark.parametrize("storage", [1, 2, 3])
+def test_reduced_precision_storage_vs_fp64_oracle(storage):
+    """FP32 / FP16 / BF16 deviation storage with FP32 collision against the
+    FP64 oracle (velocity relative L2)."""
+    say(f"case precision storage{storage}")
+    shape = (24, 20, 16)
+    rho, u = inputs.random_state(shape, seed=11, umag=0.03)
+    p = wlb.make_params(tau=0.6, magic=3 / 16)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 19, storage, wlb.TRT, p, rho, u, steps=20)
+    orc = oracle_run(oracle_params(19, 1, 0.6, 3 / 16, (1, 1, 1)), shape, rho, u, None, 20)
+    _compare(f"precision {storage}", storage, 19, gpu, orc, None, np.prod(shape), check_pops=False)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_reduced_precision_porous(storage):
+    say(f"case precision porous storage{storage}")
+    gpu, orc, solid, dom = _porous_case(27, 2, storage, 12)
+    _compare(f"porous prec {storage}", storage, 27, gpu, orc, solid, np.prod(dom), check_pops=False)
+
+
+# ---------------------------------------------------------------------------
+# Bitwise invariances of the GPU path
+# ---------------------------------------------------------------------------
+def _porous_inputs(dom, seed=3):
+    solid, _, _ = inputs.spheres(dom, seed=seed, rmin=2.0, rmax=3.5, solid_fraction=0.15, clear_x=2)
+    rho, u = inputs.random_state(dom, seed=seed, umag=0.01)
+    return solid, rho, u
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_block_decomposition_is_bitwise_invariant(storage):
+    say(f"case decomposition storage{storage}")
+    dom = (48, 32, 24)
+    solid, rho, u = _porous_inputs(dom)
+    p = wlb.make_params(tau=0.7, magic=3 / 16, omega_bulk=1.1, omega_higher=1.0, pressure_axis=0, rho_in=1.001,
+                        rho_out=0.999)
+    layouts = [wlb.single_block(dom), inputs.uniform_blocks(dom, (16, 16, 8))[0],
+               inputs.rectilinear_blocks([16, 8, 24], [10, 22], [4, 12, 8])[0]]
+    ref = None
+    for k, bl in enumerate(layouts):
+        for steps in (9,):
+            d, r, uu, tot, B = gpu_run(bl, dom, (0, 1, 1), 27, storage, 2, p, rho, u, solid, steps=steps)
+            B.close()
+            if ref is None:
+                ref = d
+            else:
+                assert np.array_equal(d, ref), f"layout {k} differs"
+
+
+def test_tiles_grid_graph_and_split_are_bitwise_invariant():
+    say("case tiles/graph/split")
+    dom = (40, 24, 20)
+    solid, rho, u = _porous_inputs(dom, seed=4)
+    blocks = inputs.rectilinear_blocks([16, 24], [24], [12, 8])[0]
+    p = wlb.make_params(tau=0.66, magic=3 / 16, force=(1e-5, 0, 0))
+    runs = [dict(), dict(tiles=(16, 4, 4, 0)), dict(tiles=(64, 4, 1, 7)), dict(tiles=(8, 8, 4, 3)),
+            dict(graph=False), dict(mode="split")]
+    ref = None
+    for kw in runs:
+        d, r, uu, tot, B = gpu_run(blocks, dom, (1, 1, 0), 19, wlb.F32, wlb.TRT, p, rho, u, solid, steps=13, **kw)
+        B.close()
+        if ref is None:
+            ref = d
+        else:
+            assert np.array_equal(d, ref), kw
+
+
+@pytest.mark.parametrize("storage", [0, 2])
+def test_checkpoint_resume_is_bitwise(storage):
+    say(f"case resume storage{storage}")
+    dom = (20, 16, 12)
+    solid, rho, u = _porous_inputs(dom, seed=5)
+    p = wlb.make_params(tau=0.7, magic=3 / 16, pressure_axis=0, rho_in=1.001, rho_out=0.999)
+    blocks = inputs.rectilinear_blocks([12, 8], [16], [6, 6])[0]
+    d_full, *_, B = gpu_run(blocks, dom, (0, 1, 1), 19, storage, wlb.TRT, p, rho, u, solid, steps=15)
+    B.close()
+    d_mid, *_, B = gpu_run(blocks, dom, (0, 1, 1), 19, storage, wlb.TRT, p, rho, u, solid, steps=7)
+    B.close()
+    B2 = wlb.Blocks(blocks, dom, (0, 1, 1), stencil=19, storage=storage)
+    B2.init(wlb.TRT, p, rho, u, solid)
+    B2.pdfs_set(d_mid)
+    B2.step(8)
+    d_res = B2.pdfs_get()
+    B2.close()
+    assert np.array_equal(d_res, d_full)
+
+
+def test_health_check_reports_divergence():
+    say("case health")
+    dom = (16, 16, 8)
+    rho, u = inputs.random_state(dom, seed=6)
+    p = wlb.make_params(tau=0.8, health_every=2)
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 1, 1), stencil=19, storage=wlb.F32)
+    B.init(wlb.SRT, p, rho, u)
+    B.step(4)  # healthy
+    d = B.pdfs_get()
+    d[3, 100] = np.nan
+    B.pdfs_set(d)
+    with pytest.raises(wlb.WlbError) as e:
+        B.step(4)
+    assert e.value.code == wlb.WLB_ERR_DIVERGED
+    B.close()
+
+
+def test_totals_match_fsum_of_fields():
+    say("case totals")
+    dom = (30, 20, 10)
+    solid, rho, u = _porous_inputs(dom, seed=9)
+    p = wlb.make_params(tau=0.8, force=(1e-5, 0, 0))
+    d, r, uu, tot, B = gpu_run(wlb.single_block(dom), dom, (1, 1, 1), 19, wlb.F64, wlb.SRT, p, rho, u, solid,
+                               steps=5)
+    B.close()
+    fl = solid.reshape(-1) == 0
+    rr = r.reshape(-1)[fl]
+    assert tot[6] == fl.sum()
+    assert abs(tot[0] - math.fsum(rr)) <= 4 * np.spacing(tot[0])
+    px = math.fsum(rr * uu[0].reshape(-1)[fl])
+    assert abs(tot[1] - px) <= 1e-15 * max(1.0, abs(px)) + 1e-18
+    assert tot[7] == 5
