@@ -62,14 +62,14 @@ def poiseuille_series(H, nu, g, T, s):
     return u
 
 
-def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False):
+def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True):
     import numpy as np
     import torch
 
     shape = (N, N, N)
     rho, u = inputs.uniform_state(shape)
     p = wlb.make_params(tau=TAU, magic=MAGIC, force=(FX, 0.0, 0.0), closure=closure, cs_smag=0.1 if closure else 0.0,
-                        autotune=1)
+                        autotune=1 if autotune else 0)
     B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=19, storage=storage)
     try:
         B.init(wlb.TRT, p, rho, u)
@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default tile shape (for profiler runs that should hold only the timed launches)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (blocks would shard over GPUs "
@@ -169,7 +171,7 @@ def main():
 
     torch.cuda.set_device(0)
     print(f"[bench] device {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
-    res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True)
+    res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True, autotune=not args.no_autotune)
     head = summarize(res, wlb.F64, args.steps, 8)
     print(f"[bench] f64: {head['mlups']:.0f} MLUPS, sweep {head['sweep_ms']:.3f} ms, "
           f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
@@ -177,7 +179,7 @@ def main():
     if not args.no_variants:
         for name, st, eb, cl in (("f32", wlb.F32, 4, 0), ("f16dev", wlb.F16DEV, 2, 0), ("bf16dev", wlb.BF16DEV, 2, 0),
                                  ("f32_smagorinsky", wlb.F32, 4, 1)):
-            r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl)
+            r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune)
             sm = summarize(r, st, args.variant_steps, eb)
             variants[name] = {"mlups": round(sm["mlups"], 1), "roofline_frac": round(sm["frac"], 4),
                               "achieved_gbs": round(sm["achieved_gbs"], 1), "sweep_ms": round(sm["sweep_ms"], 4),

@@ -205,6 +205,55 @@ int wlb_set_graph(wlb_blocks_t h, int32_t on);
 int wlb_set_kernel_timing(wlb_blocks_t h, int32_t on);
 int wlb_kernel_times(wlb_blocks_t h, double ms[4], int64_t launches[4]);
 
+/* --- learned closure: network evaluation and training ------------------ */
+
+/* Box filter of the current state for LES training data: for every coarse
+ * cell of a factor^3 coarsening, the averages of rho, u (Guo velocity) and
+ * u_a u_b over its fine cells, into out[10][Nc] (device, FP64, coarse cells
+ * in global order; channels rho, ux, uy, uz, uxux, uyuy, uzuz, uxuy, uxuz,
+ * uyuz).  Single-block handles whose domain the factor divides.
+ * Synchronises the bound stream.  (Sec. 4.4: data gathered for evaluation.) */
+int wlb_box_filter(wlb_blocks_t h, int32_t factor, double *out);
+
+/* Training pairs of the learned closure from filtered fields filt[10][Nc]
+ * (device, the layout of wlb_box_filter) on a periodic coarse grid nc[3]:
+ * target[Nc] = 3 nu_t with nu_t = max(0, -dev(tau_sgs) : S / (2 S : S)),
+ * tau_sgs = avg(u u) - u u, S = symmetric central-difference gradient of the
+ * filtered u; raw[Nc][7] = (Pi = -(2/3) rho (tau0 + target) S (xx, yy, zz,
+ * xy, xz, yz), rho - 1).  Device pointers; asynchronous on `hip_stream`. */
+int wlb_les_targets(const double *filt, const int32_t nc[3], double tau0, float *raw, float *target,
+                    void *hip_stream);
+
+/* Bytes of device workspace wlb_mlp_forward needs. */
+#define WLB_MLP_WORKSPACE 4096
+
+/* Evaluate the closure network (7 -> 32 -> 32 -> 1, see WLB_MLP_NPARAM) with
+ * the same matrix-core code the sweep uses: raw[n][7] (device, FP32: Pi_xx,
+ * Pi_yy, Pi_zz, Pi_xy, Pi_xz, Pi_yz, rho - 1) -> out[n] (device, output o;
+ * tau = tau0 + softplus(o)) and fallback[n] (device, 1 where a standardised
+ * feature exceeds 8 in magnitude or o is not finite: the sweep then uses the
+ * Smagorinsky time).  params: host, WLB_MLP_NPARAM floats.  workspace:
+ * device, WLB_MLP_WORKSPACE bytes, 16-byte aligned.  Synchronises `hip_stream`.
+ * (Paper Sec. 5.1.1: relaxation times that vary per cell.) */
+int wlb_mlp_forward(const float *params, void *workspace, const float *raw, int64_t n, float *out, int32_t *fallback,
+                    void *hip_stream);
+
+/* Device workspace bytes wlb_mlp_grad needs for a minibatch of n samples. */
+size_t wlb_mlp_grad_workspace(int64_t n);
+
+/* Gradient of L = (1/n) sum ((softplus(o_s) - target_s) * inv_scale)^2 with
+ * respect to all parameters (zero for mean / inv_std), FP32, deterministic.
+ * params, raw[n][7], target[n], grad[WLB_MLP_NPARAM], loss[1], workspace:
+ * device pointers.  Asynchronous on `hip_stream`. */
+int wlb_mlp_grad(const float *params, const float *raw, const float *target, int64_t n, double inv_scale, float *grad,
+                 float *loss, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* One Adam update of the FP32 master parameters in place (mean / inv_std
+ * untouched); m, v: device moment buffers (WLB_MLP_NPARAM floats, zero at
+ * step 1); step counts from 1.  Asynchronous on `hip_stream`. */
+int wlb_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr, double beta1,
+                 double beta2, double eps, void *hip_stream);
+
 /* Release the handle (not the arena). */
 void wlb_blocks_destroy(wlb_blocks_t h);
 

@@ -102,4 +102,60 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
+// Training pairs of the learned closure from box-filtered fine fields
+// filt[10][Nc] (rho, u, u_a u_b averages) on a periodic coarse grid (spacing
+// 1, acoustic scaling keeps velocities):
+//   S_ab = (d_a u_b + d_b u_a) / 2 with central differences of the filtered u;
+//   tau_sgs = avg(u u) - u u; nu_t = max(0, -dev(tau_sgs) : S / (2 S : S + 1e-30));
+//   target dtau = 3 nu_t; features raw = (Pi = -(2/3) rho (tau0 + dtau) S, rho - 1)
+//   in the order xx, yy, zz, xy, xz, yz.
+__global__ __launch_bounds__(kWG) void les_targets_kernel(const double *__restrict__ F, int nx, int ny, int nz,
+                                                          double tau0, float *__restrict__ raw,
+                                                          float *__restrict__ target)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    for (int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x; c < N; c += (int64_t)gridDim.x * kWG) {
+        const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+        const int xp = (x + 1) % nx, xm = (x + nx - 1) % nx, yp = (y + 1) % ny, ym = (y + ny - 1) % ny,
+                  zp = (z + 1) % nz, zm = (z + nz - 1) % nz;
+        auto at = [&](int k, int X, int Y, int Z) { return F[k * N + ((int64_t)Z * ny + Y) * nx + X]; };
+        double g[3][3];  // g[a][b] = d_a u_b
+        for (int b = 0; b < 3; ++b) {
+            g[0][b] = 0.5 * (at(1 + b, xp, y, z) - at(1 + b, xm, y, z));
+            g[1][b] = 0.5 * (at(1 + b, x, yp, z) - at(1 + b, x, ym, z));
+            g[2][b] = 0.5 * (at(1 + b, x, y, zp) - at(1 + b, x, y, zm));
+        }
+        double S[6] = {g[0][0], g[1][1], g[2][2], 0.5 * (g[0][1] + g[1][0]), 0.5 * (g[0][2] + g[2][0]),
+                       0.5 * (g[1][2] + g[2][1])};
+        const double rho = at(0, x, y, z);
+        const double u[3] = {at(1, x, y, z), at(2, x, y, z), at(3, x, y, z)};
+        double t[6] = {at(4, x, y, z) - u[0] * u[0], at(5, x, y, z) - u[1] * u[1], at(6, x, y, z) - u[2] * u[2],
+                       at(7, x, y, z) - u[0] * u[1], at(8, x, y, z) - u[0] * u[2], at(9, x, y, z) - u[1] * u[2]};
+        const double tr = (t[0] + t[1] + t[2]) / 3.0;
+        t[0] -= tr;
+        t[1] -= tr;
+        t[2] -= tr;
+        const double tS = t[0] * S[0] + t[1] * S[1] + t[2] * S[2] + 2.0 * (t[3] * S[3] + t[4] * S[4] + t[5] * S[5]);
+        const double SS = S[0] * S[0] + S[1] * S[1] + S[2] * S[2] + 2.0 * (S[3] * S[3] + S[4] * S[4] + S[5] * S[5]);
+        double nu = -tS / (2.0 * SS + 1e-30);
+        if (!(nu > 0.0)) nu = 0.0;
+        const double dtau = 3.0 * nu;
+        for (int k = 0; k < 6; ++k) raw[c * 7 + k] = (float)(-(2.0 / 3.0) * rho * (tau0 + dtau) * S[k]);
+        raw[c * 7 + 6] = (float)(rho - 1.0);
+        target[c] = (float)dtau;
+    }
+}
+
+hipError_t launch_les_targets(const double *filt, const int32_t nc[3], double tau0, float *raw, float *target,
+                              hipStream_t st)
+{
+    const int64_t N = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t g = (N + kWG - 1) / kWG;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(les_targets_kernel, dim3((int)g), dim3(kWG), 0, st, filt, nc[0], nc[1], nc[2], tau0, raw,
+                       target);
+    return hipGetLastError();
+}
+
 }  // namespace wlb

@@ -682,7 +682,7 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     h->off_totals = off;
     off += 256;
     h->off_mlp = off;
-    off += round_up(WLB_MLP_NPARAM * sizeof(float), 256);
+    off += round_up(mlp_dev_bytes(), 256);
     const size_t plane_cells = (size_t)domain[0] * domain[1];
     size_t stage = (size_t)64 << 20;
     stage = std::max(stage, (size_t)dvol);                            // solid array
@@ -717,7 +717,7 @@ int wlb_blocks_bind(wlb_blocks_t h, void *arena, size_t bytes, void *stream)
     h->args.blocks = reinterpret_cast<const DevBlock *>(h->arena + h->off_blocks);
     h->args.tiles = reinterpret_cast<const int4 *>(h->arena + h->off_tiles);
     h->args.masks = reinterpret_cast<const uint32_t *>(h->arena + h->off_mask);
-    h->args.mlp = reinterpret_cast<const float *>(h->arena + h->off_mlp);
+    h->args.mlp = h->arena + h->off_mlp;
     for (int a = 0; a < 3; ++a) h->args.dom[a] = h->dom[a];
     h->args.periodic = h->periodic[0] | (h->periodic[1] << 1) | (h->periodic[2] << 2);
     HIPCHK(hipMemcpyAsync(h->arena + h->off_blocks, h->dev.data(), h->dev.size() * sizeof(DevBlock),
@@ -737,7 +737,11 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
     if (p->pressure_axis >= 0 && h->periodic[p->pressure_axis])
         return fail(WLB_ERR_ARG, "the pressure axis must not be periodic");
     if (p->closure < WLB_CLOSURE_NONE || p->closure > WLB_CLOSURE_MLP) return fail(WLB_ERR_ARG, "bad closure");
-    if (p->closure == WLB_CLOSURE_MLP) return fail(WLB_ERR_UNSUPPORTED, "MLP closure not available in this build");
+    if (p->closure == WLB_CLOSURE_MLP) {
+        if (!p->mlp) return fail(WLB_ERR_ARG, "the MLP closure needs weights");
+        if (h->q != WLB_D3Q19 || collision == WLB_MRT || h->storage == WLB_F64)
+            return fail(WLB_ERR_UNSUPPORTED, "the MLP closure runs with D3Q19 SRT/TRT and FP32/FP16/BF16 storage");
+    }
     h->collision = collision;
     h->params = *p;
     drop_graph(h);
@@ -754,6 +758,11 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
     a.rho_out = p->rho_out;
     a.tau0 = p->tau;
     a.smag_k = 18.0 * std::sqrt(2.0) * p->cs_smag * p->cs_smag;
+    if (p->closure == WLB_CLOSURE_MLP) {
+        std::vector<unsigned char> dev(mlp_dev_bytes());
+        mlp_prepare(p->mlp, dev.data());
+        HIPCHK(hipMemcpyAsync(h->arena + h->off_mlp, dev.data(), dev.size(), hipMemcpyHostToDevice, h->stream));
+    }
     // --- geometry: which blocks need masks, then build them on the device
     const int64_t plane = (int64_t)h->dom[0] * h->dom[1];
     const int64_t N = plane * h->dom[2];
@@ -1020,6 +1029,79 @@ void wlb_blocks_destroy(wlb_blocks_t h)
         hipEventDestroy(e.b);
     }
     delete h;
+}
+
+int wlb_box_filter(wlb_blocks_t h, int32_t factor, double *out)
+{
+    if (!h || !out) return fail(WLB_ERR_ARG, "null argument");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    if (h->blocks.size() != 1) return fail(WLB_ERR_UNSUPPORTED, "the box filter works on single-block handles");
+    if (factor < 1) return fail(WLB_ERR_ARG, "filter factor must be >= 1");
+    for (int a = 0; a < 3; ++a)
+        if (h->dom[a] % factor) return fail(WLB_ERR_ARG, "the filter factor must divide the domain");
+    if (h->pending) {
+        int rc = wlb_ghost_exchange(h);
+        if (rc) return rc;
+    }
+    const int64_t nc = (int64_t)(h->dom[0] / factor) * (h->dom[1] / factor) * (h->dom[2] / factor);
+    const bool sw = h->parity == 1;
+    hipError_t e;
+    switch (h->storage) {
+    case WLB_F64: e = filter_f64(h->q, h->args, factor, out, nc, sw, h->stream); break;
+    case WLB_F32: e = filter_f32(h->q, h->args, factor, out, nc, sw, h->stream); break;
+    case WLB_F16DEV: e = filter_f16(h->q, h->args, factor, out, nc, sw, h->stream); break;
+    default: e = filter_bf16(h->q, h->args, factor, out, nc, sw, h->stream); break;
+    }
+    HIPCHK(e);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return WLB_OK;
+}
+
+int wlb_les_targets(const double *filt, const int32_t nc[3], double tau0, float *raw, float *target, void *stream)
+{
+    if (!filt || !nc || !raw || !target) return fail(WLB_ERR_ARG, "null argument");
+    for (int a = 0; a < 3; ++a)
+        if (nc[a] < 3) return fail(WLB_ERR_ARG, "coarse grid must have at least 3 cells per axis");
+    HIPCHK(launch_les_targets(filt, nc, tau0, raw, target, static_cast<hipStream_t>(stream)));
+    return WLB_OK;
+}
+
+int wlb_mlp_forward(const float *params, void *workspace, const float *raw, int64_t n, float *out, int32_t *fallback,
+                    void *stream)
+{
+    if (!params || !workspace || (n > 0 && (!raw || !out || !fallback))) return fail(WLB_ERR_ARG, "null argument");
+    if (n < 0) return fail(WLB_ERR_ARG, "negative sample count");
+    if (((uintptr_t)workspace) % 16) return fail(WLB_ERR_ARG, "workspace must be 16-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<unsigned char> dev(mlp_dev_bytes());
+    mlp_prepare(params, dev.data());
+    HIPCHK(hipMemcpyAsync(workspace, dev.data(), dev.size(), hipMemcpyHostToDevice, st));
+    if (n > 0) HIPCHK(launch_mlp_forward(workspace, raw, n, out, fallback, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return WLB_OK;
+}
+
+size_t wlb_mlp_grad_workspace(int64_t n) { return n > 0 ? mlp_grad_workspace_bytes(n) : 0; }
+
+int wlb_mlp_grad(const float *params, const float *raw, const float *target, int64_t n, double inv_scale, float *grad,
+                 float *loss, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!params || !raw || !target || !grad || !loss || !workspace) return fail(WLB_ERR_ARG, "null argument");
+    if (n <= 0) return fail(WLB_ERR_ARG, "empty minibatch");
+    if (ws_bytes < mlp_grad_workspace_bytes(n)) return fail(WLB_ERR_ARG, "workspace too small");
+    HIPCHK(launch_mlp_grad(params, raw, target, n, (float)inv_scale, grad, loss, static_cast<float *>(workspace),
+                           static_cast<hipStream_t>(stream)));
+    return WLB_OK;
+}
+
+int wlb_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr, double beta1,
+                 double beta2, double eps, void *stream)
+{
+    if (!params || !grad || !m || !v) return fail(WLB_ERR_ARG, "null argument");
+    if (step < 1) return fail(WLB_ERR_ARG, "Adam step count starts at 1");
+    HIPCHK(launch_mlp_adam(params, grad, m, v, step, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                           static_cast<hipStream_t>(stream)));
+    return WLB_OK;
 }
 
 int wlb_copy_probe(void *dst, const void *src, size_t bytes, int32_t reps, void *stream, double *ms)

@@ -23,7 +23,10 @@
 
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "lattice.hpp"
+#include "mlp.hpp"
 #include "wlb_internal.hpp"
 
 namespace wlb {
@@ -38,28 +41,51 @@ struct bf16_t {
 
 template <typename ST> struct Codec;
 
+// Populations are streamed once per sweep with no reuse inside the sweep:
+// WLB_NT selects non-temporal loads / stores for them.
+#ifndef WLB_NT
+#define WLB_NT 0
+#endif
+template <typename V>
+__device__ __forceinline__ V mem_ld(const V *p)
+{
+    if constexpr (WLB_NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <typename V>
+__device__ __forceinline__ void mem_st(V *p, V v)
+{
+    if constexpr (WLB_NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <> struct Codec<double> {
     using T = double;
     using Raw = uint64_t;
-    static __device__ __forceinline__ double ld(const double *p) { return *p; }
-    static __device__ __forceinline__ void st(double *p, double v) { *p = v; }
+    static __device__ __forceinline__ double ld(const double *p) { return mem_ld(p); }
+    static __device__ __forceinline__ void st(double *p, double v) { mem_st(p, v); }
 };
 template <> struct Codec<float> {
     using T = float;
     using Raw = uint32_t;
-    static __device__ __forceinline__ float ld(const float *p) { return *p; }
-    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ float ld(const float *p) { return mem_ld(p); }
+    static __device__ __forceinline__ void st(float *p, float v) { mem_st(p, v); }
 };
 template <> struct Codec<_Float16> {
     using T = float;
     using Raw = uint16_t;
-    static __device__ __forceinline__ float ld(const _Float16 *p) { return (float)*p; }
-    static __device__ __forceinline__ void st(_Float16 *p, float v) { *p = (_Float16)v; }
+    static __device__ __forceinline__ float ld(const _Float16 *p) { return (float)mem_ld(p); }
+    static __device__ __forceinline__ void st(_Float16 *p, float v) { mem_st(p, (_Float16)v); }
 };
 template <> struct Codec<bf16_t> {
     using T = float;
     using Raw = uint16_t;
-    static __device__ __forceinline__ float ld(const bf16_t *p) { return __uint_as_float((uint32_t)p->v << 16); }
+    static __device__ __forceinline__ float ld(const bf16_t *p)
+    {
+        return __uint_as_float((uint32_t)mem_ld(&p->v) << 16);
+    }
     static __device__ __forceinline__ void st(bf16_t *p, float v)
     {
         uint32_t u = __float_as_uint(v);
@@ -68,7 +94,7 @@ template <> struct Codec<bf16_t> {
             r = (u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u);  // inf stays inf, nan stays (quiet) nan
         else
             r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
-        p->v = (uint16_t)r;
+        mem_st(&p->v, (uint16_t)r);
     }
 };
 
@@ -295,13 +321,65 @@ __device__ __forceinline__ CollParams<T> coll_params(const SweepArgs &a)
     return c;
 }
 
-// Collide one cell in place.  Returns the macroscopic state used.
-// SRT / TRT are evaluated pair by pair (i, opp(i)) on the symmetric and
-// antisymmetric parts:
+// Non-equilibrium stress from the symmetric pair parts:
+// Pi = sum over pairs of c c (d_i + d_opp - 2 e+), e+ = w (A + 9/2 rho cu^2),
+// A = drho - 3/2 rho uu.
+template <int Q, typename T>
+__device__ __forceinline__ void pi_pairs(const T (&d)[Q], const Macro<Q, T> &m, T P[6])
+{
+    const T A = m.drho - T(1.5) * m.rho * m.uu;
+    for (int k = 0; k < 6; ++k) P[k] = T(0);
+    sfor<(Q - 1) / 2>([&](auto K) {
+        constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
+        constexpr T w = weight<Q, T>(i);
+        const T cu = cdot<i>(m.u);
+        const T n = d[i] + d[o] - T(2) * w * (A + T(4.5) * m.rho * cu * cu);
+        if constexpr (cx(i) != 0) P[0] += n;
+        if constexpr (cy(i) != 0) P[1] += n;
+        if constexpr (cz(i) != 0) P[2] += n;
+        if constexpr (cx(i) * cy(i) == 1) P[3] += n;
+        if constexpr (cx(i) * cy(i) == -1) P[3] -= n;
+        if constexpr (cx(i) * cz(i) == 1) P[4] += n;
+        if constexpr (cx(i) * cz(i) == -1) P[4] -= n;
+        if constexpr (cy(i) * cz(i) == 1) P[5] += n;
+        if constexpr (cy(i) * cz(i) == -1) P[5] -= n;
+    });
+}
+
+// SRT / TRT relaxation evaluated pair by pair (i, opp(i)) on the symmetric
+// and antisymmetric parts:
 //   e+ = w (drho - 3/2 rho uu + 9/2 rho cu^2),  e- = 3 w rho cu,
 //   F+ = w (9 cu cF - 3 u.F),                   F- = 3 w cF,
 //   d_i += r+ + r-, d_opp += r+ - r-,  r+- = -omega+- (d+- - e+-) + (1 - omega+-/2) F+-,
 // which keeps only the populations live (no equilibrium arrays).
+template <int Q, typename T>
+__device__ __forceinline__ void relax_pairs(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omm)
+{
+    const T A = m.drho - T(1.5) * m.rho * m.uu;
+    const T uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
+    const T fop = T(1) - T(0.5) * om, fom = T(1) - T(0.5) * omm;
+    {
+        constexpr T w0 = weight<Q, T>(0);
+        d[0] += -om * (d[0] - w0 * A) + fop * (w0 * (T(-3) * uF));
+    }
+    sfor<(Q - 1) / 2>([&](auto K) {
+        constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
+        constexpr T w = weight<Q, T>(i);
+        const T cu = cdot<i>(m.u);
+        const T cF = cdot<i>(F);
+        const T ep = w * (A + T(4.5) * m.rho * cu * cu);
+        const T em = T(3) * w * m.rho * cu;
+        const T fp = w * (T(9) * cu * cF - T(3) * uF);
+        const T fm = T(3) * w * cF;
+        const T dp = T(0.5) * (d[i] + d[o]), dm = T(0.5) * (d[i] - d[o]);
+        const T rp = -om * (dp - ep) + fop * fp;
+        const T rm = -omm * (dm - em) + fom * fm;
+        d[i] += rp + rm;
+        d[o] += rp - rm;
+    });
+}
+
+// Collide one cell in place.  Returns the macroscopic state used.
 template <int Q, int COLL, typename T>
 __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p)
 {
@@ -317,51 +395,15 @@ __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p
         }
         mrt_relax<Q, T>(d, de, Fi, om, p.omb, p.omh, nullptr);
     } else {
-        const T A = m.drho - T(1.5) * m.rho * m.uu;
-        const T uF = m.u[0] * p.F[0] + m.u[1] * p.F[1] + m.u[2] * p.F[2];
         if (p.closure == 1) {
-            // Pi_neq from the symmetric parts: sum over pairs of c c (d_i + d_opp - 2 e+)
-            T P[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-            sfor<(Q - 1) / 2>([&](auto K) {
-                constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
-                constexpr T w = weight<Q, T>(i);
-                const T cu = cdot<i>(m.u);
-                const T n = d[i] + d[o] - T(2) * w * (A + T(4.5) * m.rho * cu * cu);
-                if constexpr (cx(i) != 0) P[0] += n;
-                if constexpr (cy(i) != 0) P[1] += n;
-                if constexpr (cz(i) != 0) P[2] += n;
-                if constexpr (cx(i) * cy(i) == 1) P[3] += n;
-                if constexpr (cx(i) * cy(i) == -1) P[3] -= n;
-                if constexpr (cx(i) * cz(i) == 1) P[4] += n;
-                if constexpr (cx(i) * cz(i) == -1) P[4] -= n;
-                if constexpr (cy(i) * cz(i) == 1) P[5] += n;
-                if constexpr (cy(i) * cz(i) == -1) P[5] -= n;
-            });
+            T P[6];
+            pi_pairs<Q, T>(d, m, P);
             const T tau = tau_smagorinsky<T>(P, m.rho, p.tau0, p.smag_k);
             om = T(1) / tau;
             omm = T(1) / (T(0.5) + p.magic / (tau - T(0.5)));
         }
         if constexpr (COLL == 0) omm = om;
-        const T fop = T(1) - T(0.5) * om, fom = T(1) - T(0.5) * omm;
-        {
-            constexpr T w0 = weight<Q, T>(0);
-            d[0] += -om * (d[0] - w0 * A) + fop * (w0 * (T(-3) * uF));
-        }
-        sfor<(Q - 1) / 2>([&](auto K) {
-            constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
-            constexpr T w = weight<Q, T>(i);
-            const T cu = cdot<i>(m.u);
-            const T cF = cdot<i>(p.F);
-            const T ep = w * (A + T(4.5) * m.rho * cu * cu);
-            const T em = T(3) * w * m.rho * cu;
-            const T fp = w * (T(9) * cu * cF - T(3) * uF);
-            const T fm = T(3) * w * cF;
-            const T dp = T(0.5) * (d[i] + d[o]), dm = T(0.5) * (d[i] - d[o]);
-            const T rp = -om * (dp - ep) + fop * fp;
-            const T rm = -omm * (dm - em) + fom * fm;
-            d[i] += rp + rm;
-            d[o] += rp - rm;
-        });
+        relax_pairs<Q, T>(d, m, p.F, om, omm);
     }
     return m;
 }
@@ -526,8 +568,12 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
 // ---------------------------------------------------------------------------
 // The sweep kernel (one launch covers every tile of every block)
 // ---------------------------------------------------------------------------
+#ifndef WLB_WAVES_PER_EU
+#define WLB_WAVES_PER_EU 1
+#endif
 template <int Q, int COLL, typename ST, bool ODD>
-__global__ __launch_bounds__(kWG) void sweep_kernel(const SweepArgs a)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_PER_EU, 8))) void sweep_kernel(
+    const SweepArgs a)
 {
     using T = typename Codec<ST>::T;
     const CollParams<T> cp = coll_params<T>(a);
@@ -576,6 +622,78 @@ __global__ __launch_bounds__(kWG) void sweep_kernel(const SweepArgs a)
                 Codec<ST>::st(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
             });
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep with the learned closure (D3Q19, SRT/TRT, FP32 collision).  The MLP
+// is evaluated by the whole wavefront, so every lane runs the tile body;
+// lanes without a fluid cell compute on zeros and store nothing.  Falls back
+// to the Smagorinsky time when a feature is outside |x| <= 8 or the output is
+// not finite.
+// ---------------------------------------------------------------------------
+template <int COLL, typename ST, bool ODD>
+__global__ __launch_bounds__(kWG) void sweep_mlp_kernel(const SweepArgs a)
+{
+    constexpr int Q = 19;
+    using T = float;
+    static_assert(std::is_same<typename Codec<ST>::T, float>::value, "MLP closure runs in FP32");
+    const CollParams<T> cp = coll_params<T>(a);
+    const MlpDev *__restrict__ net = reinterpret_cast<const MlpDev *>(a.mlp);
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int4 tv = a.tiles[t];
+        const CellPos c = tile_cell(tv, threadIdx.x);
+        const DevBlock B = a.blocks[tv.x];
+        uint32_t mask = 0;
+        if (c.valid && B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
+        const bool active = c.valid && !(mask & kSolidBit);
+        const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
+        const uint32_t special = L.bb | L.alo | L.ahi;
+        const uint32_t off = active ? cell_off(B, c.x, c.y, c.z) : 0u;
+        T f[Q];
+        if (active) {
+            gather<Q, ST, ODD>(a, B, off, special, f);
+        } else {
+            for (int i = 0; i < Q; ++i) f[i] = T(0);
+        }
+        const Macro<Q, T> m = moments_of<Q, T>(f, cp.F);
+        T P[6];
+        pi_pairs<Q, T>(f, m, P);
+        const T tau_s = tau_smagorinsky<T>(P, m.rho, cp.tau0, cp.smag_k);
+        float x[7];
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const float raw = k < 6 ? P[k] : m.drho;
+            x[k] = (raw - net->mean[k]) * net->istd[k];
+            bad |= !(fabsf(x[k]) <= 8.f);
+        }
+        if (!active)
+            for (int k = 0; k < 7; ++k) x[k] = 0.f;
+        const float o = mlp_forward_wave(net, x);
+        const T tau = (bad || !isfinite(o)) ? tau_s : cp.tau0 + softplus_f(o);
+        const T om = T(1) / tau;
+        const T omm = COLL == 1 ? T(1) / (T(0.5) + cp.magic / (tau - T(0.5))) : om;
+        relax_pairs<Q, T>(f, m, cp.F, om, omm);
+        if (!active) continue;
+        if (L.alo | L.ahi) {
+            const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
+                if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
+            });
+        }
+        const uint32_t boff = off * (uint32_t)sizeof(ST);
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (!ODD) {
+                Codec<ST>::st(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
+            } else {
+                const Alt<ST> p = alt_out<ST, i>(a, B);
+                Codec<ST>::st(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
+            }
+        });
     }
 }
 
@@ -663,6 +781,60 @@ __global__ __launch_bounds__(kWG) void moments_kernel(const MomArgs ma)
             }
             __syncthreads();
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Box filter for LES training data: averages over factor^3 fine cells of
+// rho, u (Guo velocity) and the products u_a u_b, one thread per coarse cell,
+// fixed summation order.  Single-block handles; out[10][Nc] =
+// (rho, ux, uy, uz, uxux, uyuy, uzuz, uxuy, uxuz, uyuz).
+// ---------------------------------------------------------------------------
+template <int Q, typename ST, bool SWAPPED>
+__global__ __launch_bounds__(kWG) void filter_kernel(const SweepArgs a, int fac, double *out)
+{
+    const DevBlock B = a.blocks[0];
+    const int ncx = B.n[0] / fac, ncy = B.n[1] / fac, ncz = B.n[2] / fac;
+    const int64_t Nc = (int64_t)ncx * ncy * ncz;
+    const double inv = 1.0 / ((double)fac * fac * fac);
+    for (int64_t c = (int64_t)blockIdx.x * kWG + threadIdx.x; c < Nc; c += (int64_t)gridDim.x * kWG) {
+        const int X = (int)(c % ncx), Y = (int)((c / ncx) % ncy), Z = (int)(c / ((int64_t)ncx * ncy));
+        double acc[10];
+        for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+        for (int dz = 0; dz < fac; ++dz)
+            for (int dy = 0; dy < fac; ++dy)
+                for (int dx = 0; dx < fac; ++dx) {
+                    const int x = X * fac + dx, y = Y * fac + dy, z = Z * fac + dz;
+                    uint32_t mask = 0;
+                    if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)z * B.mplane + y * B.mpitch + x];
+                    if (mask & kSolidBit) continue;
+                    const Links<Q> L = classify<Q>(mask, B, x, y, z, a);
+                    typename Codec<ST>::T f[Q];
+                    gather<Q, ST, SWAPPED>(a, B, cell_off(B, x, y, z), L.bb | L.alo | L.ahi, f);
+                    double drho = 0, j[3] = {0, 0, 0};
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        const double v = (double)f[i];
+                        drho += v;
+                        if constexpr (cx(i) != 0) j[0] += cx(i) * v;
+                        if constexpr (cy(i) != 0) j[1] += cy(i) * v;
+                        if constexpr (cz(i) != 0) j[2] += cz(i) * v;
+                    });
+                    const double rho = 1.0 + drho;
+                    double u[3];
+                    for (int k = 0; k < 3; ++k) u[k] = (j[k] + 0.5 * a.force[k]) / rho;
+                    acc[0] += rho;
+                    acc[1] += u[0];
+                    acc[2] += u[1];
+                    acc[3] += u[2];
+                    acc[4] += u[0] * u[0];
+                    acc[5] += u[1] * u[1];
+                    acc[6] += u[2] * u[2];
+                    acc[7] += u[0] * u[1];
+                    acc[8] += u[0] * u[2];
+                    acc[9] += u[1] * u[2];
+                }
+        for (int k = 0; k < 10; ++k) out[k * Nc + c] = acc[k] * inv;
     }
 }
 
@@ -779,9 +951,28 @@ static hipError_t sweep_q(bool odd, const SweepArgs &a, int grid, hipStream_t st
     return hipGetLastError();
 }
 
+template <int COLL>
+static hipError_t sweep_mlp_q(bool odd, const SweepArgs &a, int grid, hipStream_t st)
+{
+    if constexpr (std::is_same<WLB_STORAGE, double>::value) {
+        return hipErrorNotSupported;
+    } else {
+        if (odd)
+            hipLaunchKernelGGL((sweep_mlp_kernel<COLL, WLB_STORAGE, true>), dim3(grid), dim3(kWG), 0, st, a);
+        else
+            hipLaunchKernelGGL((sweep_mlp_kernel<COLL, WLB_STORAGE, false>), dim3(grid), dim3(kWG), 0, st, a);
+        return hipGetLastError();
+    }
+}
+
 template <int Q>
 static hipError_t sweep_c(int coll, bool odd, const SweepArgs &a, int grid, hipStream_t st)
 {
+    if (a.closure == 2) {
+        if (Q != 19) return hipErrorNotSupported;
+        return coll == 0 ? sweep_mlp_q<0>(odd, a, grid, st)
+                         : (coll == 1 ? sweep_mlp_q<1>(odd, a, grid, st) : hipErrorNotSupported);
+    }
     switch (coll) {
     case 0: return sweep_q<Q, 0>(odd, a, grid, st);
     case 1: return sweep_q<Q, 1>(odd, a, grid, st);
@@ -842,6 +1033,26 @@ hipError_t WLB_CAT(pdfs_, WLB_SUFFIX)(int q, const SweepArgs &a, double *buf, in
 {
     return q == 19 ? pdfs_q<19>(a, buf, z0, z1, to_device, swapped, grid, st)
                    : pdfs_q<27>(a, buf, z0, z1, to_device, swapped, grid, st);
+}
+
+hipError_t WLB_CAT(filter_, WLB_SUFFIX)(int q, const SweepArgs &a, int fac, double *out, int64_t ncoarse,
+                                        bool swapped, hipStream_t st)
+{
+    int64_t g = (ncoarse + kWG - 1) / kWG;
+    if (g > 16384) g = 16384;
+    if (g < 1) g = 1;
+    if (q == 19) {
+        if (swapped)
+            hipLaunchKernelGGL((filter_kernel<19, WLB_STORAGE, true>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
+        else
+            hipLaunchKernelGGL((filter_kernel<19, WLB_STORAGE, false>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
+    } else {
+        if (swapped)
+            hipLaunchKernelGGL((filter_kernel<27, WLB_STORAGE, true>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
+        else
+            hipLaunchKernelGGL((filter_kernel<27, WLB_STORAGE, false>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
+    }
+    return hipGetLastError();
 }
 
 hipError_t WLB_CAT(exchange_, WLB_SUFFIX)(void *arena, const DevBlock *blocks, const uint32_t *masks,

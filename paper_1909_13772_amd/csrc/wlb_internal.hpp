@@ -62,7 +62,7 @@ struct SweepArgs {
     const DevBlock *blocks;
     const int4 *tiles;
     const uint32_t *masks;
-    const float *mlp;
+    const void *mlp;  // MlpDev of the learned closure (closure == 2)
     int32_t ntiles;
     int32_t dom[3];
     int32_t periodic;      // bit a set: axis a wraps
@@ -98,15 +98,30 @@ struct MomArgs {
     hipError_t pdfs_##S(int q, const SweepArgs &a, double *buf, int z0, int z1, bool to_device, bool swapped, \
                         int grid, hipStream_t st);                                                            \
     hipError_t exchange_##S(void *arena, const DevBlock *blocks, const uint32_t *masks, const XItem *items,   \
-                            int nitems, hipStream_t st);
+                            int nitems, hipStream_t st);                                                      \
+    hipError_t filter_##S(int q, const SweepArgs &a, int fac, double *out, int64_t ncoarse, bool swapped,       \
+                          hipStream_t st);
 WLB_DECLARE_LAUNCHERS(f64)
 WLB_DECLARE_LAUNCHERS(f32)
 WLB_DECLARE_LAUNCHERS(f16)
 WLB_DECLARE_LAUNCHERS(bf16)
 
+// Learned closure (mlp_train.hip).
+hipError_t launch_mlp_forward(const void *net, const float *raw, int64_t n, float *out, int32_t *flag, hipStream_t st);
+size_t mlp_grad_workspace_bytes(int64_t n);
+hipError_t launch_mlp_grad(const float *P, const float *raw, const float *target, int64_t n, float inv_scale,
+                           float *grad, float *loss, float *work, hipStream_t st);
+hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, int64_t step, float lr, float b1, float b2,
+                           float eps, hipStream_t st);
+// Builds the per-lane device layout of the network from packed float params.
+void mlp_prepare(const float *params, void *mlpdev_host);
+size_t mlp_dev_bytes();
+
 // Storage-independent kernels (misc.hip).
 hipError_t launch_masks(const SweepArgs &a, const uint8_t *solid, int q, int grid, hipStream_t st);
 hipError_t launch_reduce_totals(const double *partials, int n, double *out8, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+hipError_t launch_les_targets(const double *filt, const int32_t nc[3], double tau0, float *raw, float *target,
+                              hipStream_t st);
 
 }  // namespace wlb

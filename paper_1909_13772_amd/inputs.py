@@ -197,3 +197,56 @@ def mlp_params(seed, mean=None, inv_std=None, out_bias=0.0, scale=1.0):
     w3 = rng.uniform(-1, 1, H) * np.sqrt(6.0 / (H + 1)) * scale
     P = np.concatenate([mean, inv_std, W1.ravel(), b1, W2.ravel(), b2, w3, [out_bias]])
     return P.astype(np.float32)
+
+
+def turbulence_bandlimited(n, seed, u_rms=0.05, k0=4.0, kmax=20):
+    """Decaying-turbulence initial velocity as a band-limited Fourier series.
+
+    Integer wavevectors with |k_a| <= kmax, random phases (PCG64 seeded with
+    ``seed``), solenoidal projection, shell-wise amplitudes so the shell
+    energy follows E(k) ~ k^4 exp(-2 (k/k0)^2) (negligible beyond kmax = 20
+    for k0 = 4), Hermitian symmetry, evaluated on an n^3 grid by separable
+    real DFTs (matrix products).  The same seed gives samples of the same
+    continuous field at every resolution, so a fine and a coarse run start
+    from one flow.  Scaled so the per-component rms velocity is ``u_rms`` on
+    the sampled grid.  Returns rho (ones) and u with shape (3, n, n, n).
+    """
+    rng = np.random.default_rng(seed)
+    K = 2 * kmax + 1
+    ks = np.arange(-kmax, kmax + 1)
+    kz, ky, kx = np.meshgrid(ks, ks, ks, indexing="ij")
+    k2 = kx * kx + ky * ky + kz * kz
+    uh = rng.standard_normal((3, K, K, K)) + 1j * rng.standard_normal((3, K, K, K))
+    # Hermitian symmetry: u(-k) = conj(u(k))
+    uh = 0.5 * (uh + np.conj(uh[:, ::-1, ::-1, ::-1]))
+    kdotu = kx * uh[0] + ky * uh[1] + kz * uh[2]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        inv = np.where(k2 > 0, 1.0 / k2, 0.0)
+    uh[0] -= kx * kdotu * inv
+    uh[1] -= ky * kdotu * inv
+    uh[2] -= kz * kdotu * inv
+    kmag = np.sqrt(k2)
+    shell = np.rint(kmag).astype(np.int64)
+    valid = (k2 > 0) & (kmag <= kmax)
+    e_mode = 0.5 * (np.abs(uh[0]) ** 2 + np.abs(uh[1]) ** 2 + np.abs(uh[2]) ** 2)
+    nsh = int(shell.max()) + 1
+    e_shell = np.bincount(shell[valid], weights=e_mode[valid], minlength=nsh)
+    kk = np.arange(nsh, dtype=np.float64)
+    e_target = kk ** 4 * np.exp(-2.0 * (kk / k0) ** 2)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        gain = np.where(e_shell > 0, np.sqrt(e_target / e_shell), 0.0)
+    uh = uh * np.where(valid, gain[shell], 0.0)[None]
+    x = np.arange(n)
+    E = np.exp(2j * np.pi * np.outer(ks, x) / n)  # (K, n): e^{i k x}
+    u = np.empty((3, n, n, n))
+    for a in range(3):
+        # sum over kx: (kz, ky, kx) x (kx, X) -> (kz, ky, X)
+        A = uh[a].reshape(K * K, K) @ E
+        A = A.reshape(K, K, n)
+        # sum over ky: -> (kz, Y, X)
+        Bm = np.einsum("zyx,yY->zYx", A, E, optimize=True)
+        # sum over kz: -> (Z, Y, X), real part (Hermitian)
+        u[a] = (E.T @ Bm.reshape(K, n * n)).real.reshape(n, n, n)
+    rms = np.sqrt(np.mean(u[0] ** 2 + u[1] ** 2 + u[2] ** 2) / 3.0)
+    u *= u_rms / rms
+    return np.ones((n, n, n)), u

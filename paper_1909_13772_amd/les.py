@@ -1,0 +1,296 @@
+"""Learned relaxation-time closure: training data, training and evaluation.
+
+Pipeline (every numerical step runs in libwlb's kernels; PyTorch only holds
+device buffers and streams):
+
+1. Fine runs: decaying turbulence (band-limited E(k) ~ k^4 exp(-2 (k/4)^2),
+   u_rms = 0.05) on an n_f^3 periodic box, D3Q19 SRT, FP32 storage,
+   tau_f = 0.53.  Every `snap` fine steps the state is box-filtered by
+   `factor` (wlb_box_filter) and turned into training pairs (wlb_les_targets):
+   features = (Pi_neq the coarse run would see, rho - 1), target = 3 nu_t of
+   the sub-grid stress.
+2. Training: minibatches of the pairs, loss on the standardised target,
+   gradients by wlb_mlp_grad and Adam by wlb_mlp_adam (FP32 master weights).
+3. Evaluation: coarse LES (n_f / factor)^3, tau0 = 1/2 + 3 nu_f / factor
+   (acoustic scaling: dx and dt grow by `factor`, velocities unchanged),
+   from the filtered fine initial state, with no model, Smagorinsky (C_s 0.1)
+   and the MLP, against the filtered fine run of the same seed: kinetic
+   energy history and the final shell spectrum.
+
+The paper lets relaxation rates vary per cell, read from a field or set by a
+turbulence model (Sec. 5.1.1); the learned closure is this project's
+addition and its gain is measured, not assumed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import inputs
+
+TAU_F = 0.53
+U_RMS = 0.05
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def coarse_tau(factor, tau_f=TAU_F):
+    nu_f = (tau_f - 0.5) / 3.0
+    return 0.5 + 3.0 * nu_f / factor
+
+
+def shell_spectrum(u):
+    """E(k) over integer shells of a periodic (3, n, n, n) velocity field."""
+    n = u.shape[-1]
+    uh = np.fft.rfftn(u, axes=(1, 2, 3)) / n ** 3
+    e = 0.5 * (np.abs(uh) ** 2).sum(0)
+    e[..., 1:-1 if n % 2 == 0 else None] *= 2.0  # rfft half-spectrum weights
+    f = np.fft.fftfreq(n) * n
+    fr = np.fft.rfftfreq(n) * n
+    k = np.sqrt(f[:, None, None] ** 2 + f[None, :, None] ** 2 + fr[None, None, :] ** 2)
+    sh = np.rint(k).astype(np.int64)
+    return np.bincount(sh.ravel(), weights=e.ravel())[: n // 2 + 1]
+
+
+def filtered_energy(filt_dev):
+    """Kinetic energy sum rho |u|^2 / 2 of box-filtered fields (host FP64)."""
+    F = filt_dev.cpu().numpy().reshape(10, -1)
+    return float(0.5 * np.sum(F[0] * (F[1] ** 2 + F[2] ** 2 + F[3] ** 2)))
+
+
+class FineRun:
+    """One fine decaying-turbulence run producing filtered snapshots."""
+
+    def __init__(self, wlb, torch, seed, n, factor, storage=None):
+        self.wlb, self.torch = wlb, torch
+        self.n, self.factor = n, factor
+        self.nc = n // factor
+        rho, u = inputs.turbulence_bandlimited(n, seed, u_rms=U_RMS)
+        st = wlb.F32 if storage is None else storage
+        self.B = wlb.Blocks(wlb.single_block((n, n, n)), (n, n, n), (1, 1, 1), stencil=19, storage=st)
+        self.B.init(wlb.SRT, wlb.make_params(tau=TAU_F), rho, u)
+        del rho, u
+        self.filt = torch.empty(10 * self.nc ** 3, dtype=torch.float64, device="cuda")
+
+    def filtered(self):
+        self.wlb.wlb_box_filter(self.B.h, self.factor, self.filt.data_ptr())
+        return self.filt
+
+    def pairs(self, tau0):
+        nc3 = self.nc ** 3
+        raw = self.torch.empty(nc3 * 7, dtype=self.torch.float32, device="cuda")
+        tgt = self.torch.empty(nc3, dtype=self.torch.float32, device="cuda")
+        self.wlb.wlb_les_targets(self.filtered().data_ptr(), (self.nc,) * 3, tau0, raw.data_ptr(), tgt.data_ptr(),
+                                 self.B.stream.cuda_stream)
+        self.B.synchronize()
+        return raw.view(nc3, 7), tgt
+
+    def coarse_state(self):
+        """Filtered density and velocity (host) of the current state."""
+        F = self.filtered().cpu().numpy().reshape(10, self.nc, self.nc, self.nc)
+        return F[0].copy(), F[1:4].copy()
+
+    def close(self):
+        self.B.close()
+
+
+def generate(wlb, torch, seeds, n, factor, steps, snap, per_snap, rng_seed=0):
+    """Training pairs (host float32) from fine runs: raw (M, 7), target (M,),
+    and for each seed the filtered kinetic energy / final spectrum."""
+    tau0 = coarse_tau(factor)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(rng_seed)
+    raws, tgts, refs = [], [], {}
+    for seed in seeds:
+        t0 = time.time()
+        fr = FineRun(wlb, torch, seed, n, factor)
+        energy = []
+        for s in range(0, steps + 1, snap):
+            if s > 0:
+                fr.B.step(snap)
+            raw, tgt = fr.pairs(tau0)
+            energy.append(filtered_energy(fr.filt))
+            idx = torch.randint(0, tgt.numel(), (per_snap,), device="cuda", generator=g)
+            raws.append(raw[idx].cpu().numpy())
+            tgts.append(tgt[idx].cpu().numpy())
+        rho_c, u_c = fr.coarse_state()
+        refs[seed] = {"energy": energy, "spectrum": shell_spectrum(u_c).tolist()}
+        fr.close()
+        _log(f"[les] fine seed {seed}: {steps} steps at {n}^3 in {time.time() - t0:.1f} s")
+    return np.concatenate(raws), np.concatenate(tgts), refs
+
+
+def standardisation(raw):
+    mean = raw.mean(0).astype(np.float64)
+    std = raw.std(0).astype(np.float64)
+    return mean, 1.0 / np.maximum(std, 1e-30)
+
+
+def train(wlb, torch, raw, tgt, vraw, vtgt, epochs=20, batch=65536, lr=2e-3, seed=0):
+    """Adam on the library's gradient kernel; returns (params, history)."""
+    mean, istd = standardisation(raw)
+    P = inputs.mlp_params(seed, mean=mean, inv_std=istd, out_bias=-4.0)
+    inv_scale = 1.0 / max(float(np.std(tgt)), 1e-30)
+    dev = torch.device("cuda")
+    s = torch.cuda.Stream()
+    hist = []
+    with torch.cuda.stream(s):  # every buffer op and library call on one stream
+        Pd = torch.tensor(P, device=dev)
+        m = torch.zeros_like(Pd)
+        v = torch.zeros_like(Pd)
+        g = torch.empty_like(Pd)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        R = torch.tensor(raw, device=dev)
+        T = torch.tensor(tgt, device=dev)
+        VR = torch.tensor(vraw, device=dev)
+        VT = torch.tensor(vtgt, device=dev)
+        wsb = wlb.wlb_mlp_grad_workspace(max(batch, VT.numel()))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        step = 0
+        for ep in range(epochs):
+            perm = torch.randperm(T.numel(), device=dev, generator=gen)
+            tot, nb = 0.0, 0
+            for b0 in range(0, T.numel() - batch + 1, batch):
+                idx = perm[b0:b0 + batch]
+                rb = R[idx].contiguous()
+                tb = T[idx].contiguous()
+                wlb.wlb_mlp_grad(Pd.data_ptr(), rb.data_ptr(), tb.data_ptr(), batch, inv_scale, g.data_ptr(),
+                                 loss.data_ptr(), ws.data_ptr(), wsb, s.cuda_stream)
+                step += 1
+                wlb.wlb_mlp_adam(Pd.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, 0.9, 0.999, 1e-8,
+                                 s.cuda_stream)
+                tot += float(loss.item())
+                nb += 1
+            wlb.wlb_mlp_grad(Pd.data_ptr(), VR.data_ptr(), VT.data_ptr(), VT.numel(), inv_scale, g.data_ptr(),
+                             loss.data_ptr(), ws.data_ptr(), wsb, s.cuda_stream)
+            hist.append({"epoch": ep, "train_loss": tot / max(nb, 1), "val_loss": float(loss.item())})
+            _log(f"[les] epoch {ep}: train {tot / max(nb, 1):.4f} val {float(loss.item()):.4f}")
+        s.synchronize()
+    return Pd.cpu().numpy(), hist, inv_scale
+
+
+def les_run(wlb, torch, rho_c, u_c, closure, params, steps, every, tau0):
+    """Coarse LES from (rho_c, u_c); returns kinetic energy every `every`
+    steps and the final spectrum (None on divergence)."""
+    n = rho_c.shape[-1]
+    kw = dict(tau=tau0, closure=closure, cs_smag=0.1, health_every=every, health_umax=0.5)
+    if closure == wlb.CLOSURE_MLP:
+        kw["mlp"] = params
+    B = wlb.Blocks(wlb.single_block((n, n, n)), (n, n, n), (1, 1, 1), stencil=19, storage=wlb.F32)
+    try:
+        B.init(wlb.SRT, wlb.make_params(**kw), rho_c, u_c)
+        energy = [float(B.moments(fields=False)[2][4])]
+        t0 = time.time()
+        for _ in range(0, steps, every):
+            try:
+                B.step(every)
+            except wlb.WlbError as e:
+                if e.code == wlb.WLB_ERR_DIVERGED:
+                    return {"energy": energy, "spectrum": None, "diverged": True}
+                raise
+            energy.append(float(B.moments(fields=False)[2][4]))
+        B.synchronize()
+        dt = time.time() - t0
+        _, uu, _ = B.moments()
+        return {"energy": energy, "spectrum": shell_spectrum(uu).tolist(), "diverged": False,
+                "mlups": n ** 3 * steps / dt / 1e6}
+    finally:
+        B.close()
+
+
+def compare(run, ref, kmax):
+    e = np.asarray(run["energy"])
+    er = np.asarray(ref["energy"])[: len(e)]
+    out = {"energy_rel_err_max": float(np.max(np.abs(e - er) / er)),
+           "energy_rel_err_final": float(abs(e[-1] - er[-1]) / er[-1]) if len(e) == len(ref["energy"]) else None}
+    if run.get("spectrum") is not None:
+        s = np.asarray(run["spectrum"])[1:kmax + 1]
+        sr = np.asarray(ref["spectrum"])[1:kmax + 1]
+        ok = sr > 1e-30
+        out["spectrum_rel_err_max"] = float(np.max(np.abs(s[ok] - sr[ok]) / sr[ok]))
+    return out
+
+
+def evaluate(wlb, torch, seed, params, n, factor, steps, snap):
+    """A-posteriori comparison on a held-out seed."""
+    tau0 = coarse_tau(factor)
+    fr = FineRun(wlb, torch, seed, n, factor)
+    rho_c, u_c = fr.coarse_state()
+    energy = []
+    for s in range(0, steps + 1, snap):
+        if s > 0:
+            fr.B.step(snap)
+        energy.append(filtered_energy(fr.filtered()))
+    _, u_end = fr.coarse_state()
+    fr.close()
+    ref = {"energy": energy, "spectrum": shell_spectrum(u_end).tolist()}
+    csteps, cevery = steps // factor, snap // factor
+    nc = n // factor
+    res = {}
+    for name, cl in (("none", wlb.CLOSURE_NONE), ("smagorinsky", wlb.CLOSURE_SMAG), ("mlp", wlb.CLOSURE_MLP)):
+        r = les_run(wlb, torch, rho_c, u_c, cl, params, csteps, cevery, tau0)
+        res[name] = {"diverged": r["diverged"], "mlups": r.get("mlups"), **compare(r, ref, nc // 2)}
+        _log(f"[les] a-posteriori {name}: {res[name]}")
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--factor", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=8000)
+    ap.add_argument("--snap", type=int, default=400)
+    ap.add_argument("--per-snap", type=int, default=4096)
+    ap.add_argument("--train-seeds", type=str, default="0-15")
+    ap.add_argument("--val-seeds", type=str, default="16-19")
+    ap.add_argument("--test-seed", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--out", type=str, default="gpurun_out/les")
+    ap.add_argument("--phase", choices=["all", "data", "train"], default="all")
+    ap.add_argument("--data", type=str, default=None, help="npz of previously generated pairs")
+    args = ap.parse_args(argv)
+
+    def seeds(spec):
+        if "-" in spec:
+            a, b = spec.split("-")
+            return list(range(int(a), int(b) + 1))
+        return [int(x) for x in spec.split(",") if x]
+
+    import torch
+
+    from . import wlb
+    os.makedirs(args.out, exist_ok=True)
+    tr, va = seeds(args.train_seeds), seeds(args.val_seeds)
+    if args.phase in ("all", "data"):
+        raw, tgt, _ = generate(wlb, torch, tr, args.n, args.factor, args.steps, args.snap, args.per_snap, 1)
+        vraw, vtgt, _ = generate(wlb, torch, va, args.n, args.factor, args.steps, args.snap, args.per_snap, 2)
+        np.savez(os.path.join(args.out, "pairs.npz"), raw=raw, tgt=tgt, vraw=vraw, vtgt=vtgt)
+        if args.phase == "data":
+            return 0
+    else:
+        d = np.load(args.data)
+        raw, tgt, vraw, vtgt = d["raw"], d["tgt"], d["vraw"], d["vtgt"]
+    P, hist, inv_scale = train(wlb, torch, raw, tgt, vraw, vtgt, epochs=args.epochs)
+    np.save(os.path.join(args.out, "mlp_params.npy"), P)
+    res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap)
+    summary = {"n_fine": args.n, "factor": args.factor, "steps_fine": args.steps, "train_seeds": tr,
+               "val_seeds": va, "test_seed": args.test_seed, "pairs": int(tgt.size), "history": hist,
+               "inv_scale": inv_scale, "a_posteriori": res}
+    with open(os.path.join(args.out, "summary.json"), "w") as fh:
+        json.dump(summary, fh, indent=1)
+    _log(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwlb.so")
+# WLB_LIBRARY may point at another build of the same library (e.g. a debug build).
+LIB_PATH = os.environ.get("WLB_LIBRARY") or os.path.join(_HERE, "libwlb.so")
 
 WLB_OK = 0
 WLB_ERR_ARG = -1
@@ -112,6 +113,12 @@ _sig = {
     "wlb_blocks_destroy": (None, [_h]),
     "wlb_last_error": (C.c_char_p, []),
     "wlb_copy_probe": (C.c_int, [_vp, _vp, C.c_size_t, C.c_int32, _vp, C.POINTER(C.c_double)]),
+    "wlb_box_filter": (C.c_int, [_h, C.c_int32, _vp]),
+    "wlb_les_targets": (C.c_int, [_vp, C.POINTER(C.c_int32), C.c_double, _vp, _vp, _vp]),
+    "wlb_mlp_forward": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
+    "wlb_mlp_grad_workspace": (C.c_size_t, [C.c_int64]),
+    "wlb_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "wlb_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, _vp]),
 }
 for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
@@ -215,6 +222,39 @@ def wlb_copy_probe(dst_ptr, src_ptr, nbytes, reps, stream_ptr):
     ms = C.c_double(0.0)
     _check(_lib.wlb_copy_probe(_vp(dst_ptr), _vp(src_ptr), nbytes, reps, _vp(stream_ptr), C.byref(ms)))
     return ms.value
+
+
+MLP_WORKSPACE = 4096
+
+
+def wlb_box_filter(h, factor, out_ptr):
+    _check(_lib.wlb_box_filter(h, int(factor), _vp(out_ptr)))
+
+
+def wlb_les_targets(filt_ptr, nc, tau0, raw_ptr, target_ptr, stream_ptr):
+    n = (C.c_int32 * 3)(*nc)
+    _check(_lib.wlb_les_targets(_vp(filt_ptr), n, float(tau0), _vp(raw_ptr), _vp(target_ptr), _vp(stream_ptr)))
+
+
+def wlb_mlp_forward(params, workspace_ptr, raw_ptr, n, out_ptr, fallback_ptr, stream_ptr):
+    p = np.ascontiguousarray(params, np.float32)
+    assert p.size == MLP_NPARAM
+    _check(_lib.wlb_mlp_forward(p.ctypes.data_as(_vp), _vp(workspace_ptr), _vp(raw_ptr), int(n), _vp(out_ptr),
+                                _vp(fallback_ptr), _vp(stream_ptr)))
+
+
+def wlb_mlp_grad_workspace(n):
+    return _lib.wlb_mlp_grad_workspace(int(n))
+
+
+def wlb_mlp_grad(params_ptr, raw_ptr, target_ptr, n, inv_scale, grad_ptr, loss_ptr, ws_ptr, ws_bytes, stream_ptr):
+    _check(_lib.wlb_mlp_grad(_vp(params_ptr), _vp(raw_ptr), _vp(target_ptr), int(n), float(inv_scale), _vp(grad_ptr),
+                             _vp(loss_ptr), _vp(ws_ptr), int(ws_bytes), _vp(stream_ptr)))
+
+
+def wlb_mlp_adam(params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, stream_ptr):
+    _check(_lib.wlb_mlp_adam(_vp(params_ptr), _vp(grad_ptr), _vp(m_ptr), _vp(v_ptr), int(step), float(lr),
+                             float(beta1), float(beta2), float(eps), _vp(stream_ptr)))
 
 
 # --- convenience wrapper ---------------------------------------------------

@@ -1,0 +1,60 @@
+"""GPU parity of the LES training-data kernels (box filter, targets) against
+the numpy FP64 oracle in oracle/les.py."""
+import numpy as np
+import pytest
+
+from gpu_util import inputs, say
+
+pytestmark = pytest.mark.gpu
+
+wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("steps", [0, 3])
+def test_box_filter_and_targets_match_oracle(steps):
+    from oracle import les
+    say(f"case les filter steps{steps}")
+    n, f = 32, 4
+    shape = (n, n, n)
+    rho, u = inputs.turbulence_bandlimited(n, seed=2, u_rms=0.03)
+    B = wlb.Blocks(wlb.single_block(shape), shape, (1, 1, 1), stencil=19, storage=wlb.F64)
+    B.init(wlb.SRT, wlb.make_params(tau=0.6), rho, u)
+    B.step(steps)
+    r, uu, _ = B.moments()
+    nc = n // f
+    out = torch.empty(10 * nc ** 3, dtype=torch.float64, device="cuda")
+    wlb.wlb_box_filter(B.h, f, out.data_ptr())
+    F_gpu = out.cpu().numpy().reshape(10, nc, nc, nc)
+    F_orc = les.box_filter(r, uu, f)
+    err = np.abs(F_gpu - F_orc).max()
+    say(f"filter max abs err {err:.3e}")
+    assert err < 1e-14
+    raw = torch.empty(nc ** 3 * 7, dtype=torch.float32, device="cuda")
+    tgt = torch.empty(nc ** 3, dtype=torch.float32, device="cuda")
+    wlb.wlb_les_targets(out.data_ptr(), (nc, nc, nc), 0.5075, raw.data_ptr(), tgt.data_ptr(), B.stream.cuda_stream)
+    B.synchronize()
+    raw_o, tgt_o = les.les_targets(F_gpu, 0.5075)
+    rg = raw.cpu().numpy().reshape(-1, 7).astype(np.float64)
+    tg = tgt.cpu().numpy().astype(np.float64)
+    assert np.abs(tg - tgt_o).max() <= 1e-6 * max(tgt_o.max(), 1e-12)
+    assert np.abs(rg - raw_o).max() <= 1e-6 * np.abs(raw_o).max()
+    B.close()
+
+
+def test_learned_closure_pipeline_small():
+    """Fine runs -> filtered pairs -> training with the library's kernels ->
+    a-posteriori LES, at toy size (the full-size numbers are a separate run)."""
+    from paper_1909_13772_amd import les
+    say("case les pipeline small")
+    n, f = 32, 4
+    raw, tgt, refs = les.generate(wlb, torch, [0, 1], n, f, 40, 20, 256, rng_seed=1)
+    vraw, vtgt, _ = les.generate(wlb, torch, [2], n, f, 40, 20, 256, rng_seed=2)
+    assert raw.shape == (2 * 3 * 256, 7) and np.all(np.isfinite(raw)) and np.all(tgt >= 0)
+    P, hist, _ = les.train(wlb, torch, raw, tgt, vraw, vtgt, epochs=3, batch=256)
+    assert np.all(np.isfinite(P)) and len(hist) == 3
+    assert hist[-1]["train_loss"] <= hist[0]["train_loss"] * 1.5
+    res = les.evaluate(wlb, torch, 3, P, n, f, 40, 20)
+    for name in ("none", "smagorinsky", "mlp"):
+        assert name in res
+    assert not res["smagorinsky"]["diverged"]

@@ -1,0 +1,195 @@
+"""GPU parity of the learned closure: the matrix-core forward pass, the
+training gradient and Adam kernels, and the sweep with the MLP closure,
+against the FP64 CPU oracle (same bf16 rounding points).
+
+Where FP32 decides a bf16 rounding (x, h1, h2) the two sides may round a
+value that sits on a rounding boundary differently; such flips are rare and
+bounded, so the forward check requires 1e-5 relative agreement on at least
+99.5 % of the samples and 1e-2 absolute on all of them."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import gpu_run, inputs, oracle_params, oracle_run, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
+torch = pytest.importorskip("torch")
+
+
+def _raw_samples(n, seed):
+    rng = np.random.default_rng(seed)
+    raw = np.empty((n, 7))
+    raw[:, :6] = rng.normal(0, 2e-3, (n, 6))
+    raw[:, 6] = rng.normal(0, 5e-3, n)
+    return raw
+
+
+def _params(seed):
+    mean = np.zeros(7)
+    istd = np.array([400.0] * 6 + [150.0])
+    return inputs.mlp_params(seed, mean=mean, inv_std=istd, out_bias=-2.0)
+
+
+def _gpu_forward(P, raw):
+    n = raw.shape[0]
+    dev = torch.device("cuda")
+    r = torch.tensor(raw.astype(np.float32), device=dev)
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    flag = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = torch.empty(wlb.MLP_WORKSPACE, dtype=torch.uint8, device=dev)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    wlb.wlb_mlp_forward(P, ws.data_ptr(), r.data_ptr(), n, out.data_ptr(), flag.data_ptr(), s.cuda_stream)
+    return out.cpu().numpy().astype(np.float64), flag.cpu().numpy()
+
+
+def test_forward_matches_oracle():
+    say("case mlp forward")
+    n = 65536 + 37  # ragged tail
+    raw = _raw_samples(n, 1)
+    P = _params(3)
+    o_gpu, f_gpu = _gpu_forward(P, raw)
+    # the oracle sees exactly the FP32 values the GPU read
+    o_orc, f_orc = O.mlp_forward(P.astype(np.float64), raw.astype(np.float32).astype(np.float64))
+    err = np.abs(o_gpu - o_orc)
+    rel = err / np.maximum(1.0, np.abs(o_orc))
+    frac = float((rel > 1e-5).mean())
+    say(f"mlp forward: max abs {err.max():.3e}, frac beyond 1e-5 {frac:.4f}")
+    assert frac < 5e-3
+    assert err.max() < 1e-2
+    assert (f_gpu != f_orc).mean() < 1e-3
+
+
+def test_forward_zero_last_layer_and_structured_weights():
+    say("case mlp special")
+    raw = _raw_samples(1000, 2)
+    P = _params(4)
+    P[O.MLP_OFF_W3:O.MLP_OFF_W3 + 32] = 0
+    P[O.MLP_OFF_B3] = 0
+    o, _ = _gpu_forward(P, raw)
+    assert np.all(o == 0.0)
+    # single path: o = gelu(gelu(bf16(x_5))) rounded like the oracle
+    Q = np.zeros(O.MLP_NPARAM, np.float32)
+    Q[O.MLP_OFF_ISTD:O.MLP_OFF_ISTD + 7] = 1.0
+    Q[O.MLP_OFF_W1 + 3 * 7 + 5] = 1.0
+    Q[O.MLP_OFF_W2 + 0 * 32 + 3] = 1.0
+    Q[O.MLP_OFF_W3 + 0] = 1.0
+    raw2 = np.zeros((64, 7))
+    raw2[:, 5] = np.linspace(-3, 3, 64)
+    o2, _ = _gpu_forward(Q, raw2)
+    ex, _ = O.mlp_forward(Q.astype(np.float64), raw2)
+    assert np.abs(o2 - ex).max() < 1e-6
+
+
+def test_gradient_matches_oracle():
+    say("case mlp grad")
+    n = 8192 + 5
+    raw = _raw_samples(n, 5)
+    P = _params(6)
+    rng = np.random.default_rng(7)
+    t = rng.uniform(0.0, 0.05, n)
+    inv_scale = 40.0
+    dev = torch.device("cuda")
+    Pd = torch.tensor(P, device=dev)
+    rd = torch.tensor(raw.astype(np.float32), device=dev)
+    td = torch.tensor(t.astype(np.float32), device=dev)
+    g = torch.empty(wlb.MLP_NPARAM, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    wsb = wlb.wlb_mlp_grad_workspace(n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    wlb.wlb_mlp_grad(Pd.data_ptr(), rd.data_ptr(), td.data_ptr(), n, inv_scale, g.data_ptr(), loss.data_ptr(),
+                     ws.data_ptr(), wsb, s.cuda_stream)
+    s.synchronize()
+    g_gpu = g.cpu().numpy().astype(np.float64)
+    g_orc, L_orc = O.mlp_backward(P.astype(np.float64), raw.astype(np.float32).astype(np.float64),
+                                  t.astype(np.float32).astype(np.float64), inv_scale)
+    L_gpu = float(loss.cpu()[0])
+    say(f"mlp grad: loss gpu {L_gpu:.6e} oracle {L_orc:.6e}")
+    assert abs(L_gpu - L_orc) <= 1e-4 * abs(L_orc)
+    for name, a, b in (("W1", O.MLP_OFF_W1, O.MLP_OFF_B1), ("b1", O.MLP_OFF_B1, O.MLP_OFF_W2),
+                       ("W2", O.MLP_OFF_W2, O.MLP_OFF_B2), ("b2", O.MLP_OFF_B2, O.MLP_OFF_W3),
+                       ("w3", O.MLP_OFF_W3, O.MLP_OFF_B3), ("b3", O.MLP_OFF_B3, O.MLP_NPARAM)):
+        e = np.linalg.norm(g_gpu[a:b] - g_orc[a:b]) / max(np.linalg.norm(g_orc[a:b]), 1e-30)
+        say(f"  grad {name}: normwise rel {e:.3e}")
+        assert e <= 1e-4, name
+    assert np.all(g_gpu[:14] == 0)
+
+
+def test_adam_step():
+    say("case mlp adam")
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(8)
+    P = rng.normal(0, 1, wlb.MLP_NPARAM).astype(np.float32)
+    G = rng.normal(0, 1e-3, wlb.MLP_NPARAM).astype(np.float32)
+    Pd, Gd = torch.tensor(P, device=dev), torch.tensor(G, device=dev)
+    m = torch.zeros(wlb.MLP_NPARAM, device=dev)
+    v = torch.zeros(wlb.MLP_NPARAM, device=dev)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for step in (1, 2):
+        wlb.wlb_mlp_adam(Pd.data_ptr(), Gd.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, b1, b2, eps,
+                         s.cuda_stream)
+    s.synchronize()
+    # two identical gradients: m_hat = v_hat^(1/2) * sign(g) -> each step moves lr * g / (|g| + eps')
+    mh = G.astype(np.float64)
+    expected = P.astype(np.float64).copy()
+    for step in (1, 2):
+        expected[14:] -= lr * mh[14:] / (np.abs(mh[14:]) + eps)
+    got = Pd.cpu().numpy().astype(np.float64)
+    assert np.abs(got[:14] - P[:14]).max() == 0
+    assert np.abs(got - expected).max() < 1e-6
+
+
+@pytest.mark.parametrize("coll,storage", [(0, 1), (1, 1), (0, 2)])
+def test_sweep_with_mlp_closure_vs_oracle(coll, storage):
+    say(f"case sweep mlp coll{coll} storage{storage}")
+    shape = (20, 16, 12)
+    rho, u = inputs.random_state(shape, seed=12, umag=0.04)
+    P = _params(9)
+    tau0 = 0.51
+    p = wlb.make_params(tau=tau0, magic=3 / 16, closure=wlb.CLOSURE_MLP, cs_smag=0.1, mlp=P)
+    d, r, uu, tot, B = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 19, storage, coll, p, rho, u, steps=9)
+    B.close()
+    op = oracle_params(19, coll, tau0, 3 / 16, (1, 1, 1), closure=2, cs_smag=0.1)
+    op.mlp = P.astype(np.float64)
+    do, ro, uo, to = oracle_run(op, shape, rho, u, None, 9)
+    eu = rel_l2(uu.reshape(3, -1), uo)
+    say(f"sweep mlp coll{coll} storage{storage}: u rel L2 {eu:.3e}")
+    assert eu <= (1e-5 if storage == 1 else 1e-3)
+    assert abs(tot[0] - np.prod(shape)) < 1e-6 * np.prod(shape)
+
+
+def test_sweep_mlp_out_of_range_falls_back_to_smagorinsky():
+    """With huge input scales every feature is out of range, so the MLP sweep
+    must reproduce the Smagorinsky sweep (same FP32 arithmetic)."""
+    say("case sweep mlp fallback")
+    shape = (16, 12, 10)
+    rho, u = inputs.random_state(shape, seed=13, umag=0.04)
+    P = _params(10)
+    P[O.MLP_OFF_ISTD:O.MLP_OFF_ISTD + 7] = 1e9
+    p_mlp = wlb.make_params(tau=0.52, closure=wlb.CLOSURE_MLP, cs_smag=0.1, mlp=P)
+    p_smg = wlb.make_params(tau=0.52, closure=wlb.CLOSURE_SMAG, cs_smag=0.1)
+    d1, *_, B = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 19, 1, 0, p_mlp, rho, u, steps=6)
+    B.close()
+    d2, *_, B = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 19, 1, 0, p_smg, rho, u, steps=6)
+    B.close()
+    assert np.abs(d1 - d2).max() <= 1e-6 * np.abs(d2).max()
+
+
+def test_mlp_closure_rejected_where_unsupported():
+    shape = (8, 8, 8)
+    rho, u = inputs.uniform_state(shape)
+    P = _params(1)
+    B = wlb.Blocks(wlb.single_block(shape), shape, (1, 1, 1), stencil=27, storage=wlb.F32)
+    with pytest.raises(wlb.WlbError) as e:
+        B.init(wlb.SRT, wlb.make_params(closure=wlb.CLOSURE_MLP, mlp=P), rho, u)
+    assert e.value.code == wlb.WLB_ERR_UNSUPPORTED
+    B.close()
+    assert math.isfinite(0.0)

@@ -579,3 +579,59 @@ def test_totals_match_fsum():
     assert abs(tot[1] - ex_px) <= 2 * np.spacing(abs(ex_px))
     assert tot[6] == 9 * 8 * 7
     assert tot[5] == np.sqrt((uu ** 2).sum(0)).max()
+
+
+# --------------------------------------------------------------------------
+# LES training data (box filter, targets)
+# --------------------------------------------------------------------------
+def test_box_filter_exact_on_blockwise_constant_and_linear_fields():
+    from oracle import les
+    rng = np.random.default_rng(40)
+    blocks = rng.normal(size=(2, 3, 4))
+    rho = np.kron(blocks, np.ones((4, 4, 4)))  # constant on 4^3 blocks
+    u = np.stack([rho, 2 * rho, -rho])
+    F = les.box_filter(rho, u, 4)
+    assert np.allclose(F[0], blocks, atol=1e-14, rtol=0)
+    assert np.allclose(F[4], blocks ** 2, atol=1e-13, rtol=0)
+    assert np.allclose(F[7], 2 * blocks ** 2, atol=1e-13, rtol=0)
+    # linear field -> value at the block centre; mean preserved
+    z, y, x = np.meshgrid(np.arange(8), np.arange(12), np.arange(16), indexing="ij")
+    lin = 0.5 * x - 0.25 * y + 2 * z
+    Fl = les.box_filter(lin, np.stack([lin, lin, lin]), 4)
+    zc, yc, xc = np.meshgrid(np.arange(2) * 4 + 1.5, np.arange(3) * 4 + 1.5, np.arange(4) * 4 + 1.5, indexing="ij")
+    assert np.allclose(Fl[0], 0.5 * xc - 0.25 * yc + 2 * zc, atol=1e-13, rtol=0)
+    assert abs(Fl[0].mean() - lin.mean()) < 1e-13
+
+
+def test_les_targets_recover_an_eddy_viscosity():
+    """Filtered fields whose sub-grid stress is exactly -2 nu0 S give nu_t = nu0;
+    the opposite sign (backscatter) is clamped to 0."""
+    from oracle import les
+    n = 16
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    k = 2 * np.pi / n
+    ub = np.stack([0.01 * np.sin(k * y), 0.02 * np.cos(k * z), 0.015 * np.sin(k * x)])
+    S = les.strain(ub)
+    nu0 = 0.003
+    tau = -2 * nu0 * S  # deviatoric already (trace of S is 0 here)
+    filt = np.empty((10, n, n, n))
+    filt[0] = 1.0 + 0.001 * np.cos(k * x)
+    filt[1:4] = ub
+    filt[4] = tau[0] + ub[0] ** 2
+    filt[5] = tau[1] + ub[1] ** 2
+    filt[6] = tau[2] + ub[2] ** 2
+    filt[7] = tau[3] + ub[0] * ub[1]
+    filt[8] = tau[4] + ub[0] * ub[2]
+    filt[9] = tau[5] + ub[1] * ub[2]
+    raw, target = les.les_targets(filt, 0.51)
+    SS = (S[:3] ** 2).sum(0) + 2 * (S[3:] ** 2).sum(0)
+    ok = SS.reshape(-1) > 1e-12
+    assert np.allclose(target[ok], 3 * nu0, rtol=1e-9, atol=0)
+    assert np.allclose(raw[:, 6], filt[0].reshape(-1) - 1.0)
+    assert np.allclose(raw[ok, 3], (-(2 / 3) * filt[0] * (0.51 + 3 * nu0) * S[3]).reshape(-1)[ok], rtol=1e-9)
+    filt2 = filt.copy()
+    filt2[4:10] = 2 * filt[4:10] - filt2[4:10] + 0  # unchanged base
+    for kk, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        filt2[4 + kk] = -tau[kk] + ub[a] * ub[b]
+    _, t2 = les.les_targets(filt2, 0.51)
+    assert np.all(t2 == 0.0)
