@@ -54,6 +54,17 @@ def load_traffic(storage_name: str):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
+def closure_weights(inputs):
+    """Trained closure weights if present (paper_1909_13772_amd/mlp_closure.npy),
+    else seeded weights of the same shape (the sweep's cost does not depend on
+    the values)."""
+    import numpy as np
+    path = os.path.join(ROOT, "paper_1909_13772_amd", "mlp_closure.npy")
+    if os.path.exists(path):
+        return np.load(path).astype(np.float32)
+    return inputs.mlp_params(0, inv_std=[300.0] * 6 + [100.0], out_bias=-4.0)
+
+
 def poiseuille_series(H, nu, g, T, s):
     u = g * s * (H - s) / (2 * nu)
     for n in range(1, 4000, 2):
@@ -68,8 +79,11 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
 
     shape = (N, N, N)
     rho, u = inputs.uniform_state(shape)
+    mlp = None
+    if closure == 2:
+        mlp = closure_weights(inputs)
     p = wlb.make_params(tau=TAU, magic=MAGIC, force=(FX, 0.0, 0.0), closure=closure, cs_smag=0.1 if closure else 0.0,
-                        autotune=1 if autotune else 0)
+                        mlp=mlp, autotune=1 if autotune else 0)
     B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=19, storage=storage)
     try:
         B.init(wlb.TRT, p, rho, u)
@@ -160,6 +174,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
+    ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures"], default="channel",
+                    help="channel = the headline configuration; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (blocks would shard over GPUs "
@@ -171,6 +187,16 @@ def main():
 
     torch.cuda.set_device(0)
     print(f"[bench] device {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    if args.workload != "channel":
+        from paper_1909_13772_amd import workloads
+        if args.workload == "porous":
+            r = workloads.porous(wlb, steps=args.steps, warmup=args.warmup, autotune=not args.no_autotune)
+        elif args.workload == "turbulence":
+            r = workloads.turbulence_precision(wlb, steps=args.steps)
+        else:
+            r = workloads.closure_cost(wlb, steps=args.steps, warmup=args.warmup)
+        print(json.dumps(r))
+        return
     res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True, autotune=not args.no_autotune)
     head = summarize(res, wlb.F64, args.steps, 8)
     print(f"[bench] f64: {head['mlups']:.0f} MLUPS, sweep {head['sweep_ms']:.3f} ms, "
@@ -178,7 +204,7 @@ def main():
     variants = {}
     if not args.no_variants:
         for name, st, eb, cl in (("f32", wlb.F32, 4, 0), ("f16dev", wlb.F16DEV, 2, 0), ("bf16dev", wlb.BF16DEV, 2, 0),
-                                 ("f32_smagorinsky", wlb.F32, 4, 1)):
+                                 ("f32_smagorinsky", wlb.F32, 4, 1), ("f32_mlp_closure", wlb.F32, 4, 2)):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune)
             sm = summarize(r, st, args.variant_steps, eb)
             variants[name] = {"mlups": round(sm["mlups"], 1), "roofline_frac": round(sm["frac"], 4),

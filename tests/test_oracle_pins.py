@@ -635,3 +635,31 @@ def test_les_targets_recover_an_eddy_viscosity():
         filt2[4 + kk] = -tau[kk] + ub[a] * ub[b]
     _, t2 = les.les_targets(filt2, 0.51)
     assert np.all(t2 == 0.0)
+
+
+@pytest.mark.parametrize("case", ["channel", "porous"])
+def test_light_cone_crops_reproduce_full_domain(case):
+    """Locality of the update: a region's state after s steps computed from a
+    crop of the initial data (margin s) equals the full-domain result.  This
+    is what the full-size GPU parity tests rely on."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from gpu_util import crop_compare
+    if case == "channel":
+        dom, per, q, coll = (20, 16, 12), (1, 0, 1), 19, O.TRT
+        solid = None
+        p = O.Params(q=q, collision=coll, tau=0.7, force=(1e-5, 0, 0), periodic=per)
+        regions = [(0, 0, 0), (12, 10, 7), (19, 12, 11)]
+    else:
+        dom, per, q, coll = (24, 14, 16), (0, 1, 1), 27, O.MRT
+        solid, _, _ = inputs.spheres(dom, seed=4, rmin=1.5, rmax=3.0, solid_fraction=0.2, clear_x=2)
+        p = O.Params(q=q, collision=coll, tau=0.7, periodic=per, pressure_axis=0, rho_in=1.001, rho_out=0.999)
+        regions = [(0, 3, 5), (20, 10, 12), (9, 0, 15)]
+    rho, u = inputs.random_state(dom, seed=5)
+    s, m = 3, 4
+    d = O.run(p, dom, O.init(q, dom, rho, u, solid), s, solid)
+    r, uu, _ = O.moments(q, p.force, dom, d, solid)
+    r = r.reshape(dom[2], dom[1], dom[0])
+    uu = uu.reshape(3, dom[2], dom[1], dom[0])
+    eu, er = crop_compare(p, dom, per, rho, u, solid, r, uu, regions, m, s)
+    assert eu < 1e-14 and er < 1e-15
