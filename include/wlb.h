@@ -183,6 +183,7 @@ typedef struct {
     int32_t n_tiles;
     int32_t tile[3];        /* tile shape target in use (x, y, z) */
     int32_t grid;           /* workgroups per sweep launch (0 = one per tile) */
+    int32_t lds_staging;    /* 1: the odd sweep stages x-shifted populations in LDS */
     int32_t n_xchg_items;   /* exchange work items per exchange */
     int64_t xchg_elems;     /* populations copied per exchange */
     size_t arena_bytes;
@@ -193,6 +194,12 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *out);
 /* Use tile shape (tx, ty, tz) (tx*ty*tz <= 256) and `grid` workgroups per
  * sweep launch (0 = one workgroup per tile) from now on. */
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid);
+
+/* Stage (1) or not (0, default) the odd sweep's x-shifted populations in LDS
+ * row buffers so that all its global accesses are row-aligned; staging is
+ * skipped automatically when the buffers exceed 64 KiB per workgroup.  The
+ * autotuner tries both. */
+int wlb_set_lds_staging(wlb_blocks_t h, int32_t on);
 
 /* Use (1) or bypass (0) the captured HIP graph in wlb_lbm_step. */
 int wlb_set_graph(wlb_blocks_t h, int32_t on);

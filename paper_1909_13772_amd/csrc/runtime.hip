@@ -79,6 +79,7 @@ struct wlb_blocks {
     int last_sweep = -1;  // parity of the last sweep (-1: none since init / set)
     int shape[3] = {0, 0, 0};
     int grid = 0;
+    bool lds_stage = false;  // odd sweep stages x-shifted populations in LDS (autotuner candidate)
     bool use_graph = true;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -141,6 +142,19 @@ size_t count_tiles(const wlb_blocks *h, int tx, int ty, int tz)
     return t.size();
 }
 
+// Row-buffer length of the LDS-staged odd sweep: the largest tile's rows
+// times (segment length + 2 halo cells).  Staging is used only when it fits
+// in 64 KiB of LDS per workgroup.
+void update_lds_stride(wlb_blocks *h)
+{
+    int stride = 0;
+    for (const TileHost &t : h->tiles) stride = std::max(stride, t.ey * t.ez * (t.ex + 2));
+    const int nsh = h->q == 19 ? 10 : 18;
+    const size_t bytes = ((2 * (size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
+    h->args.lds_stride = (h->lds_stage && bytes <= 65536) ? stride : 0;
+    h->graph_valid = false;
+}
+
 int upload_tiles(wlb_blocks *h)
 {
     std::vector<int4> packed(h->tiles.size());
@@ -152,6 +166,7 @@ int upload_tiles(wlb_blocks *h)
                           hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->args.ntiles = (int)h->tiles.size();
+    update_lds_stride(h);
     return WLB_OK;
 }
 
@@ -442,24 +457,31 @@ int autotune(wlb_blocks *h)
     int bs[3] = {0, 0, 0}, bg = 0;
     // repetitions scaled so each candidate runs ~ 2e8 cell updates at most
     int reps = (int)std::max<int64_t>(2, std::min<int64_t>(10, 200000000 / std::max<int64_t>(1, 2 * h->ncells)));
-    for (const auto &s : kShapes) {
-        if (count_tiles(h, s[0], s[1], s[2]) > h->tile_cap) continue;
-        for (int g : kGrids) {
-            int rc = set_tiles(h, s[0], s[1], s[2], g);
-            if (rc) return rc;
-            if (g > 0 && g >= (int)h->tiles.size()) continue;  // same as one workgroup per tile
-            float ms = 0.f;
-            rc = time_pairs(h, reps, &ms);
-            if (rc) return rc;
-            if (ms < best) {
-                best = ms;
-                bs[0] = s[0];
-                bs[1] = s[1];
-                bs[2] = s[2];
-                bg = g;
+    bool blds = false;
+    for (int lds = 0; lds <= 1; ++lds) {
+        h->lds_stage = lds != 0;
+        for (const auto &s : kShapes) {
+            if (count_tiles(h, s[0], s[1], s[2]) > h->tile_cap) continue;
+            for (int g : kGrids) {
+                int rc = set_tiles(h, s[0], s[1], s[2], g);
+                if (rc) return rc;
+                if (g > 0 && g >= (int)h->tiles.size()) continue;  // same as one workgroup per tile
+                if (lds && h->args.lds_stride == 0) continue;      // staging does not fit: covered by lds = 0
+                float ms = 0.f;
+                rc = time_pairs(h, reps, &ms);
+                if (rc) return rc;
+                if (ms < best) {
+                    best = ms;
+                    bs[0] = s[0];
+                    bs[1] = s[1];
+                    bs[2] = s[2];
+                    bg = g;
+                    blds = lds != 0;
+                }
             }
         }
     }
+    h->lds_stage = blds;
     return set_tiles(h, bs[0], bs[1], bs[2], bg);
 }
 
@@ -969,6 +991,7 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
     o->n_tiles = (int32_t)h->tiles.size();
     for (int a = 0; a < 3; ++a) o->tile[a] = h->shape[a];
     o->grid = h->grid;
+    o->lds_staging = h->args.lds_stride > 0 ? 1 : 0;
     o->n_xchg_items = (int32_t)h->pull.size();
     o->xchg_elems = h->xchg_elems;
     o->arena_bytes = h->arena_bytes;
@@ -983,6 +1006,14 @@ int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t gr
     if (tx != 0 && (ty < 1 || tz < 1 || (int64_t)tx * ty * tz > kWG))
         return fail(WLB_ERR_ARG, "tile shape must have at most %d cells", kWG);
     return set_tiles(h, tx, ty, tz, grid);
+}
+
+int wlb_set_lds_staging(wlb_blocks_t h, int32_t on)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    h->lds_stage = on != 0;
+    update_lds_stride(h);
+    return WLB_OK;
 }
 
 int wlb_set_graph(wlb_blocks_t h, int32_t on)

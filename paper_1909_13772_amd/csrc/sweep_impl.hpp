@@ -41,62 +41,83 @@ struct bf16_t {
 
 template <typename ST> struct Codec;
 
-// Populations are streamed once per sweep with no reuse inside the sweep:
-// WLB_NT selects non-temporal loads / stores for them.
-#ifndef WLB_NT
-#define WLB_NT 0
-#endif
-template <typename V>
+// Populations are streamed once per sweep with no reuse inside the sweep, so
+// aligned (full-line) accesses carry the non-temporal hint; accesses that
+// share cache lines with neighbouring waves (single-lane halo accesses) use
+// ordinary loads / stores.  Measured on MI355X: non-temporal aligned
+// accesses raise the sweep from ~4.7 to ~5.4 TB/s (FP64).
+template <bool NT, typename V>
 __device__ __forceinline__ V mem_ld(const V *p)
 {
-    if constexpr (WLB_NT) return __builtin_nontemporal_load(p);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
     return *p;
 }
-template <typename V>
+template <bool NT, typename V>
 __device__ __forceinline__ void mem_st(V *p, V v)
 {
-    if constexpr (WLB_NT)
+    if constexpr (NT)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
 }
 
+// Codec: Raw is the storage bit pattern (used by LDS staging and the
+// exchange); dec / enc convert between Raw and the compute type T (enc
+// rounds to nearest even).
 template <> struct Codec<double> {
     using T = double;
     using Raw = uint64_t;
-    static __device__ __forceinline__ double ld(const double *p) { return mem_ld(p); }
-    static __device__ __forceinline__ void st(double *p, double v) { mem_st(p, v); }
+    static __device__ __forceinline__ T dec(Raw r) { return __longlong_as_double((long long)r); }
+    static __device__ __forceinline__ Raw enc(T v) { return (Raw)__double_as_longlong(v); }
 };
 template <> struct Codec<float> {
     using T = float;
     using Raw = uint32_t;
-    static __device__ __forceinline__ float ld(const float *p) { return mem_ld(p); }
-    static __device__ __forceinline__ void st(float *p, float v) { mem_st(p, v); }
+    static __device__ __forceinline__ T dec(Raw r) { return __uint_as_float(r); }
+    static __device__ __forceinline__ Raw enc(T v) { return __float_as_uint(v); }
 };
 template <> struct Codec<_Float16> {
     using T = float;
     using Raw = uint16_t;
-    static __device__ __forceinline__ float ld(const _Float16 *p) { return (float)mem_ld(p); }
-    static __device__ __forceinline__ void st(_Float16 *p, float v) { mem_st(p, (_Float16)v); }
+    static __device__ __forceinline__ T dec(Raw r) { return (float)__builtin_bit_cast(_Float16, r); }
+    static __device__ __forceinline__ Raw enc(T v) { return __builtin_bit_cast(Raw, (_Float16)v); }
 };
 template <> struct Codec<bf16_t> {
     using T = float;
     using Raw = uint16_t;
-    static __device__ __forceinline__ float ld(const bf16_t *p)
+    static __device__ __forceinline__ T dec(Raw r) { return __uint_as_float((uint32_t)r << 16); }
+    static __device__ __forceinline__ Raw enc(T v)
     {
-        return __uint_as_float((uint32_t)mem_ld(&p->v) << 16);
-    }
-    static __device__ __forceinline__ void st(bf16_t *p, float v)
-    {
-        uint32_t u = __float_as_uint(v);
-        uint32_t r;
+        const uint32_t u = __float_as_uint(v);
         if ((u & 0x7f800000u) == 0x7f800000u)
-            r = (u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u);  // inf stays inf, nan stays (quiet) nan
-        else
-            r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // round to nearest even
-        mem_st(&p->v, (uint16_t)r);
+            return (Raw)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));  // inf stays inf, nan stays (quiet) nan
+        return (Raw)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);           // round to nearest even
     }
 };
+
+// Typed loads / stores through the codec.
+template <typename ST, bool NT = true>
+__device__ __forceinline__ typename Codec<ST>::T ldv(const ST *p)
+{
+    using Raw = typename Codec<ST>::Raw;
+    return Codec<ST>::dec(mem_ld<NT>(reinterpret_cast<const Raw *>(p)));
+}
+template <typename ST, bool NT = true>
+__device__ __forceinline__ void stv(ST *p, typename Codec<ST>::T v)
+{
+    using Raw = typename Codec<ST>::Raw;
+    mem_st<NT>(reinterpret_cast<Raw *>(p), Codec<ST>::enc(v));
+}
+template <typename ST, bool NT = true>
+__device__ __forceinline__ typename Codec<ST>::Raw ldraw(const ST *p)
+{
+    return mem_ld<NT>(reinterpret_cast<const typename Codec<ST>::Raw *>(p));
+}
+template <typename ST, bool NT = true>
+__device__ __forceinline__ void straw(ST *p, typename Codec<ST>::Raw r)
+{
+    mem_st<NT>(reinterpret_cast<typename Codec<ST>::Raw *>(p), r);
+}
 
 // ---------------------------------------------------------------------------
 // Collision (deviation form).  In: d[Q] = f - w.  Out: post-collision d[Q],
@@ -557,10 +578,10 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (!SWAPPED) {
-            f[i] = Codec<ST>::ld(at<ST>(slot_base<ST>(a, B, i), boff));
+            f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
         } else {
             const Alt<ST> p = alt_in<ST, i>(a, B);
-            f[i] = Codec<ST>::ld(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+            f[i] = ldv<ST>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
         }
     });
 }
@@ -592,13 +613,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         if constexpr (!ODD) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                f[i] = Codec<ST>::ld(at<ST>(slot_base<ST>(a, B, i), boff));
+                f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
             });
         } else {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const Alt<ST> p = alt_in<ST, i>(a, B);
-                f[i] = Codec<ST>::ld(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+                f[i] = ldv<ST>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
             });
         }
         const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
@@ -613,15 +634,152 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         if constexpr (!ODD) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                Codec<ST>::st(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
+                stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
             });
         } else {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const Alt<ST> p = alt_out<ST, i>(a, B);
-                Codec<ST>::st(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
+                stv<ST>(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
             });
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Odd sweep with LDS staging of the x-shifted populations.  A tile is a box
+// of whole x-row segments.  Populations whose link has c_x != 0 would be read
+// from x - c_x and written to x + c_x, one element off the row alignment;
+// instead every lane moves its own aligned element between memory and an
+// LDS row buffer (with one halo element per row segment), and the one-cell
+// shift happens in LDS.  Every global access of the sweep is then a
+// full-line aligned access.  Targets outside the row segment (one lane per
+// row and population) are stored directly.
+// ---------------------------------------------------------------------------
+template <int Q>
+__host__ __device__ constexpr int n_xshift()
+{
+    int n = 0;
+    for (int i = 0; i < Q; ++i) n += cx(i) != 0;
+    return n;
+}
+__host__ __device__ constexpr int xshift_index(int i)
+{
+    int n = 0;
+    for (int j = 0; j < i; ++j) n += cx(j) != 0;
+    return n;
+}
+
+template <int Q, int COLL, typename ST>
+__global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
+{
+    using T = typename Codec<ST>::T;
+    using Raw = typename Codec<ST>::Raw;
+    constexpr int NSH = n_xshift<Q>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int stride = a.lds_stride;
+    Raw *lin = reinterpret_cast<Raw *>(smem);  // incoming row buffers [NSH][stride]
+    Raw *lout = lin + (size_t)NSH * stride;     // outgoing row buffers [NSH][stride]
+    uint32_t *info = reinterpret_cast<uint32_t *>(smem + ((2 * (size_t)NSH * stride * sizeof(Raw) + 15) & ~15ull));
+    const CollParams<T> cp = coll_params<T>(a);
+    const int l = threadIdx.x;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int4 tv = a.tiles[t];
+        const int ex = tv.y >> 16, ey = tv.z >> 16, ez = tv.w >> 16;
+        const bool valid = l < ex * ey * ez;
+        const int lx = l % ex, lr = l / ex;  // lr = row within the tile = ly + ey * lz
+        const int x = (tv.y & 0xffff) + lx, y = (tv.z & 0xffff) + lr % ey, z = (tv.w & 0xffff) + lr / ey;
+        const DevBlock B = a.blocks[tv.x];
+        uint32_t mask = 0;
+        if (valid && B.mask >= 0) mask = a.masks[B.mask + (int64_t)z * B.mplane + y * B.mpitch + x];
+        const bool active = valid && !(mask & kSolidBit);
+        const Links<Q> L = classify<Q>(mask, B, x, y, z, a);
+        const uint32_t special = L.bb | L.alo | L.ahi;
+        const uint32_t boff = valid ? cell_off(B, x, y, z) * (uint32_t)sizeof(ST) : 0u;
+        const int rb = lr * (ex + 2) + lx + 1;  // this lane's slot in its row buffer
+        info[l] = active ? special : 0xffffffffu;
+        // ---- all loads in one phase: the shifted incoming populations are
+        // staged (aligned element at (x, y - c_y, z - c_z) of slot opp(i),
+        // plus the halo one cell outside the segment), the others are read
+        // directly (they are row-aligned either way).
+        T f[Q];
+        if (valid) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (cx(i) != 0) {
+                    constexpr int k = xshift_index(i);
+                    const char *base = slot_base<ST>(a, B, opp(i)) -
+                                       (int64_t)(cy(i) * B.pitch + cz(i) * B.plane) * (int64_t)sizeof(ST);
+                    lin[k * stride + rb] = ldraw<ST>(at<ST>(base, boff));
+                    if (cx(i) == 1 && lx == 0) lin[k * stride + rb - 1] = ldraw<ST, false>(at<ST>(base, boff - sizeof(ST)));
+                    if (cx(i) == -1 && lx == ex - 1)
+                        lin[k * stride + rb + 1] = ldraw<ST, false>(at<ST>(base, boff + sizeof(ST)));
+                    if ((special >> opp(i)) & 1u) f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
+                } else {
+                    const Alt<ST> p = alt_in<ST, i>(a, B);
+                    f[i] = ldv<ST>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+                }
+            });
+        }
+        __syncthreads();
+        if (active) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (cx(i) != 0) {
+                    constexpr int k = xshift_index(i);
+                    if (!((special >> opp(i)) & 1u)) f[i] = Codec<ST>::dec(lin[k * stride + rb - cx(i)]);
+                }
+            });
+            const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
+            if (L.alo | L.ahi) {
+                const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
+                    if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
+                });
+            }
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const bool sp = (special >> i) & 1u;
+                if constexpr (cx(i) == 0) {
+                    const Alt<ST> p = alt_out<ST, i>(a, B);
+                    stv<ST>(at<ST>(p.base, boff + (sp ? p.add_sp : p.add_reg)), f[i]);
+                } else {
+                    constexpr int k = xshift_index(i);
+                    if (sp) {
+                        stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
+                    } else if ((cx(i) == 1 && lx == ex - 1) || (cx(i) == -1 && lx == 0)) {
+                        // target outside the row segment: direct store
+                        stv<ST, false>(at<ST>(slot_base<ST>(a, B, i),
+                                              boff + (uint32_t)(link_delta<i>(B) * (int)sizeof(ST))),
+                                       f[i]);
+                    } else {
+                        lout[k * stride + rb + cx(i)] = Codec<ST>::enc(f[i]);
+                    }
+                }
+            });
+        }
+        __syncthreads();
+        // ---- aligned stores of the shifted outgoing populations: this lane
+        // stores the element at (x, y + c_y, z + c_z) of slot i when its
+        // writer, the lane at x - c_x of the same row, is a fluid cell of the
+        // segment with a regular link i.
+        if (valid) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (cx(i) != 0) {
+                    constexpr int k = xshift_index(i);
+                    const int lw = lx - cx(i);
+                    if (lw >= 0 && lw < ex && !((info[l - cx(i)] >> i) & 1u)) {
+                        const char *base = slot_base<ST>(a, B, i) +
+                                           (int64_t)(cy(i) * B.pitch + cz(i) * B.plane) * (int64_t)sizeof(ST);
+                        straw<ST>(at<ST>(base, boff), lout[k * stride + rb]);
+                    }
+                }
+            });
+        }
+        __syncthreads();  // LDS and info are reused by the next tile
     }
 }
 
@@ -688,10 +846,10 @@ __global__ __launch_bounds__(kWG) void sweep_mlp_kernel(const SweepArgs a)
         sfor<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             if constexpr (!ODD) {
-                Codec<ST>::st(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
+                stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
             } else {
                 const Alt<ST> p = alt_out<ST, i>(a, B);
-                Codec<ST>::st(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
+                stv<ST>(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
             }
         });
     }
@@ -856,7 +1014,7 @@ __global__ __launch_bounds__(kWG) void init_kernel(const SweepArgs a, const doub
         if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
         const uint32_t off = cell_off(B, c.x, c.y, c.z);
         if (mask & kSolidBit) {
-            sfor<Q>([&](auto I) { Codec<ST>::st(at<ST>(slot_base<ST>(a, B, decltype(I)::value), off * sizeof(ST)), T(0)); });
+            sfor<Q>([&](auto I) { stv<ST>(at<ST>(slot_base<ST>(a, B, decltype(I)::value), off * sizeof(ST)), T(0)); });
             continue;
         }
         const int64_t S = (int64_t)(z1 - z0) * a.dom[1] * a.dom[0];
@@ -869,7 +1027,7 @@ __global__ __launch_bounds__(kWG) void init_kernel(const SweepArgs a, const doub
             constexpr int i = decltype(I)::value;
             const double cu = cdot<i>(u);
             const double v = weight<Q, double>(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-            Codec<ST>::st(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)v);
+            stv<ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)v);
         });
     }
 }
@@ -901,7 +1059,7 @@ __global__ __launch_bounds__(kWG) void pdfs_kernel(const SweepArgs a, double *bu
         if constexpr (TO_DEVICE) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                Codec<ST>::st(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)buf[i * S + k]);
+                stv<ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)buf[i * S + k]);
             });
         } else {
             const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
@@ -935,7 +1093,7 @@ __global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBloc
     }
     const Raw *src = arena + S.pop + (int64_t)it.slot * S.slot + cell_off(S, it.s0[0] + rx, it.s0[1] + ry, it.s0[2] + rz);
     Raw *dst = arena + D.pop + (int64_t)it.slot * D.slot + cell_off(D, dx, dy, dz);
-    *dst = *src;
+    mem_st<true>(dst, mem_ld<true>(src));
 }
 
 // ---------------------------------------------------------------------------
@@ -944,6 +1102,12 @@ __global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBloc
 template <int Q, int COLL>
 static hipError_t sweep_q(bool odd, const SweepArgs &a, int grid, hipStream_t st)
 {
+    if (odd && a.lds_stride > 0) {
+        using Raw = typename Codec<WLB_STORAGE>::Raw;
+        const size_t bytes = ((2 * (size_t)n_xshift<Q>() * a.lds_stride * sizeof(Raw) + 15) & ~(size_t)15) + kWG * 4;
+        hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE>), dim3(grid), dim3(kWG), bytes, st, a);
+        return hipGetLastError();
+    }
     if (odd)
         hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, true>), dim3(grid), dim3(kWG), 0, st, a);
     else

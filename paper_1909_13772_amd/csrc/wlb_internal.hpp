@@ -68,7 +68,7 @@ struct SweepArgs {
     int32_t periodic;      // bit a set: axis a wraps
     int32_t pressure_axis; // -1 or axis
     int32_t closure;
-    int32_t pad0;
+    int32_t lds_stride;    // > 0: odd sweep stages x-shifted populations in LDS rows of this many elements
     double omega;          // 1 / tau0
     double omega_minus;    // TRT rate of the antisymmetric part at tau0
     double magic;          // TRT Lambda

@@ -108,7 +108,7 @@ def generate(wlb, torch, seeds, n, factor, steps, snap, per_snap, rng_seed=0):
     tau0 = coarse_tau(factor)
     g = torch.Generator(device="cuda")
     g.manual_seed(rng_seed)
-    raws, tgts, refs = [], [], {}
+    raws, tgts, sids, refs = [], [], [], {}
     for seed in seeds:
         t0 = time.time()
         fr = FineRun(wlb, torch, seed, n, factor)
@@ -121,10 +121,12 @@ def generate(wlb, torch, seeds, n, factor, steps, snap, per_snap, rng_seed=0):
             idx = torch.randint(0, tgt.numel(), (per_snap,), device="cuda", generator=g)
             raws.append(raw[idx].cpu().numpy())
             tgts.append(tgt[idx].cpu().numpy())
+            sids.append(np.full(per_snap, seed, np.int32))
         rho_c, u_c = fr.coarse_state()
         refs[seed] = {"energy": energy, "spectrum": shell_spectrum(u_c).tolist()}
         fr.close()
         _log(f"[les] fine seed {seed}: {steps} steps at {n}^3 in {time.time() - t0:.1f} s")
+    generate.last_seed_ids = np.concatenate(sids)
     return np.concatenate(raws), np.concatenate(tgts), refs
 
 
@@ -250,17 +252,20 @@ def main(argv=None):
     ap.add_argument("--factor", type=int, default=4)
     ap.add_argument("--steps", type=int, default=8000)
     ap.add_argument("--snap", type=int, default=400)
-    ap.add_argument("--per-snap", type=int, default=4096)
+    ap.add_argument("--per-snap", type=int, default=2048)
+    ap.add_argument("--seeds", type=str, default="0-19", help="phase data: seeds to run")
     ap.add_argument("--train-seeds", type=str, default="0-15")
     ap.add_argument("--val-seeds", type=str, default="16-19")
     ap.add_argument("--test-seed", type=int, default=20)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--out", type=str, default="gpurun_out/les")
-    ap.add_argument("--phase", choices=["all", "data", "train"], default="all")
-    ap.add_argument("--data", type=str, default=None, help="npz of previously generated pairs")
+    ap.add_argument("--phase", choices=["data", "train"], default="data")
+    ap.add_argument("--data", type=str, default="", help="phase train: comma-separated npz files of pairs")
     args = ap.parse_args(argv)
 
     def seeds(spec):
+        if not spec:
+            return []
         if "-" in spec:
             a, b = spec.split("-")
             return list(range(int(a), int(b) + 1))
@@ -270,22 +275,25 @@ def main(argv=None):
 
     from . import wlb
     os.makedirs(args.out, exist_ok=True)
+    if args.phase == "data":
+        sd = seeds(args.seeds)
+        raw, tgt, _ = generate(wlb, torch, sd, args.n, args.factor, args.steps, args.snap, args.per_snap, sd[0] + 1)
+        name = f"pairs_{sd[0]}-{sd[-1]}.npz"
+        np.savez_compressed(os.path.join(args.out, name), raw=raw, tgt=tgt, seed=generate.last_seed_ids)
+        _log(f"[les] wrote {name}: {tgt.size} pairs")
+        return 0
+    parts = [np.load(f) for f in args.data.split(",") if f]
+    raw = np.concatenate([p["raw"] for p in parts])
+    tgt = np.concatenate([p["tgt"] for p in parts])
+    sid = np.concatenate([p["seed"] for p in parts])
     tr, va = seeds(args.train_seeds), seeds(args.val_seeds)
-    if args.phase in ("all", "data"):
-        raw, tgt, _ = generate(wlb, torch, tr, args.n, args.factor, args.steps, args.snap, args.per_snap, 1)
-        vraw, vtgt, _ = generate(wlb, torch, va, args.n, args.factor, args.steps, args.snap, args.per_snap, 2)
-        np.savez(os.path.join(args.out, "pairs.npz"), raw=raw, tgt=tgt, vraw=vraw, vtgt=vtgt)
-        if args.phase == "data":
-            return 0
-    else:
-        d = np.load(args.data)
-        raw, tgt, vraw, vtgt = d["raw"], d["tgt"], d["vraw"], d["vtgt"]
-    P, hist, inv_scale = train(wlb, torch, raw, tgt, vraw, vtgt, epochs=args.epochs)
+    mt, mv = np.isin(sid, tr), np.isin(sid, va)
+    P, hist, inv_scale = train(wlb, torch, raw[mt], tgt[mt], raw[mv], tgt[mv], epochs=args.epochs)
     np.save(os.path.join(args.out, "mlp_params.npy"), P)
     res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap)
-    summary = {"n_fine": args.n, "factor": args.factor, "steps_fine": args.steps, "train_seeds": tr,
-               "val_seeds": va, "test_seed": args.test_seed, "pairs": int(tgt.size), "history": hist,
-               "inv_scale": inv_scale, "a_posteriori": res}
+    summary = {"n_fine": args.n, "factor": args.factor, "steps_fine": args.steps, "snap": args.snap,
+               "train_seeds": tr, "val_seeds": va, "test_seed": args.test_seed, "train_pairs": int(mt.sum()),
+               "val_pairs": int(mv.sum()), "history": hist, "inv_scale": inv_scale, "a_posteriori": res}
     with open(os.path.join(args.out, "summary.json"), "w") as fh:
         json.dump(summary, fh, indent=1)
     _log(json.dumps(res))

@@ -73,6 +73,7 @@ class wlb_info_t(C.Structure):
         ("n_tiles", C.c_int32),
         ("tile", C.c_int32 * 3),
         ("grid", C.c_int32),
+        ("lds_staging", C.c_int32),
         ("n_xchg_items", C.c_int32),
         ("xchg_elems", C.c_int64),
         ("arena_bytes", C.c_size_t),
@@ -108,6 +109,7 @@ _sig = {
     "wlb_info": (C.c_int, [_h, C.POINTER(wlb_info_t)]),
     "wlb_set_tiles": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "wlb_set_graph": (C.c_int, [_h, C.c_int32]),
+    "wlb_set_lds_staging": (C.c_int, [_h, C.c_int32]),
     "wlb_set_kernel_timing": (C.c_int, [_h, C.c_int32]),
     "wlb_kernel_times": (C.c_int, [_h, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "wlb_blocks_destroy": (None, [_h]),
@@ -197,6 +199,10 @@ def wlb_info(h) -> wlb_info_t:
 
 def wlb_set_tiles(h, tx, ty, tz, grid):
     _check(_lib.wlb_set_tiles(h, tx, ty, tz, grid))
+
+
+def wlb_set_lds_staging(h, on):
+    _check(_lib.wlb_set_lds_staging(h, 1 if on else 0))
 
 
 def wlb_set_graph(h, on):
@@ -351,6 +357,9 @@ class Blocks:
 
     def set_tiles(self, tx, ty, tz, grid=0):
         wlb_set_tiles(self.h, tx, ty, tz, grid)
+
+    def set_lds_staging(self, on):
+        wlb_set_lds_staging(self.h, on)
 
     def set_graph(self, on):
         wlb_set_graph(self.h, on)

@@ -14,7 +14,7 @@ def say(msg):
 
 
 def gpu_run(blocks, domain, periodic, q, storage, coll, params, rho, u, solid=None, steps=0, tiles=None,
-            graph=True, mode="step"):
+            graph=True, mode="step", lds=True):
     """Returns (d[q][N] natural-layout deviations, rho, u, totals, Blocks)."""
     from paper_1909_13772_amd import wlb
     B = wlb.Blocks(blocks, domain, periodic, stencil=q, storage=storage)
@@ -22,6 +22,7 @@ def gpu_run(blocks, domain, periodic, q, storage, coll, params, rho, u, solid=No
     if tiles is not None:
         B.set_tiles(*tiles)
     B.set_graph(graph)
+    B.set_lds_staging(lds)
     if mode == "step":
         B.step(steps)
     else:

