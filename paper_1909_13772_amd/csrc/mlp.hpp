@@ -31,7 +31,7 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 // Device copy of the network, laid out per lane (built by mlp_prepare).
-struct MlpDev {
+struct alignas(16) MlpDev {
     float mean[8];
     float istd[8];
     uint16_t w1[64][8];     // layer-1 A operand per lane (bf16 bits)
@@ -42,19 +42,57 @@ struct MlpDev {
     float b3;
     float pad[7];
 };
+static_assert(sizeof(MlpDev) % 16 == 0, "MlpDev is copied in 16-byte units");
+
+// Copy the network into a workgroup's shared memory (all threads call it).
+__device__ __forceinline__ void mlp_stage(MlpDev *dst, const void *src)
+{
+    const uint4 *s = static_cast<const uint4 *>(src);
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+    for (int k = threadIdx.x; k < (int)(sizeof(MlpDev) / 16); k += blockDim.x) d[k] = s[k];
+    __syncthreads();
+}
 
 // Host-side: hidden unit held in result register j by lane half h.
 __host__ __device__ constexpr int mlp_unit(int j, int h) { return 8 * (j / 4) + 4 * h + (j % 4); }
 
 __device__ __forceinline__ uint16_t bf16_bits(float v)
 {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
-    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    // round to nearest even; a NaN keeps its sign and top payload bits and
+    // is made quiet (selects, not branches: the whole wave takes this path)
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t nan = (u >> 16) | 0x40u;
+    return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? nan : rne);
 }
 __device__ __forceinline__ float bf16_round(float v) { return __uint_as_float((uint32_t)bf16_bits(v) << 16); }
 
-__device__ __forceinline__ float gelu_erf(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Standard normal CDF Phi(z) = erfc(-z / sqrt 2) / 2 without branches:
+// erfc(u) for u >= 0 from the Chebyshev-fitted form t exp(-u^2 + P(t)),
+// t = 1 / (1 + u / 2), of Numerical Recipes (2nd ed., Sec. 6.2), whose
+// fractional error is below 1.2e-7 for every u >= 0; Phi(z) = 1 - erfc/2 for
+// z >= 0.  One hardware reciprocal, one exp and a degree-9 polynomial, the
+// same for every lane, where a library erf takes divergent branches.
+__device__ __forceinline__ float norm_cdf(float z)
+{
+    const float u = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, u, 1.0f));  // 1 ulp; the divisor lies in [1, inf)
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    const float half_erfc = 0.5f * t * expf(fmaf(-u, u, p));
+    return z >= 0.f ? 1.0f - half_erfc : half_erfc;
+}
+
+// GELU with the exact Gaussian CDF: z Phi(z).
+__device__ __forceinline__ float gelu_erf(float z) { return z * norm_cdf(z); }
 
 __device__ __forceinline__ bf16x8_t load_bf16x8(const uint16_t *p)
 {
@@ -77,9 +115,66 @@ __device__ __forceinline__ bf16x8_t pack_bf16x8(const float *v)
     return r;
 }
 
+// Sixteen floats from a 16-byte aligned address (four 128-bit reads).
+__device__ __forceinline__ f32x16_t load_f32x16(const float *p)
+{
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+    f32x16_t r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float4 v = q[k];
+        r[4 * k] = v.x;
+        r[4 * k + 1] = v.y;
+        r[4 * k + 2] = v.z;
+        r[4 * k + 3] = v.w;
+    }
+    return r;
+}
+
+// Layers 1-3 for one 32-cell tile: b1op is the layer-1 B operand (the
+// lane's features in its k half, zeros in the other), the result is this
+// lane's half of the output dot product for the tile's cell in its column.
+// The biases enter as the accumulators' initial values.
+__device__ __forceinline__ float mlp_tile(const MlpDev *__restrict__ P, int lane, int h, const bf16x8_t b1op)
+{
+    // An opaque zero in the weight indices keeps these reads inside the
+    // tile loop: hoisted, they would hold ~60 registers for the whole sweep.
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    h += z;
+    f32x16_t c = load_f32x16(P->b1[h]);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf16x8(P->w1[lane]), b1op, c, 0, 0, 0);
+    bf16x8_t g[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            v[t] = gelu_erf(c[8 * q + t]);
+            // evaluate the activations a few at a time: all sixteen in
+            // flight need ~80 registers for their temporaries
+            if (t % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+        g[q] = pack_bf16x8(v);
+    }
+    f32x16_t d = load_f32x16(P->b2[h]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf16x8(P->w2[q][lane]), g[q], d, 0, 0, 0);
+    const f32x16_t w3 = load_f32x16(P->w3[h]);
+    float part = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        part += w3[j] * bf16_round(gelu_erf(d[j]));
+        if (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    return part;
+}
+
 // Wave-collective forward pass: every lane of the wavefront must call it
 // (inactive lanes pass zeros).  x[7] are the standardised features of the
-// lane's own cell.  Returns the network output o for the lane's cell.
+// lane's own cell.  Returns the network output o for the lane's cell.  The
+// two 32-cell tiles are evaluated one after the other so their
+// accumulators share registers.
 __device__ __forceinline__ float mlp_forward_wave(const MlpDev *__restrict__ P, const float x[7])
 {
     const int lane = threadIdx.x & 63;
@@ -92,33 +187,10 @@ __device__ __forceinline__ float mlp_forward_wave(const MlpDev *__restrict__ P, 
     bf16x8_t zero;
 #pragma unroll
     for (int t = 0; t < 8; ++t) zero[t] = __builtin_bit_cast(__bf16, (uint16_t)0);
-    const bf16x8_t bA = h ? zero : xb;
-    const bf16x8_t bB = h ? xb : zero;
-    const bf16x8_t w1 = load_bf16x8(P->w1[lane]);
-    f32x16_t cA = {}, cB = {};
-    cA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bA, cA, 0, 0, 0);
-    cB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, bB, cB, 0, 0, 0);
-    float gA[16], gB[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const float b = P->b1[h][j];
-        gA[j] = gelu_erf(cA[j] + b);
-        gB[j] = gelu_erf(cB[j] + b);
-    }
-    f32x16_t dA = {}, dB = {};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const bf16x8_t w2 = load_bf16x8(P->w2[c][lane]);
-        dA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2, pack_bf16x8(gA + 8 * c), dA, 0, 0, 0);
-        dB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w2, pack_bf16x8(gB + 8 * c), dB, 0, 0, 0);
-    }
-    float pA = 0.f, pB = 0.f;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const float b = P->b2[h][j], w = P->w3[h][j];
-        pA += w * bf16_round(gelu_erf(dA[j] + b));
-        pB += w * bf16_round(gelu_erf(dB[j] + b));
-    }
+    float part[2];
+#pragma unroll 1
+    for (int tile = 0; tile < 2; ++tile) part[tile] = mlp_tile(P, lane, h, (h == tile) ? xb : zero);
+    const float pA = part[0], pB = part[1];
     // lane l < 32 owns cell l (tile A), lane l >= 32 owns cell l (tile B);
     // the other half of each dot product sits in lane l ^ 32.
     const float send = h ? pA : pB;

@@ -25,7 +25,7 @@ constexpr int kChunk = 64;  // samples staged in LDS at a time
 
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return norm_cdf(z) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 __device__ __forceinline__ float sigmoid_f(float o) { return 1.0f / (1.0f + expf(-o)); }
 

@@ -324,20 +324,31 @@ struct CollParams {
     int closure;
 };
 
+// Uniform value the compiler may not treat as loop-invariant: the parameters
+// are re-read through it once per tile so that constants derived from them
+// (force projections per direction, rates, their FP32 conversions) are
+// recomputed where used instead of being hoisted out of the tile loop, where
+// they would occupy ~50 vector registers for the whole kernel.
+__device__ __forceinline__ double opaque(double v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ CollParams<T> coll_params(const SweepArgs &a)
 {
     CollParams<T> c;
-    c.om = (T)a.omega;
-    c.omm = (T)a.omega_minus;
-    c.magic = (T)a.magic;
-    c.omb = (T)a.omega_bulk;
-    c.omh = (T)a.omega_higher;
-    c.F[0] = (T)a.force[0];
-    c.F[1] = (T)a.force[1];
-    c.F[2] = (T)a.force[2];
-    c.tau0 = (T)a.tau0;
-    c.smag_k = (T)a.smag_k;
+    c.om = (T)opaque(a.omega);
+    c.omm = (T)opaque(a.omega_minus);
+    c.magic = (T)opaque(a.magic);
+    c.omb = (T)opaque(a.omega_bulk);
+    c.omh = (T)opaque(a.omega_higher);
+    c.F[0] = (T)opaque(a.force[0]);
+    c.F[1] = (T)opaque(a.force[1]);
+    c.F[2] = (T)opaque(a.force[2]);
+    c.tau0 = (T)opaque(a.tau0);
+    c.smag_k = (T)opaque(a.smag_k);
     c.closure = a.closure;
     return c;
 }
@@ -597,8 +608,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
     const SweepArgs a)
 {
     using T = typename Codec<ST>::T;
-    const CollParams<T> cp = coll_params<T>(a);
     for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const CollParams<T> cp = coll_params<T>(a);
         const int4 tv = a.tiles[t];
         const CellPos c = tile_cell(tv, threadIdx.x);
         if (!c.valid) continue;
@@ -791,13 +802,16 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
 // not finite.
 // ---------------------------------------------------------------------------
 template <int COLL, typename ST, bool ODD>
-__global__ __launch_bounds__(kWG) void sweep_mlp_kernel(const SweepArgs a)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void sweep_mlp_kernel(const SweepArgs a)
 {
     constexpr int Q = 19;
     using T = float;
     static_assert(std::is_same<typename Codec<ST>::T, float>::value, "MLP closure runs in FP32");
     const CollParams<T> cp = coll_params<T>(a);
-    const MlpDev *__restrict__ net = reinterpret_cast<const MlpDev *>(a.mlp);
+    __shared__ MlpDev net_s;
+    __shared__ T park[Q][kWG];
+    mlp_stage(&net_s, a.mlp);
+    const MlpDev *net = &net_s;
     for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         const int4 tv = a.tiles[t];
         const CellPos c = tile_cell(tv, threadIdx.x);
@@ -814,24 +828,35 @@ __global__ __launch_bounds__(kWG) void sweep_mlp_kernel(const SweepArgs a)
         } else {
             for (int i = 0; i < Q; ++i) f[i] = T(0);
         }
-        const Macro<Q, T> m = moments_of<Q, T>(f, cp.F);
+        const Macro<Q, T> m0 = moments_of<Q, T>(f, cp.F);
         T P[6];
-        pi_pairs<Q, T>(f, m, P);
-        const T tau_s = tau_smagorinsky<T>(P, m.rho, cp.tau0, cp.smag_k);
+        pi_pairs<Q, T>(f, m0, P);
+        const T tau_s = tau_smagorinsky<T>(P, m0.rho, cp.tau0, cp.smag_k);
         float x[7];
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            const float raw = k < 6 ? P[k] : m.drho;
+            const float raw = k < 6 ? P[k] : m0.drho;
             x[k] = (raw - net->mean[k]) * net->istd[k];
             bad |= !(fabsf(x[k]) <= 8.f);
         }
         if (!active)
             for (int k = 0; k < 7; ++k) x[k] = 0.f;
+        // Park the populations in shared memory while the network runs and
+        // rebuild the moments from them afterwards: otherwise the compiler
+        // precomputes most of the relaxation before the network and keeps
+        // ~64 values live through it, halving the occupancy.
+#pragma unroll
+        for (int i = 0; i < Q; ++i) park[i][threadIdx.x] = f[i];
+        asm volatile("" ::: "memory");
         const float o = mlp_forward_wave(net, x);
         const T tau = (bad || !isfinite(o)) ? tau_s : cp.tau0 + softplus_f(o);
         const T om = T(1) / tau;
         const T omm = COLL == 1 ? T(1) / (T(0.5) + cp.magic / (tau - T(0.5))) : om;
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = park[i][threadIdx.x];
+        const Macro<Q, T> m = moments_of<Q, T>(f, cp.F);
         relax_pairs<Q, T>(f, m, cp.F, om, omm);
         if (!active) continue;
         if (L.alo | L.ahi) {
