@@ -73,7 +73,7 @@ def poiseuille_series(H, nu, g, T, s):
     return u
 
 
-def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True):
+def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True, q=19, coll=None):
     import numpy as np
     import torch
 
@@ -84,9 +84,9 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
         mlp = closure_weights(inputs)
     p = wlb.make_params(tau=TAU, magic=MAGIC, force=(FX, 0.0, 0.0), closure=closure, cs_smag=0.1 if closure else 0.0,
                         mlp=mlp, autotune=1 if autotune else 0)
-    B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=19, storage=storage)
+    B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=q, storage=storage)
     try:
-        B.init(wlb.TRT, p, rho, u)
+        B.init(wlb.TRT if coll is None else coll, p, rho, u)
         B.step(warmup)
         B.synchronize()
         B.set_kernel_timing(True)
@@ -122,7 +122,10 @@ def summarize(res, storage, steps, elem_bytes, q=19):
     xchg_ms = (res["kernel_ms"][2] + res["kernel_ms"][3]) / max(1, res["launches"][2] + res["launches"][3])
     bytes_per_launch = cells * 2 * q * elem_bytes
     achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9
+    ms, cnt = res["kernel_ms"], res["launches"]
     return {
+        "even_ms": ms[0] / max(1, cnt[0]),
+        "odd_ms": ms[1] / max(1, cnt[1]),
         "mlups": cells * steps / res["seconds"] / 1e6,
         "ms_per_step": res["seconds"] * 1e3 / steps,
         "sweep_ms": sweep_ms,
@@ -176,6 +179,7 @@ def main():
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
     ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures"], default="channel",
                     help="channel = the headline configuration; the others print their own JSON line")
+    ap.add_argument("--tau", type=float, default=0.5005, help="relaxation time of the turbulence workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (blocks would shard over GPUs "
@@ -192,7 +196,7 @@ def main():
         if args.workload == "porous":
             r = workloads.porous(wlb, steps=args.steps, warmup=args.warmup, autotune=not args.no_autotune)
         elif args.workload == "turbulence":
-            r = workloads.turbulence_precision(wlb, steps=args.steps)
+            r = workloads.turbulence_precision(wlb, steps=args.steps, tau=args.tau)
         else:
             r = workloads.closure_cost(wlb, steps=args.steps, warmup=args.warmup)
         print(json.dumps(r))
@@ -203,12 +207,17 @@ def main():
           f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     variants = {}
     if not args.no_variants:
-        for name, st, eb, cl in (("f32", wlb.F32, 4, 0), ("f16dev", wlb.F16DEV, 2, 0), ("bf16dev", wlb.BF16DEV, 2, 0),
-                                 ("f32_smagorinsky", wlb.F32, 4, 1), ("f32_mlp_closure", wlb.F32, 4, 2)):
-            r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune)
-            sm = summarize(r, st, args.variant_steps, eb)
+        for name, st, eb, cl, q, coll in (("f32", wlb.F32, 4, 0, 19, None), ("f16dev", wlb.F16DEV, 2, 0, 19, None),
+                                          ("bf16dev", wlb.BF16DEV, 2, 0, 19, None),
+                                          ("f32_smagorinsky", wlb.F32, 4, 1, 19, None),
+                                          ("f32_mlp_closure", wlb.F32, 4, 2, 19, None),
+                                          ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT)):
+            r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
+                           q=q, coll=coll)
+            sm = summarize(r, st, args.variant_steps, eb, q=q)
             variants[name] = {"mlups": round(sm["mlups"], 1), "roofline_frac": round(sm["frac"], 4),
                               "achieved_gbs": round(sm["achieved_gbs"], 1), "sweep_ms": round(sm["sweep_ms"], 4),
+                              "even_ms": round(sm["even_ms"], 4), "odd_ms": round(sm["odd_ms"], 4),
                               "steps": args.variant_steps}
             print(f"[bench] {name}: {sm['mlups']:.0f} MLUPS, {sm['achieved_gbs']:.0f} GB/s", file=sys.stderr,
                   flush=True)
@@ -240,7 +249,8 @@ def main():
                      "frac": round(head["frac"], 4), "traffic": traffic,
                      "kernel": "sweep_kernel<19,TRT,double> (even and odd AA sweeps)",
                      "algorithmic_bytes_per_launch": head["bytes_per_launch"],
-                     "avg_launch_ms": round(head["sweep_ms"], 5)},
+                     "avg_launch_ms": round(head["sweep_ms"], 5), "even_launch_ms": round(head["even_ms"], 5),
+                     "odd_launch_ms": round(head["odd_ms"], 5)},
         "cpu_baseline": cpu,
         "variants": variants,
         "exchange_ms_per_step": round(head["exchange_ms"], 5),

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -458,6 +459,9 @@ int autotune(wlb_blocks *h)
     // repetitions scaled so each candidate runs ~ 2e8 cell updates at most
     int reps = (int)std::max<int64_t>(2, std::min<int64_t>(10, 200000000 / std::max<int64_t>(1, 2 * h->ncells)));
     bool blds = false;
+    // WLB_AUTOTUNE_LOG=1 prints every candidate's time to stderr
+    const char *env = getenv("WLB_AUTOTUNE_LOG");
+    const bool log = env && env[0] == '1';
     for (int lds = 0; lds <= 1; ++lds) {
         h->lds_stage = lds != 0;
         for (const auto &s : kShapes) {
@@ -470,6 +474,9 @@ int autotune(wlb_blocks *h)
                 float ms = 0.f;
                 rc = time_pairs(h, reps, &ms);
                 if (rc) return rc;
+                if (log)
+                    fprintf(stderr, "[wlb autotune] tile %d,%d,%d grid %d lds %d: %zu tiles, %.4f ms per step\n", s[0],
+                            s[1], s[2], g, lds, h->tiles.size(), ms);
                 if (ms < best) {
                     best = ms;
                     bs[0] = s[0];

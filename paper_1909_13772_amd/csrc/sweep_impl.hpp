@@ -128,6 +128,11 @@ struct Macro {
     T drho, rho, u[3], uu;
 };
 
+// 1/x: exact division in FP64; the hardware reciprocal (1 ulp) in FP32,
+// where an IEEE division costs about ten instructions per call.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <int Q, typename T>
 __device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
 {
@@ -145,7 +150,7 @@ __device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
     Macro<Q, T> m;
     m.drho = drho;
     m.rho = T(1) + drho;
-    const T inv = T(1) / m.rho;
+    const T inv = recip(m.rho);
     m.u[0] = (jx + T(0.5) * F[0]) * inv;
     m.u[1] = (jy + T(0.5) * F[1]) * inv;
     m.u[2] = (jz + T(0.5) * F[2]) * inv;
@@ -166,49 +171,13 @@ __device__ __forceinline__ T cdot(const T v[3])
     return r;
 }
 
-// Equilibrium deviation w_i (drho + rho (3 cu + 9/2 cu^2 - 3/2 uu)) and Guo
-// term w_i (3 (c - u).F + 9 (c.u)(c.F)).
-template <int Q, typename T>
-__device__ __forceinline__ void eq_and_force(const Macro<Q, T> &m, const T F[3], T (&de)[Q], T (&Fi)[Q])
-{
-    const T uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr T w = weight<Q, T>(i);
-        const T cu = cdot<i>(m.u);
-        const T cF = cdot<i>(F);
-        de[i] = w * (m.drho + m.rho * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * m.uu));
-        Fi[i] = w * (T(3) * (cF - uF) + T(9) * cu * cF);
-    });
-}
-
-// Non-equilibrium stress Pi_ab = sum c_a c_b (d - deq): xx, yy, zz, xy, xz, yz.
-template <int Q, typename T>
-__device__ __forceinline__ void pi_neq(const T (&d)[Q], const T (&de)[Q], T P[6])
-{
-    for (int k = 0; k < 6; ++k) P[k] = T(0);
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const T n = d[i] - de[i];
-        if constexpr (cx(i) != 0) P[0] += n;
-        if constexpr (cy(i) != 0) P[1] += n;
-        if constexpr (cz(i) != 0) P[2] += n;
-        if constexpr (cx(i) * cy(i) == 1) P[3] += n;
-        if constexpr (cx(i) * cy(i) == -1) P[3] -= n;
-        if constexpr (cx(i) * cz(i) == 1) P[4] += n;
-        if constexpr (cx(i) * cz(i) == -1) P[4] -= n;
-        if constexpr (cy(i) * cz(i) == 1) P[5] += n;
-        if constexpr (cy(i) * cz(i) == -1) P[5] -= n;
-    });
-}
-
 // Smagorinsky relaxation time: tau = (tau0 + sqrt(tau0^2 + k sqrt(Pi:Pi) / rho)) / 2,
 // k = 18 sqrt(2) C_s^2 (from nu_t = C_s^2 |S| and Pi = -2 rho c_s^2 tau S).
 template <typename T>
 __device__ __forceinline__ T tau_smagorinsky(const T P[6], T rho, T tau0, T k)
 {
     const T Q = P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + T(2) * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]);
-    return T(0.5) * (tau0 + sqrt(tau0 * tau0 + k * sqrt(Q) / rho));
+    return T(0.5) * (tau0 + sqrt(tau0 * tau0 + k * sqrt(Q) * recip(rho)));
 }
 
 // Raw-moment transform along one axis of a 3x3x3 array v[z][y][x] (index
@@ -245,43 +214,127 @@ __device__ __forceinline__ void tvalues(T (&v)[27])
 }
 __host__ __device__ constexpr int tpos(int i) { return 9 * (cz(i) + 1) + 3 * (cy(i) + 1) + (cx(i) + 1); }
 
+// Lattice moment numerator sum_i wnum_i c_x^a c_y^b c_z^c (divide by wden):
+// compile-time constants of the stencil.
+template <int Q>
+__host__ __device__ constexpr int lmom_num(int a, int b, int c)
+{
+    int s = 0;
+    for (int i = 0; i < Q; ++i) {
+        int t = wnum<Q>(i);
+        for (int k = 0; k < a; ++k) t *= cx(i);
+        for (int k = 0; k < b; ++k) t *= cy(i);
+        for (int k = 0; k < c; ++k) t *= cz(i);
+        s += t;
+    }
+    return s;
+}
+
+// Per-cell inputs of the closed-form equilibrium and source moments.
+template <typename T>
+struct MomentSources {
+    T A;       // drho - 3/2 rho u.u
+    T ru[3];   // rho u
+    T ruu[6];  // rho u_j u_l: xx yy zz xy xz yz
+    T uF;      // u.F
+    T F[3];
+    T uFs[6];  // u_j F_j (diagonal), u_j F_l + u_l F_j (off-diagonal)
+};
+
+template <int Q, typename T>
+__device__ __forceinline__ MomentSources<T> moment_sources(const Macro<Q, T> &m, const T F[3])
+{
+    MomentSources<T> s;
+    s.A = m.drho - T(1.5) * m.rho * m.uu;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        s.ru[k] = m.rho * m.u[k];
+        s.F[k] = F[k];
+    }
+    s.ruu[0] = s.ru[0] * m.u[0];
+    s.ruu[1] = s.ru[1] * m.u[1];
+    s.ruu[2] = s.ru[2] * m.u[2];
+    s.ruu[3] = s.ru[0] * m.u[1];
+    s.ruu[4] = s.ru[0] * m.u[2];
+    s.ruu[5] = s.ru[1] * m.u[2];
+    s.uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
+    s.uFs[0] = m.u[0] * F[0];
+    s.uFs[1] = m.u[1] * F[1];
+    s.uFs[2] = m.u[2] * F[2];
+    s.uFs[3] = m.u[0] * F[1] + m.u[1] * F[0];
+    s.uFs[4] = m.u[0] * F[2] + m.u[2] * F[0];
+    s.uFs[5] = m.u[1] * F[2] + m.u[2] * F[1];
+    return s;
+}
+
+// Raw moment of order (a, b, c) of the equilibrium deviation
+// w (drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)) (EQ) or of the Guo term
+// w (3 (c - u).F + 9 (c.u)(c.F)) (!EQ): expanding (c.u)^2 and (c.u)(c.F)
+// leaves sums sum w c^(a,b,c) c_j c_l, i.e. lattice moments of higher order,
+// most of which vanish; what remains is a few FMAs per moment.
+template <int Q, bool EQ, int a, int b, int c, typename T>
+__device__ __forceinline__ T source_moment(const MomentSources<T> &s)
+{
+    constexpr double D = wden<Q>();
+    constexpr int L0 = lmom_num<Q>(a, b, c);
+    constexpr int L1[3] = {lmom_num<Q>(a + 1, b, c), lmom_num<Q>(a, b + 1, c), lmom_num<Q>(a, b, c + 1)};
+    constexpr int L2[6] = {lmom_num<Q>(a + 2, b, c),     lmom_num<Q>(a, b + 2, c),     lmom_num<Q>(a, b, c + 2),
+                           lmom_num<Q>(a + 1, b + 1, c), lmom_num<Q>(a + 1, b, c + 1), lmom_num<Q>(a, b + 1, c + 1)};
+    T r = T(0);
+    if constexpr (L0 != 0) {
+        if constexpr (EQ)
+            r += T(L0 / D) * s.A;
+        else
+            r -= T(3.0 * L0 / D) * s.uF;
+    }
+    sfor<3>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        if constexpr (L1[j] != 0) r += T(3.0 * L1[j] / D) * (EQ ? s.ru[j] : s.F[j]);
+    });
+    sfor<6>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        // (c.u)^2 counts each off-diagonal product twice; (c.u)(c.F) is
+        // already summed over both orders in uFs
+        constexpr double k = EQ ? (j < 3 ? 4.5 : 9.0) : 9.0;
+        if constexpr (L2[j] != 0) r += T(k * L2[j] / D) * (EQ ? s.ruu[j] : s.uFs[j]);
+    });
+    return r;
+}
+
 // MRT in the raw-moment basis sum c_x^a c_y^b c_z^c (a, b, c <= 2) through
 // the tensor-product transform; the three diagonal second-order moments are
 // relaxed as x2-y2, x2-z2 (rate omega) and x2+y2+z2 (omega_bulk), xy/xz/yz
 // with omega, order >= 3 with omega_higher, conserved moments with 0.  The
-// Guo source enters as M^{-1} (I - S/2) M F.  D3Q19 uses the same transform
-// with the eight corner populations held at zero: D3Q19 distributions are
-// exactly those whose moments with a factor xyz vanish, a subspace that the
-// relaxation maps into itself.
+// Guo source enters as M^{-1} (I - S/2) M F.  Only the populations are
+// transformed: the equilibrium's and the source's moments are closed forms.
+// D3Q19 uses the same transform with the eight corner populations held at
+// zero: D3Q19 distributions are exactly those whose moments with a factor
+// xyz vanish, a subspace that the relaxation maps into itself.  With the
+// Smagorinsky closure omega comes from the non-equilibrium second moments.
 template <int Q, typename T>
-__device__ __forceinline__ void mrt_relax(T (&d)[Q], const T (&de)[Q], const T (&Fi)[Q], T om, T omb, T omh,
-                                          T *Pout /* 6 or nullptr */)
+__device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omb, T omh,
+                                            int closure, T tau0, T smag_k)
 {
-    T mn[27], mf[27];
-    for (int k = 0; k < 27; ++k) {
-        mn[k] = T(0);
-        mf[k] = T(0);
-    }
+    T mn[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) mn[k] = T(0);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        mn[tpos(i)] = d[i] - de[i];
-        mf[tpos(i)] = Fi[i];
+        mn[tpos(i)] = d[i];
     });
     tmoments<0>(mn);
     tmoments<1>(mn);
     tmoments<2>(mn);
-    tmoments<0>(mf);
-    tmoments<1>(mf);
-    tmoments<2>(mf);
-    // after the transform, index 9 c + 3 b + a holds the moment of order (a, b, c)
+    const MomentSources<T> src = moment_sources<Q, T>(m, F);
+    // after the transform, index a + 3 b + 9 c holds the moment of order (a, b, c)
+    sfor<27>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        mn[k] -= source_moment<Q, true, k % 3, (k / 3) % 3, k / 9>(src);
+    });
     constexpr int XX = 2, YY = 6, ZZ = 18, XY = 4, XZ = 10, YZ = 12;
-    if (Pout) {
-        Pout[0] = mn[XX];
-        Pout[1] = mn[YY];
-        Pout[2] = mn[ZZ];
-        Pout[3] = mn[XY];
-        Pout[4] = mn[XZ];
-        Pout[5] = mn[YZ];
+    if (closure == 1) {
+        const T P[6] = {mn[XX], mn[YY], mn[ZZ], mn[XY], mn[XZ], mn[YZ]};
+        om = recip(tau_smagorinsky<T>(P, m.rho, tau0, smag_k));
     }
     T g[27];
     sfor<27>([&](auto K) {
@@ -289,18 +342,20 @@ __device__ __forceinline__ void mrt_relax(T (&d)[Q], const T (&de)[Q], const T (
         constexpr int a = k % 3, b = (k / 3) % 3, c = k / 9;
         constexpr int ord = a + b + c;
         if constexpr (ord <= 1) {
-            g[k] = -mf[k];
+            g[k] = -source_moment<Q, false, a, b, c>(src);
         } else if constexpr (ord == 2 && (a == 2 || b == 2 || c == 2)) {
             g[k] = T(0);  // diagonal: below
         } else if constexpr (ord == 2) {
-            g[k] = om * mn[k] - (T(1) - T(0.5) * om) * mf[k];
+            g[k] = om * mn[k] - (T(1) - T(0.5) * om) * source_moment<Q, false, a, b, c>(src);
         } else {
-            g[k] = omh * mn[k] - (T(1) - T(0.5) * omh) * mf[k];
+            g[k] = omh * mn[k] - (T(1) - T(0.5) * omh) * source_moment<Q, false, a, b, c>(src);
         }
     });
     {
+        const T fxx = source_moment<Q, false, 2, 0, 0>(src), fyy = source_moment<Q, false, 0, 2, 0>(src),
+                fzz = source_moment<Q, false, 0, 0, 2>(src);
         const T An = mn[XX] - mn[YY], Bn = mn[XX] - mn[ZZ], Tn = mn[XX] + mn[YY] + mn[ZZ];
-        const T Af = mf[XX] - mf[YY], Bf = mf[XX] - mf[ZZ], Tf = mf[XX] + mf[YY] + mf[ZZ];
+        const T Af = fxx - fyy, Bf = fxx - fzz, Tf = fxx + fyy + fzz;
         const T gA = om * An - (T(1) - T(0.5) * om) * Af;
         const T gB = om * Bn - (T(1) - T(0.5) * om) * Bf;
         const T gT = omb * Tn - (T(1) - T(0.5) * omb) * Tf;
@@ -378,36 +433,52 @@ __device__ __forceinline__ void pi_pairs(const T (&d)[Q], const Macro<Q, T> &m, 
     });
 }
 
-// SRT / TRT relaxation evaluated pair by pair (i, opp(i)) on the symmetric
-// and antisymmetric parts:
-//   e+ = w (drho - 3/2 rho uu + 9/2 rho cu^2),  e- = 3 w rho cu,
-//   F+ = w (9 cu cF - 3 u.F),                   F- = 3 w cF,
-//   d_i += r+ + r-, d_opp += r+ - r-,  r+- = -omega+- (d+- - e+-) + (1 - omega+-/2) F+-,
-// which keeps only the populations live (no equilibrium arrays).
-template <int Q, typename T>
+// SRT / TRT relaxation evaluated pair by pair (i, opp(i)).  With the pair
+// parts d+- = (d_i +- d_opp) / 2 the update is
+//   d_i += r+ + r-,  d_opp += r+ - r-,  r+- = -omega+- (d+- - e+-) + (1 - omega+-/2) F+-,
+//   e+ = w (A + 9/2 rho cu^2),  e- = 3 w rho cu,  A = drho - 3/2 rho uu,
+//   F+ = w (9 cu cF - 3 u.F),   F- = 3 w cF.
+// The source parts are gathered into per-cell vectors so that a pair costs
+// three dot products with c (a few adds) and a handful of FMAs:
+//   omega+ e+ + (1 - omega+/2) F+ = w (K + cu c.V),  K = omega+ A - 3 (1 - omega+/2) u.F,
+//                                                    V = 9/2 omega+ rho u + 9 (1 - omega+/2) F,
+//   omega- e- + (1 - omega-/2) F- = w c.W,           W = 3 omega- rho u + 3 (1 - omega-/2) F,
+// and d_i' = alpha d_i + beta d_opp + z+ + z-, alpha = 1 - (omega+ + omega-)/2,
+// beta = (omega- - omega+)/2 (zero for SRT).  Only the populations stay live.
+template <int Q, typename T, bool SRT = false>
 __device__ __forceinline__ void relax_pairs(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omm)
 {
+    const T fop = T(1) - T(0.5) * om, fom = T(1) - T(0.5) * omm;
     const T A = m.drho - T(1.5) * m.rho * m.uu;
     const T uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
-    const T fop = T(1) - T(0.5) * om, fom = T(1) - T(0.5) * omm;
+    const T K = om * A - T(3) * fop * uF;
+    const T kv = T(4.5) * om * m.rho, kw = T(3) * omm * m.rho;
+    const T fv = T(9) * fop, fw = T(3) * fom;
+    T V[3], W[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        V[k] = kv * m.u[k] + fv * F[k];
+        W[k] = kw * m.u[k] + fw * F[k];
+    }
+    const T al = T(1) - T(0.5) * (om + omm), be = T(0.5) * (omm - om);
     {
         constexpr T w0 = weight<Q, T>(0);
-        d[0] += -om * (d[0] - w0 * A) + fop * (w0 * (T(-3) * uF));
+        d[0] = (T(1) - om) * d[0] + w0 * K;
     }
-    sfor<(Q - 1) / 2>([&](auto K) {
-        constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
+    sfor<(Q - 1) / 2>([&](auto I) {
+        constexpr int i = 2 * decltype(I)::value + 1, o = i + 1;
         constexpr T w = weight<Q, T>(i);
         const T cu = cdot<i>(m.u);
-        const T cF = cdot<i>(F);
-        const T ep = w * (A + T(4.5) * m.rho * cu * cu);
-        const T em = T(3) * w * m.rho * cu;
-        const T fp = w * (T(9) * cu * cF - T(3) * uF);
-        const T fm = T(3) * w * cF;
-        const T dp = T(0.5) * (d[i] + d[o]), dm = T(0.5) * (d[i] - d[o]);
-        const T rp = -om * (dp - ep) + fop * fp;
-        const T rm = -omm * (dm - em) + fom * fm;
-        d[i] += rp + rm;
-        d[o] += rp - rm;
+        const T zp = w * (K + cu * cdot<i>(V));
+        const T zm = w * cdot<i>(W);
+        const T di = d[i], dd = d[o];
+        if constexpr (SRT) {
+            d[i] = al * di + (zp + zm);
+            d[o] = al * dd + (zp - zm);
+        } else {
+            d[i] = al * di + be * dd + (zp + zm);
+            d[o] = al * dd + be * di + (zp - zm);
+        }
     });
 }
 
@@ -418,24 +489,17 @@ __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p
     const Macro<Q, T> m = moments_of<Q, T>(d, p.F);
     T om = p.om, omm = p.omm;
     if constexpr (COLL == 2) {
-        T de[Q], Fi[Q];
-        eq_and_force<Q, T>(m, p.F, de, Fi);
-        if (p.closure == 1) {
-            T P[6];
-            pi_neq<Q, T>(d, de, P);
-            om = T(1) / tau_smagorinsky<T>(P, m.rho, p.tau0, p.smag_k);
-        }
-        mrt_relax<Q, T>(d, de, Fi, om, p.omb, p.omh, nullptr);
+        mrt_collide<Q, T>(d, m, p.F, om, p.omb, p.omh, p.closure, p.tau0, p.smag_k);
     } else {
         if (p.closure == 1) {
             T P[6];
             pi_pairs<Q, T>(d, m, P);
             const T tau = tau_smagorinsky<T>(P, m.rho, p.tau0, p.smag_k);
-            om = T(1) / tau;
-            omm = T(1) / (T(0.5) + p.magic / (tau - T(0.5)));
+            om = recip(tau);
+            omm = recip(T(0.5) + p.magic * recip(tau - T(0.5)));
         }
         if constexpr (COLL == 0) omm = om;
-        relax_pairs<Q, T>(d, m, p.F, om, omm);
+        relax_pairs<Q, T, COLL == 0>(d, m, p.F, om, omm);
     }
     return m;
 }
@@ -851,13 +915,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         asm volatile("" ::: "memory");
         const float o = mlp_forward_wave(net, x);
         const T tau = (bad || !isfinite(o)) ? tau_s : cp.tau0 + softplus_f(o);
-        const T om = T(1) / tau;
-        const T omm = COLL == 1 ? T(1) / (T(0.5) + cp.magic / (tau - T(0.5))) : om;
+        const T om = recip(tau);
+        const T omm = COLL == 1 ? recip(T(0.5) + cp.magic * recip(tau - T(0.5))) : om;
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = park[i][threadIdx.x];
         const Macro<Q, T> m = moments_of<Q, T>(f, cp.F);
-        relax_pairs<Q, T>(f, m, cp.F, om, omm);
+        relax_pairs<Q, T, COLL == 0>(f, m, cp.F, om, omm);
         if (!active) continue;
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;

@@ -78,43 +78,71 @@ def _spectrum(u):
     return shell_spectrum(u)
 
 
-def turbulence_precision(wlb, n=384, steps=1000, warmup=0, seed=0, storages=None):
+def turbulence_precision(wlb, n=384, steps=1000, every=100, seed=0, storages=None, tau=0.5005, umax=0.5):
     """Decaying turbulence (E(k) ~ k^4 exp(-2 (k/4)^2), u_rms 0.05) on n^3,
-    D3Q19 TRT (Lambda 3/16), tau 0.5005; each storage type against the FP64
-    run: velocity relative L2 error and the worst shell-spectrum error for
-    k <= 64 after `steps` steps."""
+    D3Q19 TRT (Lambda 3/16).  Every storage type advances in lockstep with the
+    FP64 run; every `every` steps each is compared with it (velocity relative
+    L2 error, worst shell-spectrum error for 1 <= k <= 64) for as long as the
+    FP64 run stays healthy (finite, max |u| < umax), and the step at which a
+    run first fails that check is recorded.  At tau = 0.5005 (nu = 1.7e-4)
+    the flow is far from resolved at any of these sizes and the plain
+    collision operators do not survive 1000 steps in any precision, so the
+    ladder is reported up to the reference's breakdown."""
     storages = storages or [wlb.F64, wlb.F32, wlb.F16DEV, wlb.BF16DEV]
     rho, u = inputs.turbulence_bandlimited(n, seed)
-    p = wlb.make_params(tau=0.5005, magic=3.0 / 16.0, autotune=1, health_every=100, health_umax=0.5)
-    ref_u, ref_e, out = None, None, {}
-    for st in storages:
-        B = wlb.Blocks(wlb.single_block((n, n, n)), (n, n, n), (1, 1, 1), stencil=19, storage=st)
-        name = wlb.STORAGE_NAMES[st]
-        try:
+    p = wlb.make_params(tau=tau, magic=3.0 / 16.0, autotune=1)
+    runs, secs, out = {}, {}, {}
+    try:
+        for st in storages:
+            name = wlb.STORAGE_NAMES[st]
+            B = wlb.Blocks(wlb.single_block((n, n, n)), (n, n, n), (1, 1, 1), stencil=19, storage=st)
             B.init(wlb.TRT, p, rho, u)
-            try:
-                secs, ms, cnt = _timed_steps(B, steps, warmup)
-            except wlb.WlbError as e:
-                out[name] = {"diverged": True, "error": str(e)}
+            runs[name], secs[name] = B, 0.0
+            out[name] = {"diverged_at": None, "checkpoints": []}
+        del rho, u
+        ref_alive = True
+        for step in range(every, steps + 1, every):
+            fields = {}
+            for name, B in list(runs.items()):
+                t0 = time.perf_counter()
+                B.step(every)
+                B.synchronize()
+                secs[name] += time.perf_counter() - t0
+                _, uu, tot = B.moments()
+                vmax = float(np.abs(uu).max())
+                if not np.isfinite(vmax) or vmax >= umax:
+                    out[name]["diverged_at"] = step
+                    B.close()
+                    del runs[name]
+                    continue
+                fields[name] = (uu, float(tot[4]), float(tot[0]))
+            ref = fields.get("f64")
+            if ref is None:
+                ref_alive = False
+            if not ref_alive:
+                if not runs:
+                    break
                 continue
-            _, uu, tot = B.moments()
-        finally:
+            e_ref = _spectrum(ref[0])
+            k = np.arange(1, min(64, len(e_ref) - 1) + 1)
+            for name, (uu, energy, mass) in fields.items():
+                rec = {"step": step, "energy": energy, "mass_rel_drift": abs(mass - n ** 3) / n ** 3,
+                       "max_u": float(np.abs(uu).max())}
+                if name != "f64":
+                    e = _spectrum(uu)
+                    rec["u_rel_l2_vs_f64"] = float(np.linalg.norm(uu - ref[0]) / np.linalg.norm(ref[0]))
+                    rec["spectrum_rel_err_max_vs_f64"] = float(np.max(np.abs(e[k] - e_ref[k]) / e_ref[k]))
+                out[name]["checkpoints"].append(rec)
+    finally:
+        for B in runs.values():
             B.close()
-        sweep_ms = (ms[0] + ms[1]) / max(1, cnt[0] + cnt[1])
-        bl = n ** 3 * 2 * 19 * wlb.ELEM_BYTES[st]
-        e = _spectrum(uu)
-        rec = {"mlups": n ** 3 * steps / secs / 1e6, "sweep_ms": sweep_ms,
-               "achieved_gbs": bl / (sweep_ms * 1e-3) / 1e9,
-               "roofline_frac": bl / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "energy": float(tot[4]),
-               "mass_rel_drift": float(abs(tot[0] - n ** 3) / n ** 3)}
-        if ref_u is None:
-            ref_u, ref_e = uu, e
-        else:
-            rec["u_rel_l2_vs_f64"] = float(np.linalg.norm(uu - ref_u) / np.linalg.norm(ref_u))
-            k = np.arange(1, min(64, len(e) - 1) + 1)
-            rec["spectrum_rel_err_max_vs_f64"] = float(np.max(np.abs(e[k] - ref_e[k]) / ref_e[k]))
-        out[name] = rec
-    return {"workload": f"decaying turbulence {n}^3, D3Q19 TRT, tau 0.5005", "steps": steps, "storage": out}
+    for name, rec in out.items():
+        done = rec["checkpoints"][-1]["step"] if rec["checkpoints"] else 0
+        rec["steps_timed"] = rec["diverged_at"] or steps
+        rec["mlups"] = n ** 3 * rec["steps_timed"] / secs[name] / 1e6 if secs[name] > 0 else None
+        rec["last_compared_step"] = done
+    return {"workload": f"decaying turbulence {n}^3, D3Q19 TRT, tau {tau}", "steps": steps, "every": every,
+            "storage": out}
 
 
 def closure_cost(wlb, n=128, steps=500, warmup=10, params=None):
