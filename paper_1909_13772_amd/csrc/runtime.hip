@@ -77,6 +77,7 @@ struct wlb_blocks {
     int64_t steps = 0;
     int parity = 0;       // 0 natural layout, 1 swapped (after an even sweep)
     int pending = 0;      // 0 none, 1 pull due (after even), 2 push due (after odd)
+    bool any_wrap = false;  // some block wraps its x accesses (no LDS-staged odd sweep then)
     int last_sweep = -1;  // parity of the last sweep (-1: none since init / set)
     int shape[3] = {0, 0, 0};
     int grid = 0;
@@ -152,7 +153,8 @@ void update_lds_stride(wlb_blocks *h)
     for (const TileHost &t : h->tiles) stride = std::max(stride, t.ey * t.ez * (t.ex + 2));
     const int nsh = h->q == 19 ? 10 : 18;
     const size_t bytes = ((2 * (size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
-    h->args.lds_stride = (h->lds_stage && bytes <= 65536) ? stride : 0;
+    // the staged odd sweep keeps the ghost-layer addressing along x
+    h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->any_wrap) ? stride : 0;
     h->graph_valid = false;
 }
 
@@ -475,7 +477,7 @@ int autotune(wlb_blocks *h)
                 rc = time_pairs(h, reps, &ms);
                 if (rc) return rc;
                 if (log)
-                    fprintf(stderr, "[wlb autotune] tile %d,%d,%d grid %d lds %d: %zu tiles, %.4f ms per step\n", s[0],
+                    fprintf(stderr, "[wlb autotune] tile %d,%d,%d grid %d lds %d: %zu tiles, %.4f ms per two steps\n", s[0],
                             s[1], s[2], g, lds, h->tiles.size(), ms);
                 if (ms < best) {
                     best = ms;
@@ -602,8 +604,14 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
         const HostBlock &B = h->blocks[b];
         DevBlock &D = h->dev[b];
         std::memset(&D, 0, sizeof D);
-        D.xoff = align_e;
-        D.pitch = (int32_t)round_up((size_t)align_e + B.n[0] + 1, align_e);
+        // Rows of at least 256 bytes start interior x = 0 on a 128-byte
+        // boundary (whole lines per wave).  Shorter rows are packed with just
+        // their two ghost cells: a wave then covers several rows of nearly
+        // contiguous memory instead of touching a mostly empty line per row
+        // and another for each ghost cell.
+        const bool packed = (size_t)B.n[0] * h->esize < 256;
+        D.xoff = packed ? 1 : align_e;
+        D.pitch = packed ? B.n[0] + 2 : (int32_t)round_up((size_t)align_e + B.n[0] + 1, align_e);
         const int64_t plane = (int64_t)D.pitch * (B.n[1] + 2);
         const int64_t slot = (int64_t)round_up((size_t)(plane * (B.n[2] + 2)), align_e);
         if (slot * h->esize >= (int64_t)1 << 31) {
@@ -618,6 +626,10 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
             D.n[a] = B.n[a];
             D.g[a] = B.org[a];
         }
+        // a block that is its own neighbour on both x faces wraps its x
+        // accesses in the kernels and takes no part in x exchanges
+        D.wrapx = (B.nbr[12] == b && B.nbr[14] == b) ? B.n[0] : 0;
+        if (D.wrapx) h->any_wrap = true;
         D.mpitch = (int32_t)round_up(B.n[0], 32);
         D.mplane = D.mpitch * B.n[1];
         D.mask = (int64_t)mwords;  // provisional; -1 if the block has no solid nearby (set at init)
@@ -640,11 +652,15 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     // --- exchange work lists
     for (int b = 0; b < n; ++b) {
         const HostBlock &A = h->blocks[b];
+        const bool wrapx = h->dev[b].wrapx != 0;
         for (int k = 0; k < 27; ++k) {
             const int nb = A.nbr[k];
             if (nb < 0) continue;
             const HostBlock &Bn = h->blocks[nb];
             const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+            // x-crossing populations of a wrapping block never leave it:
+            // the kernels address the other end of the row directly
+            if (wrapx && o[0] != 0) continue;
             for (int j = 1; j < stencil; ++j) {
                 bool in = true;
                 for (int a = 0; a < 3; ++a)
@@ -663,6 +679,11 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
                         ext[a] = 1;
                         ghost0[a] = o[a] < 0 ? -1 : A.n[a];
                         inner0[a] = o[a] < 0 ? Bn.n[a] - 1 : 0;
+                    } else if (a == 0 && wrapx) {
+                        // every cell of the row: the reader / writer wraps along x
+                        ext[a] = A.n[a];
+                        ghost0[a] = 0;
+                        inner0[a] = 0;
                     } else {
                         const int lo = std::max(0, cc(j, a)), hi = std::min(A.n[a], A.n[a] + cc(j, a));
                         ext[a] = hi - lo;

@@ -641,22 +641,67 @@ __device__ __forceinline__ Alt<ST> alt_out(const SweepArgs &a, const DevBlock &B
     return pick_alt<ST>(a, B, i, link_delta<i>(B), opp(i));
 }
 
+// Byte offsets of a cell for regular accesses shifted by 0, -1 and +1 cells
+// along x.  A block that is its own neighbour along x (one block spanning a
+// periodic axis) has no x exchange: the odd sweep and every reader of the
+// swapped layout wrap the shifted accesses around the block instead, so that
+// the sweep writes whole cache lines at both row ends.
+struct XOff {
+    uint32_t at, left, right;
+};
+template <typename ST>
+__device__ __forceinline__ XOff xoffsets(const DevBlock &B, uint32_t off, int x)
+{
+    const uint32_t w = (uint32_t)B.wrapx * (uint32_t)sizeof(ST);
+    XOff o;
+    o.at = off * (uint32_t)sizeof(ST);
+    o.left = o.at + (x == 0 ? w : 0u);
+    o.right = o.at - (x == B.n[0] - 1 ? w : 0u);
+    return o;
+}
+// Offset of the regular access shifted by dx in {-1, 0, 1} cells along x.
+template <int dx>
+__device__ __forceinline__ uint32_t xshift(const XOff &o)
+{
+    return dx < 0 ? o.left : (dx > 0 ? o.right : o.at);
+}
+
 // Gather the populations f_i(x) of a fluid cell for the current layout:
 // natural (after an odd sweep / init) reads slot i of x; swapped (after an
 // even sweep) reads slot opp(i) of x - c_i, or slot i of x on bounce-back /
 // anti-bounce-back links.
 template <int Q, typename ST, bool SWAPPED>
-__device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, uint32_t off, uint32_t special,
+__device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, uint32_t special,
                                        typename Codec<ST>::T (&f)[Q])
 {
-    const uint32_t boff = off * (uint32_t)sizeof(ST);
+    const XOff o = xoffsets<ST>(B, off, x);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (!SWAPPED) {
-            f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
+            f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), o.at));
         } else {
             const Alt<ST> p = alt_in<ST, i>(a, B);
-            f[i] = ldv<ST>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+            f[i] = ldv<ST>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
+                                                                      : xshift<-cx(i)>(o) + p.add_reg));
+        }
+    });
+}
+
+// Store the post-collision populations of a fluid cell: even sweep into
+// slot opp(i) of x; odd sweep into slot i of x + c_i, or slot opp(i) of x on
+// bounce-back / anti-bounce-back links.
+template <int Q, typename ST, bool ODD>
+__device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, uint32_t special,
+                                        const typename Codec<ST>::T (&f)[Q])
+{
+    const XOff o = xoffsets<ST>(B, off, x);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (!ODD) {
+            stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i]);
+        } else {
+            const Alt<ST> p = alt_out<ST, i>(a, B);
+            stv<ST>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx(i)>(o) + p.add_reg), f[i]);
         }
     });
 }
@@ -682,21 +727,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
         if (mask & kSolidBit) continue;
         const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
-        const uint32_t boff = cell_off(B, c.x, c.y, c.z) * (uint32_t)sizeof(ST);
+        const uint32_t off = cell_off(B, c.x, c.y, c.z);
         const uint32_t special = L.bb | L.alo | L.ahi;
         T f[Q];
-        if constexpr (!ODD) {
-            sfor<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
-            });
-        } else {
-            sfor<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                const Alt<ST> p = alt_in<ST, i>(a, B);
-                f[i] = ldv<ST>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
-            });
-        }
+        gather<Q, ST, ODD>(a, B, off, c.x, special, f);
         const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;
@@ -706,18 +740,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
             });
         }
-        if constexpr (!ODD) {
-            sfor<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
-            });
-        } else {
-            sfor<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                const Alt<ST> p = alt_out<ST, i>(a, B);
-                stv<ST>(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
-            });
-        }
+        scatter<Q, ST, ODD>(a, B, off, c.x, special, f);
     }
 }
 
@@ -888,7 +911,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const uint32_t off = active ? cell_off(B, c.x, c.y, c.z) : 0u;
         T f[Q];
         if (active) {
-            gather<Q, ST, ODD>(a, B, off, special, f);
+            gather<Q, ST, ODD>(a, B, off, c.x, special, f);
         } else {
             for (int i = 0; i < Q; ++i) f[i] = T(0);
         }
@@ -931,16 +954,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
             });
         }
-        const uint32_t boff = off * (uint32_t)sizeof(ST);
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (!ODD) {
-                stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
-            } else {
-                const Alt<ST> p = alt_out<ST, i>(a, B);
-                stv<ST>(at<ST>(p.base, boff + (((special >> i) & 1u) ? p.add_sp : p.add_reg)), f[i]);
-            }
-        });
+        scatter<Q, ST, ODD>(a, B, off, c.x, special, f);
     }
 }
 
@@ -978,7 +992,7 @@ __global__ __launch_bounds__(kWG) void moments_kernel(const MomArgs ma)
                 const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
                 const uint32_t off = cell_off(B, c.x, c.y, c.z);
                 typename Codec<ST>::T f[Q];
-                gather<Q, ST, SWAPPED>(a, B, off, L.bb | L.alo | L.ahi, f);
+                gather<Q, ST, SWAPPED>(a, B, off, c.x, L.bb | L.alo | L.ahi, f);
                 double drho = 0, j[3] = {0, 0, 0};
                 sfor<Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
@@ -1057,7 +1071,7 @@ __global__ __launch_bounds__(kWG) void filter_kernel(const SweepArgs a, int fac,
                     if (mask & kSolidBit) continue;
                     const Links<Q> L = classify<Q>(mask, B, x, y, z, a);
                     typename Codec<ST>::T f[Q];
-                    gather<Q, ST, SWAPPED>(a, B, cell_off(B, x, y, z), L.bb | L.alo | L.ahi, f);
+                    gather<Q, ST, SWAPPED>(a, B, cell_off(B, x, y, z), x, L.bb | L.alo | L.ahi, f);
                     double drho = 0, j[3] = {0, 0, 0};
                     sfor<Q>([&](auto I) {
                         constexpr int i = decltype(I)::value;
@@ -1153,7 +1167,7 @@ __global__ __launch_bounds__(kWG) void pdfs_kernel(const SweepArgs a, double *bu
         } else {
             const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
             T f[Q];
-            gather<Q, ST, SWAPPED>(a, B, off, L.bb | L.alo | L.ahi, f);
+            gather<Q, ST, SWAPPED>(a, B, off, c.x, L.bb | L.alo | L.ahi, f);
             for (int i = 0; i < Q; ++i) buf[i * S + k] = (double)f[i];
         }
     }

@@ -12,8 +12,9 @@ constexpr int kWG = 256;  // threads per workgroup of every sweep kernel
 
 // Storage of one block in the arena.  Every population slot i is an array
 // s_i[z][y][x] over the block's cells plus one ghost layer on each side,
-// x fastest.  Rows are padded so that interior x = 0 starts on a 128-byte
-// boundary (the alignment rule of the paper's Field, Sec. 4.2):
+// x fastest.  Rows of 256 bytes or more are padded so that interior x = 0
+// starts on a 128-byte boundary (the alignment rule of the paper's Field,
+// Sec. 4.2); shorter rows are packed with only their ghost cells (xoff 1):
 //   element(i, x, y, z) = pop + i * slot + (z + 1) * plane + (y + 1) * pitch + xoff + x
 // for x in [-1, n0], y in [-1, n1], z in [-1, n2].  Read with scalar loads.
 struct DevBlock {
@@ -27,7 +28,8 @@ struct DevBlock {
     int32_t mpitch; // mask elements per row (interior only)
     int32_t mplane; // mask elements per plane
     int32_t xoff;   // element offset of interior x = 0 within a row
-    int32_t pad[3];
+    int32_t wrapx;  // n[0] if the block is its own neighbour along x (periodic), else 0
+    int32_t pad[2];
 };
 static_assert(sizeof(DevBlock) == 80, "DevBlock layout");
 

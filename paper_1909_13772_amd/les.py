@@ -69,14 +69,15 @@ def filtered_energy(filt_dev):
 class FineRun:
     """One fine decaying-turbulence run producing filtered snapshots."""
 
-    def __init__(self, wlb, torch, seed, n, factor, storage=None):
+    def __init__(self, wlb, torch, seed, n, factor, storage=None, tau_f=TAU_F):
         self.wlb, self.torch = wlb, torch
         self.n, self.factor = n, factor
         self.nc = n // factor
         rho, u = inputs.turbulence_bandlimited(n, seed, u_rms=U_RMS)
         st = wlb.F32 if storage is None else storage
         self.B = wlb.Blocks(wlb.single_block((n, n, n)), (n, n, n), (1, 1, 1), stencil=19, storage=st)
-        self.B.init(wlb.SRT, wlb.make_params(tau=TAU_F), rho, u)
+        # health check: a fine run that blows up must not feed the training set
+        self.B.init(wlb.SRT, wlb.make_params(tau=tau_f, health_every=200, health_umax=0.5), rho, u)
         del rho, u
         self.filt = torch.empty(10 * self.nc ** 3, dtype=torch.float64, device="cuda")
 
@@ -102,16 +103,16 @@ class FineRun:
         self.B.close()
 
 
-def generate(wlb, torch, seeds, n, factor, steps, snap, per_snap, rng_seed=0):
+def generate(wlb, torch, seeds, n, factor, steps, snap, per_snap, rng_seed=0, tau_f=TAU_F):
     """Training pairs (host float32) from fine runs: raw (M, 7), target (M,),
     and for each seed the filtered kinetic energy / final spectrum."""
-    tau0 = coarse_tau(factor)
+    tau0 = coarse_tau(factor, tau_f)
     g = torch.Generator(device="cuda")
     g.manual_seed(rng_seed)
     raws, tgts, sids, refs = [], [], [], {}
     for seed in seeds:
         t0 = time.time()
-        fr = FineRun(wlb, torch, seed, n, factor)
+        fr = FineRun(wlb, torch, seed, n, factor, tau_f=tau_f)
         energy = []
         for s in range(0, steps + 1, snap):
             if s > 0:
@@ -136,10 +137,14 @@ def standardisation(raw):
     return mean, 1.0 / np.maximum(std, 1e-30)
 
 
-def train(wlb, torch, raw, tgt, vraw, vtgt, epochs=20, batch=65536, lr=2e-3, seed=0):
-    """Adam on the library's gradient kernel; returns (params, history)."""
+def train(wlb, torch, raw, tgt, vraw, vtgt, epochs=200, batch=16384, lr=2e-3, seed=0):
+    """Adam on the library's gradient kernel with a cosine learning-rate
+    decay; the output bias starts at softplus^-1(mean target) so that the
+    untrained network predicts the mean correction.  Returns the parameters
+    with the lowest validation loss, the history and the loss scale."""
     mean, istd = standardisation(raw)
-    P = inputs.mlp_params(seed, mean=mean, inv_std=istd, out_bias=-4.0)
+    t_mean = max(float(np.mean(tgt)), 1e-12)
+    P = inputs.mlp_params(seed, mean=mean, inv_std=istd, out_bias=math.log(math.expm1(t_mean)))
     inv_scale = 1.0 / max(float(np.std(tgt)), 1e-30)
     dev = torch.device("cuda")
     s = torch.cuda.Stream()
@@ -159,6 +164,8 @@ def train(wlb, torch, raw, tgt, vraw, vtgt, epochs=20, batch=65536, lr=2e-3, see
         gen = torch.Generator(device="cuda")
         gen.manual_seed(seed)
         step = 0
+        total_steps = epochs * max(1, T.numel() // batch)
+        best, best_P = float("inf"), None
         for ep in range(epochs):
             perm = torch.randperm(T.numel(), device=dev, generator=gen)
             tot, nb = 0.0, 0
@@ -169,16 +176,21 @@ def train(wlb, torch, raw, tgt, vraw, vtgt, epochs=20, batch=65536, lr=2e-3, see
                 wlb.wlb_mlp_grad(Pd.data_ptr(), rb.data_ptr(), tb.data_ptr(), batch, inv_scale, g.data_ptr(),
                                  loss.data_ptr(), ws.data_ptr(), wsb, s.cuda_stream)
                 step += 1
-                wlb.wlb_mlp_adam(Pd.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, 0.9, 0.999, 1e-8,
-                                 s.cuda_stream)
+                lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * min(step, total_steps) / total_steps))
+                wlb.wlb_mlp_adam(Pd.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), step, max(lr_t, 1e-3 * lr),
+                                 0.9, 0.999, 1e-8, s.cuda_stream)
                 tot += float(loss.item())
                 nb += 1
             wlb.wlb_mlp_grad(Pd.data_ptr(), VR.data_ptr(), VT.data_ptr(), VT.numel(), inv_scale, g.data_ptr(),
                              loss.data_ptr(), ws.data_ptr(), wsb, s.cuda_stream)
-            hist.append({"epoch": ep, "train_loss": tot / max(nb, 1), "val_loss": float(loss.item())})
-            _log(f"[les] epoch {ep}: train {tot / max(nb, 1):.4f} val {float(loss.item()):.4f}")
+            vl = float(loss.item())
+            hist.append({"epoch": ep, "train_loss": tot / max(nb, 1), "val_loss": vl})
+            if vl < best:
+                best, best_P = vl, Pd.cpu().numpy()
+            if ep % 10 == 0 or ep == epochs - 1:
+                _log(f"[les] epoch {ep}: train {tot / max(nb, 1):.4f} val {vl:.4f}")
         s.synchronize()
-    return Pd.cpu().numpy(), hist, inv_scale
+    return best_P, hist, inv_scale
 
 
 def les_run(wlb, torch, rho_c, u_c, closure, params, steps, every, tau0):
@@ -211,22 +223,28 @@ def les_run(wlb, torch, rho_c, u_c, closure, params, steps, every, tau0):
 
 
 def compare(run, ref, kmax):
+    """Energy history error, and the final shell spectrum's error per shell
+    over all resolved shells (k <= kmax) and over the well-resolved ones
+    (k <= kmax / 4, where the box filter of the reference barely acts)."""
     e = np.asarray(run["energy"])
     er = np.asarray(ref["energy"])[: len(e)]
     out = {"energy_rel_err_max": float(np.max(np.abs(e - er) / er)),
            "energy_rel_err_final": float(abs(e[-1] - er[-1]) / er[-1]) if len(e) == len(ref["energy"]) else None}
     if run.get("spectrum") is not None:
-        s = np.asarray(run["spectrum"])[1:kmax + 1]
-        sr = np.asarray(ref["spectrum"])[1:kmax + 1]
-        ok = sr > 1e-30
-        out["spectrum_rel_err_max"] = float(np.max(np.abs(s[ok] - sr[ok]) / sr[ok]))
+        for key, km in (("spectrum_rel_err_max", kmax), ("spectrum_rel_err_max_low_k", max(1, kmax // 4))):
+            s = np.asarray(run["spectrum"])[1:km + 1]
+            sr = np.asarray(ref["spectrum"])[1:km + 1]
+            ok = sr > 1e-30
+            out[key] = float(np.max(np.abs(s[ok] - sr[ok]) / sr[ok]))
     return out
 
 
-def evaluate(wlb, torch, seed, params, n, factor, steps, snap):
-    """A-posteriori comparison on a held-out seed."""
-    tau0 = coarse_tau(factor)
-    fr = FineRun(wlb, torch, seed, n, factor)
+def evaluate(wlb, torch, seed, params, n, factor, steps, snap, tau_f=TAU_F, keep_series=False):
+    """A-posteriori comparison on a held-out seed: the coarse LES without a
+    model, with Smagorinsky and with the network, each against the filtered
+    fine run.  keep_series adds the energy histories and final spectra."""
+    tau0 = coarse_tau(factor, tau_f)
+    fr = FineRun(wlb, torch, seed, n, factor, tau_f=tau_f)
     rho_c, u_c = fr.coarse_state()
     energy = []
     for s in range(0, steps + 1, snap):
@@ -242,7 +260,15 @@ def evaluate(wlb, torch, seed, params, n, factor, steps, snap):
     for name, cl in (("none", wlb.CLOSURE_NONE), ("smagorinsky", wlb.CLOSURE_SMAG), ("mlp", wlb.CLOSURE_MLP)):
         r = les_run(wlb, torch, rho_c, u_c, cl, params, csteps, cevery, tau0)
         res[name] = {"diverged": r["diverged"], "mlups": r.get("mlups"), **compare(r, ref, nc // 2)}
-        _log(f"[les] a-posteriori {name}: {res[name]}")
+        e, er = np.asarray(r["energy"]), np.asarray(ref["energy"])[: len(r["energy"])]
+        res[name]["energy_ratio_final"] = float(e[-1] / er[-1])
+        if keep_series:
+            res[name]["energy"] = [float(v) for v in r["energy"]]
+            res[name]["spectrum"] = r.get("spectrum")
+        _log(f"[les] a-posteriori {name}: " + json.dumps({k: v for k, v in res[name].items()
+                                                           if k not in ("energy", "spectrum")}))
+    if keep_series:
+        res["reference"] = {"energy": [float(v) for v in ref["energy"]], "spectrum": ref["spectrum"]}
     return res
 
 
@@ -257,9 +283,11 @@ def main(argv=None):
     ap.add_argument("--train-seeds", type=str, default="0-15")
     ap.add_argument("--val-seeds", type=str, default="16-19")
     ap.add_argument("--test-seed", type=int, default=20)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--out", type=str, default="gpurun_out/les")
-    ap.add_argument("--phase", choices=["data", "train"], default="data")
+    ap.add_argument("--phase", choices=["data", "train", "eval"], default="data")
+    ap.add_argument("--tau-f", type=float, default=TAU_F, help="relaxation time of the fine runs")
+    ap.add_argument("--params", type=str, default="", help="phase eval: network parameters (.npy); default seeded")
     ap.add_argument("--data", type=str, default="", help="phase train: comma-separated npz files of pairs")
     args = ap.parse_args(argv)
 
@@ -277,10 +305,19 @@ def main(argv=None):
     os.makedirs(args.out, exist_ok=True)
     if args.phase == "data":
         sd = seeds(args.seeds)
-        raw, tgt, _ = generate(wlb, torch, sd, args.n, args.factor, args.steps, args.snap, args.per_snap, sd[0] + 1)
+        raw, tgt, _ = generate(wlb, torch, sd, args.n, args.factor, args.steps, args.snap, args.per_snap, sd[0] + 1,
+                               tau_f=args.tau_f)
         name = f"pairs_{sd[0]}-{sd[-1]}.npz"
         np.savez_compressed(os.path.join(args.out, name), raw=raw, tgt=tgt, seed=generate.last_seed_ids)
         _log(f"[les] wrote {name}: {tgt.size} pairs")
+        return 0
+    if args.phase == "eval":
+        P = np.load(args.params) if args.params else inputs.mlp_params(0, inv_std=[300.0] * 6 + [100.0],
+                                                                         out_bias=-7.0)
+        res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap, tau_f=args.tau_f,
+                       keep_series=True)
+        with open(os.path.join(args.out, f"eval_seed{args.test_seed}_tauf{args.tau_f}.json"), "w") as fh:
+            json.dump(res, fh)
         return 0
     parts = [np.load(f) for f in args.data.split(",") if f]
     raw = np.concatenate([p["raw"] for p in parts])
@@ -290,13 +327,14 @@ def main(argv=None):
     mt, mv = np.isin(sid, tr), np.isin(sid, va)
     P, hist, inv_scale = train(wlb, torch, raw[mt], tgt[mt], raw[mv], tgt[mv], epochs=args.epochs)
     np.save(os.path.join(args.out, "mlp_params.npy"), P)
-    res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap)
+    res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap, tau_f=args.tau_f,
+                   keep_series=True)
     summary = {"n_fine": args.n, "factor": args.factor, "steps_fine": args.steps, "snap": args.snap,
+               "tau_f": args.tau_f, "tau_coarse": coarse_tau(args.factor, args.tau_f),
                "train_seeds": tr, "val_seeds": va, "test_seed": args.test_seed, "train_pairs": int(mt.sum()),
                "val_pairs": int(mv.sum()), "history": hist, "inv_scale": inv_scale, "a_posteriori": res}
     with open(os.path.join(args.out, "summary.json"), "w") as fh:
         json.dump(summary, fh, indent=1)
-    _log(json.dumps(res))
     return 0
 
 

@@ -33,10 +33,12 @@ def test_param_struct_layout_matches_header():
     assert C.sizeof(wlb.wlb_block_desc) == 24
 
 
-def _crossing_links(n, periodic, q):
+def _crossing_links(n, periodic, q, wrapx=False):
     """Brute force: interior (cell, direction) pairs whose target x + c_i
     leaves the block through a periodic face -- exactly the populations one
-    exchange must move (each once)."""
+    exchange must move (each once).  A block that is its own neighbour along
+    x (wrapx) addresses the other end of its rows directly, so its targets are
+    first wrapped along x."""
     import oracle as O
     c, _, _ = O.stencil(q)
     cnt = 0
@@ -44,7 +46,8 @@ def _crossing_links(n, periodic, q):
         for z in range(n[2]):
             for y in range(n[1]):
                 for x in range(n[0]):
-                    t = (x + c[i][0], y + c[i][1], z + c[i][2])
+                    tx = (x + c[i][0]) % n[0] if wrapx else x + c[i][0]
+                    t = (tx, y + c[i][1], z + c[i][2])
                     out = [t[a] < 0 or t[a] >= n[a] for a in range(3)]
                     if any(out) and all(periodic[a] or not out[a] for a in range(3)):
                         cnt += 1
@@ -58,12 +61,34 @@ def test_create_single_block_layout():
         assert info.n_blocks == 1 and info.n_cells == 32 ** 3
         # packed rows: 32 x 8 x 1 tiles
         assert info.n_tiles == 32 * 32 // 8
-        assert info.xchg_elems == _crossing_links((32, 32, 32), (1, 1, 1), 19)
+        assert info.xchg_elems == _crossing_links((32, 32, 32), (1, 1, 1), 19, wrapx=True)
         # rows padded: x = 0 on a 128-byte boundary, pitch multiple of 16 doubles
         pitch = -(-(16 + 32 + 1) // 16) * 16
         slot = pitch * 34 * 34
         assert info.pop_bytes >= 19 * slot * 8
         assert nbytes >= info.pop_bytes
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+def test_exchange_counts_multi_block_periodic_x():
+    # two blocks along x: each is the other's x neighbour, no wrapping
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (8, 6, 5)), ((8, 0, 0), (8, 6, 5))], (16, 6, 5), (1, 1, 1), 19,
+                                 wlb.F32)
+    try:
+        info = wlb.wlb_info(h)
+        assert info.xchg_elems == 2 * _crossing_links((8, 6, 5), (1, 1, 1), 19)
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+def test_short_rows_are_packed():
+    # 16 FP32 cells = 64-byte rows: pitch n + 2, no alignment padding
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (16, 16, 16))], (16, 16, 16), (1, 1, 1), 19, wlb.F32)
+    try:
+        info = wlb.wlb_info(h)
+        slot = -(-(18 * 18 * 18) // 32) * 32
+        assert info.pop_bytes == -(-(19 * slot * 4) // 256) * 256
     finally:
         wlb.wlb_blocks_destroy(h)
 

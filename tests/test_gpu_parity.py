@@ -98,7 +98,7 @@ def _porous_case(q, coll, storage, steps, seed=1):
     return gpu, orc, solid, dom
 
 
-@pytest.mark.parametrize("q,coll", [(27, 2), (19, 0), (19, 1)])
+@pytest.mark.parametrize("q,coll", [(27, 2), (19, 0), (19, 1), (19, 2)])
 @pytest.mark.parametrize("steps", [10, 11])
 def test_porous_uneven_blocks_pressure_fp64(q, coll, steps):
     """Uneven rectilinear blocks (3 x 2 x 2), spheres, density faces on x,
@@ -121,15 +121,19 @@ def test_smagorinsky_fp64(coll):
     _compare(f"smag c{coll}", wlb.F64, 19, gpu, orc, None, np.prod(shape))
 
 
-def test_smagorinsky_mrt_fp64():
-    say("case smagorinsky mrt")
+@pytest.mark.parametrize("q", [19, 27])
+def test_smagorinsky_mrt_fp64(q):
+    """MRT with the Smagorinsky rate taken from the non-equilibrium moments,
+    with a body force on every axis."""
+    say(f"case smagorinsky mrt q{q}")
     shape = (12, 10, 9)
     rho, u = inputs.random_state(shape, seed=8, umag=0.05)
-    p = wlb.make_params(tau=0.52, closure=wlb.CLOSURE_SMAG, cs_smag=0.1, omega_bulk=1.1, omega_higher=1.0)
-    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), 27, wlb.F64, 2, p, rho, u, steps=5)
-    op = oracle_params(27, 2, 0.52, 0, (1, 1, 1), closure=1, cs_smag=0.1, omega_bulk=1.1, omega_higher=1.0)
+    F = (2e-5, -1e-5, 4e-6)
+    p = wlb.make_params(tau=0.52, closure=wlb.CLOSURE_SMAG, cs_smag=0.1, omega_bulk=1.1, omega_higher=1.0, force=F)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), q, wlb.F64, 2, p, rho, u, steps=5)
+    op = oracle_params(q, 2, 0.52, 0, (1, 1, 1), F, closure=1, cs_smag=0.1, omega_bulk=1.1, omega_higher=1.0)
     orc = oracle_run(op, shape, rho, u, None, 5)
-    _compare("smag mrt", wlb.F64, 27, gpu, orc, None, np.prod(shape))
+    _compare(f"smag mrt q{q}", wlb.F64, q, gpu, orc, None, np.prod(shape))
 
 
 @pytest.mark.parametrize("storage", [1, 2, 3])
