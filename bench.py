@@ -136,14 +136,25 @@ def summarize(res, storage, steps, elem_bytes, q=19):
     }
 
 
-def cpu_baseline(inputs):
-    import numpy as np
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
+
+def cpu_baseline(inputs):
+    """The FP64 oracle on the host: the full 256^3 channel for a few steps on
+    up to 16 OpenMP threads (the value), and one thread on a 64^3 crop."""
     import oracle as O
 
     nthreads = min(16, os.cpu_count() or 1)
     shape = (N, N, N)
-    steps = 2
+    steps = 12
     rho, u = inputs.uniform_state(shape)
     p = O.Params(q=19, collision=O.TRT, tau=TAU, magic=MAGIC, force=(FX, 0, 0), periodic=(1, 0, 1))
     d = O.init(19, shape, rho, u)
@@ -151,8 +162,16 @@ def cpu_baseline(inputs):
     O.run(p, shape, d, steps, nthreads=nthreads)
     dt = time.perf_counter() - t0
     del d
+    small = (64, 64, 64)
+    rs, us = inputs.uniform_state(small)
+    d1 = O.init(19, small, rs, us)
+    t1 = time.perf_counter()
+    O.run(p, small, d1, 4, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": N ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
-            "sample": f"full 256^3 channel, D3Q19 TRT FP64, {steps} steps ({dt:.1f} s), OpenMP threads={nthreads}"}
+            "sample": f"full 256^3 channel, D3Q19 TRT FP64, {steps} steps ({dt:.1f} s), OpenMP threads={nthreads}",
+            "single_thread_mlups": 64 ** 3 * 4 / dt1 / 1e6, "single_thread_sample": "64^3 channel crop, 4 steps",
+            "cpu_model": _cpu_model()}
 
 
 def copy_probe(wlb):

@@ -5,7 +5,7 @@ device buffers and streams):
 
 1. Fine runs: decaying turbulence (band-limited E(k) ~ k^4 exp(-2 (k/4)^2),
    u_rms = 0.05) on an n_f^3 periodic box, D3Q19 SRT, FP32 storage,
-   tau_f = 0.53.  Every `snap` fine steps the state is box-filtered by
+   tau_f = 0.51.  Every `snap` fine steps the state is box-filtered by
    `factor` (wlb_box_filter) and turned into training pairs (wlb_les_targets):
    features = (Pi_neq the coarse run would see, rho - 1), target = 3 nu_t of
    the sub-grid stress.
@@ -34,7 +34,11 @@ import numpy as np
 
 from . import inputs
 
-TAU_F = 0.53
+# Fine-run relaxation time: nu_f = 1/300.  At 512^3 with u_rms 0.05 this
+# fine run is resolved (it stays stable and smooth), while the coarse 128^3
+# run at the acoustically scaled tau0 = 0.5025 is not: without a sub-grid
+# model it blows up, which is the regime a closure is for.
+TAU_F = 0.51
 U_RMS = 0.05
 
 
@@ -129,6 +133,43 @@ def generate(wlb, torch, seeds, n, factor, steps, snap, per_snap, rng_seed=0, ta
         _log(f"[les] fine seed {seed}: {steps} steps at {n}^3 in {time.time() - t0:.1f} s")
     generate.last_seed_ids = np.concatenate(sids)
     return np.concatenate(raws), np.concatenate(tgts), refs
+
+
+# The 48 symmetries of the cube act on the stress components (xx, yy, zz, xy,
+# xz, yz) by an axis permutation and sign flips; the density and the target
+# (a scalar viscosity) are invariant.
+_PAIRS = {(0, 1): 3, (0, 2): 4, (1, 2): 5}
+
+
+def cube_symmetries():
+    """(48, 6) source component and (48, 6) sign for each symmetry."""
+    import itertools
+    out_idx, out_sgn = [], []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            idx, sgn = [perm[0], perm[1], perm[2]], [1, 1, 1]
+            for (a, b) in ((0, 1), (0, 2), (1, 2)):
+                pa, pb = perm[a], perm[b]
+                idx.append(_PAIRS[(min(pa, pb), max(pa, pb))])
+                sgn.append(signs[a] * signs[b])
+            out_idx.append(idx)
+            out_sgn.append(sgn)
+    return np.array(out_idx), np.array(out_sgn, np.float32)
+
+
+def augment(raw, tgt, copies, seed=0):
+    """Training pairs plus `copies` images of each under random cube
+    symmetries (host numpy; data marshalling before upload)."""
+    idx, sgn = cube_symmetries()
+    rng = np.random.default_rng(seed)
+    raws, tgts = [raw], [tgt]
+    for _ in range(copies):
+        g = rng.integers(0, 48, raw.shape[0])
+        r = raw.copy()
+        r[:, :6] = np.take_along_axis(raw[:, :6], idx[g], axis=1) * sgn[g]
+        raws.append(r)
+        tgts.append(tgt)
+    return np.concatenate(raws), np.concatenate(tgts)
 
 
 def standardisation(raw):
@@ -284,6 +325,7 @@ def main(argv=None):
     ap.add_argument("--val-seeds", type=str, default="16-19")
     ap.add_argument("--test-seed", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--augment", type=int, default=3, help="phase train: symmetry images per training pair")
     ap.add_argument("--out", type=str, default="gpurun_out/les")
     ap.add_argument("--phase", choices=["data", "train", "eval"], default="data")
     ap.add_argument("--tau-f", type=float, default=TAU_F, help="relaxation time of the fine runs")
@@ -325,13 +367,15 @@ def main(argv=None):
     sid = np.concatenate([p["seed"] for p in parts])
     tr, va = seeds(args.train_seeds), seeds(args.val_seeds)
     mt, mv = np.isin(sid, tr), np.isin(sid, va)
-    P, hist, inv_scale = train(wlb, torch, raw[mt], tgt[mt], raw[mv], tgt[mv], epochs=args.epochs)
+    ra, ta = augment(raw[mt], tgt[mt], args.augment)
+    P, hist, inv_scale = train(wlb, torch, ra, ta, raw[mv], tgt[mv], epochs=args.epochs)
     np.save(os.path.join(args.out, "mlp_params.npy"), P)
     res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap, tau_f=args.tau_f,
                    keep_series=True)
     summary = {"n_fine": args.n, "factor": args.factor, "steps_fine": args.steps, "snap": args.snap,
                "tau_f": args.tau_f, "tau_coarse": coarse_tau(args.factor, args.tau_f),
                "train_seeds": tr, "val_seeds": va, "test_seed": args.test_seed, "train_pairs": int(mt.sum()),
+               "augment_images": args.augment,
                "val_pairs": int(mv.sum()), "history": hist, "inv_scale": inv_scale, "a_posteriori": res}
     with open(os.path.join(args.out, "summary.json"), "w") as fh:
         json.dump(summary, fh, indent=1)

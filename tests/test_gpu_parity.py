@@ -185,6 +185,48 @@ def test_block_decomposition_is_bitwise_invariant(storage):
                 assert np.array_equal(d, ref), f"layout {k} differs"
 
 
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+def test_x_wrap_with_solids_across_the_periodic_face_fp64(q, coll):
+    """One block periodic in x (x accesses wrap, no x exchange) with spheres
+    straddling the periodic x face, a body force and walls in y."""
+    say(f"case x-wrap solids q{q} coll{coll}")
+    dom = (24, 14, 12)
+    solid, frac, _ = inputs.spheres(dom, seed=5, rmin=2.0, rmax=3.5, solid_fraction=0.15, periodic=(1, 1, 1),
+                                    clear_x=0)
+    assert solid[:, :, 0].any() and solid[:, :, -1].any(), "spheres must cross the x face"
+    rho, u = inputs.random_state(dom, seed=6, umag=0.01)
+    F = (1e-5, 0, 2e-6)
+    p = wlb.make_params(tau=0.75, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, force=F)
+    gpu = gpu_run(wlb.single_block(dom), dom, (1, 0, 1), q, wlb.F64, coll, p, rho, u, solid, steps=7)
+    op = oracle_params(q, coll, 0.75, 3 / 16, (1, 0, 1), F, omega_bulk=1.2, omega_higher=1.0)
+    orc = oracle_run(op, dom, rho, u, solid, 7)
+    _compare(f"x-wrap q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_wrapping_and_exchanging_decompositions_agree_bitwise(storage):
+    """Periodic x: one block (x wraps), blocks split along y/z only (each
+    wraps in x, exchanges in y/z) and blocks split along x (x exchange) give
+    identical populations."""
+    say(f"case wrap decomposition storage{storage}")
+    dom = (32, 24, 16)
+    solid, _, _ = inputs.spheres(dom, seed=8, rmin=2.0, rmax=3.0, solid_fraction=0.1, periodic=(1, 1, 1), clear_x=0)
+    rho, u = inputs.random_state(dom, seed=9, umag=0.01)
+    p = wlb.make_params(tau=0.7, magic=3 / 16, force=(1e-5, 1e-6, 0))
+    layouts = [wlb.single_block(dom), inputs.rectilinear_blocks([32], [8, 16], [6, 10])[0],
+               inputs.rectilinear_blocks([8, 24], [24], [16])[0], inputs.uniform_blocks(dom, (16, 8, 8))[0]]
+    ref = {}
+    for k, bl in enumerate(layouts):
+        for steps in (8, 9):  # ends in the natural and in the swapped layout
+            d, r, uu, tot, B = gpu_run(bl, dom, (1, 1, 1), 19, storage, 1, p, rho, u, solid, steps=steps)
+            B.close()
+            if steps not in ref:
+                ref[steps] = (d, r, uu)
+            else:
+                assert np.array_equal(d, ref[steps][0]), f"layout {k} steps {steps}: populations differ"
+                assert np.array_equal(r, ref[steps][1]) and np.array_equal(uu, ref[steps][2]), f"layout {k} moments"
+
+
 def test_tiles_grid_graph_and_split_are_bitwise_invariant():
     say("case tiles/graph/split")
     dom = (40, 24, 20)
