@@ -71,23 +71,26 @@ __device__ __forceinline__ float bf16_round(float v) { return __uint_as_float((u
 // erfc(u) for u >= 0 from the Chebyshev-fitted form t exp(-u^2 + P(t)),
 // t = 1 / (1 + u / 2), of Numerical Recipes (2nd ed., Sec. 6.2), whose
 // fractional error is below 1.2e-7 for every u >= 0; Phi(z) = 1 - erfc/2 for
-// z >= 0.  One hardware reciprocal, one exp and a degree-9 polynomial, the
-// same for every lane, where a library erf takes divergent branches.
+// z >= 0.  The exponential is the hardware base-2 one: P's coefficients
+// below are NR's times log2(e), with the factor 1/2 folded into the constant
+// term (-1), and u^2 log2(e) = (|z| sqrt(log2(e) / 2))^2.  One reciprocal, one
+// exp2 and a degree-9 polynomial, the same for every lane.
 __device__ __forceinline__ float norm_cdf(float z)
 {
-    const float u = fabsf(z) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, u, 1.0f));  // 1 ulp; the divisor lies in [1, inf)
-    float p = 0.17087277f;
-    p = fmaf(p, t, -0.82215223f);
-    p = fmaf(p, t, 1.48851587f);
-    p = fmaf(p, t, -1.13520398f);
-    p = fmaf(p, t, 0.27886807f);
-    p = fmaf(p, t, -0.18628806f);
-    p = fmaf(p, t, 0.09678418f);
-    p = fmaf(p, t, 0.37409196f);
-    p = fmaf(p, t, 1.00002368f);
-    p = fmaf(p, t, -1.26551223f);
-    const float half_erfc = 0.5f * t * expf(fmaf(-u, u, p));
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.35355339059327376f, az, 1.0f));  // 1 / (1 + u/2), u = |z|/sqrt2
+    const float v = az * 0.8493218003f;
+    float p = 2.465172979e-01f;
+    p = fmaf(p, t, -1.186114945e+00f);
+    p = fmaf(p, t, 2.147474464e+00f);
+    p = fmaf(p, t, -1.637753152e+00f);
+    p = fmaf(p, t, 4.023215817e-01f);
+    p = fmaf(p, t, -2.687568603e-01f);
+    p = fmaf(p, t, 1.396300565e-01f);
+    p = fmaf(p, t, 5.397006155e-01f);
+    p = fmaf(p, t, 1.442729204e+00f);
+    p = fmaf(p, t, -2.825748218e+00f);
+    const float half_erfc = t * __builtin_amdgcn_exp2f(fmaf(-v, v, p));
     return z >= 0.f ? 1.0f - half_erfc : half_erfc;
 }
 

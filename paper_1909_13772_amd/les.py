@@ -234,11 +234,11 @@ def train(wlb, torch, raw, tgt, vraw, vtgt, epochs=200, batch=16384, lr=2e-3, se
     return best_P, hist, inv_scale
 
 
-def les_run(wlb, torch, rho_c, u_c, closure, params, steps, every, tau0):
+def les_run(wlb, torch, rho_c, u_c, closure, params, steps, every, tau0, cs=0.1):
     """Coarse LES from (rho_c, u_c); returns kinetic energy every `every`
     steps and the final spectrum (None on divergence)."""
     n = rho_c.shape[-1]
-    kw = dict(tau=tau0, closure=closure, cs_smag=0.1, health_every=every, health_umax=0.5)
+    kw = dict(tau=tau0, closure=closure, cs_smag=cs, health_every=every, health_umax=0.5)
     if closure == wlb.CLOSURE_MLP:
         kw["mlp"] = params
     B = wlb.Blocks(wlb.single_block((n, n, n)), (n, n, n), (1, 1, 1), stencil=19, storage=wlb.F32)
@@ -280,11 +280,13 @@ def compare(run, ref, kmax):
     return out
 
 
-def evaluate(wlb, torch, seed, params, n, factor, steps, snap, tau_f=TAU_F, keep_series=False):
-    """A-posteriori comparison on a held-out seed: the coarse LES without a
-    model, with Smagorinsky and with the network, each against the filtered
-    fine run.  keep_series adds the energy histories and final spectra."""
-    tau0 = coarse_tau(factor, tau_f)
+# Index of the output bias b3 in the packed parameters (the last value).
+B3 = 7 + 7 + 32 * 7 + 32 + 32 * 32 + 32 + 32
+
+
+def reference(wlb, torch, seed, n, factor, steps, snap, tau_f=TAU_F):
+    """Filtered fine run of one seed: the coarse initial state, the filtered
+    kinetic energy every `snap` fine steps and the final shell spectrum."""
     fr = FineRun(wlb, torch, seed, n, factor, tau_f=tau_f)
     rho_c, u_c = fr.coarse_state()
     energy = []
@@ -294,13 +296,63 @@ def evaluate(wlb, torch, seed, params, n, factor, steps, snap, tau_f=TAU_F, keep
         energy.append(filtered_energy(fr.filtered()))
     _, u_end = fr.coarse_state()
     fr.close()
-    ref = {"energy": energy, "spectrum": shell_spectrum(u_end).tolist()}
+    return rho_c, u_c, {"energy": energy, "spectrum": shell_spectrum(u_end).tolist()}
+
+
+def energy_error(run, ref):
+    """Time-averaged relative kinetic-energy error of a coarse run against the
+    filtered fine run (infinite when the coarse run blew up)."""
+    if run["diverged"]:
+        return float("inf")
+    e = np.asarray(run["energy"])
+    er = np.asarray(ref["energy"])[: len(e)]
+    return float(np.mean(np.abs(e - er) / er))
+
+
+def calibrate(wlb, torch, params, seeds, n, factor, steps, snap, tau_f=TAU_F,
+              gains=(0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0), cs_values=(0.06, 0.08, 0.1, 0.13, 0.16, 0.2, 0.25)):
+    """A-posteriori calibration with the fine solver as judge: on held-out
+    seeds, pick the gain g of the network's correction (applied as
+    b3 += ln g, which scales softplus(o) by g wherever the correction is
+    small, as it is here) and, for a fair comparison, the Smagorinsky
+    constant, each minimising the time-averaged energy error."""
+    tau0 = coarse_tau(factor, tau_f)
+    csteps, cevery = steps // factor, snap // factor
+    refs = [reference(wlb, torch, sd, n, factor, steps, snap, tau_f) for sd in seeds]
+    table = {"gain": {}, "cs": {}}
+    for g in gains:
+        P = params.copy()
+        P[B3] += np.float32(math.log(g))
+        errs = [energy_error(les_run(wlb, torch, rc, uc, wlb.CLOSURE_MLP, P, csteps, cevery, tau0), ref)
+                for rc, uc, ref in refs]
+        table["gain"][str(g)] = float(np.mean(errs))
+        _log(f"[les] calibration gain {g}: energy error {table['gain'][str(g)]:.4f}")
+    for cs in cs_values:
+        errs = [energy_error(les_run(wlb, torch, rc, uc, wlb.CLOSURE_SMAG, None, csteps, cevery, tau0, cs=cs), ref)
+                for rc, uc, ref in refs]
+        table["cs"][str(cs)] = float(np.mean(errs))
+        _log(f"[les] calibration C_s {cs}: energy error {table['cs'][str(cs)]:.4f}")
+    g_best = float(min(table["gain"], key=lambda k: table["gain"][k]))
+    cs_best = float(min(table["cs"], key=lambda k: table["cs"][k]))
+    return g_best, cs_best, table
+
+
+def evaluate(wlb, torch, seed, params, n, factor, steps, snap, tau_f=TAU_F, keep_series=False, variants=None):
+    """A-posteriori comparison on a held-out seed: the coarse LES without a
+    model, with Smagorinsky and with the network (and any extra
+    (name, closure, params, C_s) variants), each against the filtered fine
+    run.  keep_series adds the energy histories and final spectra."""
+    tau0 = coarse_tau(factor, tau_f)
+    rho_c, u_c, ref = reference(wlb, torch, seed, n, factor, steps, snap, tau_f)
     csteps, cevery = steps // factor, snap // factor
     nc = n // factor
     res = {}
-    for name, cl in (("none", wlb.CLOSURE_NONE), ("smagorinsky", wlb.CLOSURE_SMAG), ("mlp", wlb.CLOSURE_MLP)):
-        r = les_run(wlb, torch, rho_c, u_c, cl, params, csteps, cevery, tau0)
-        res[name] = {"diverged": r["diverged"], "mlups": r.get("mlups"), **compare(r, ref, nc // 2)}
+    runs = [("none", wlb.CLOSURE_NONE, None, 0.1), ("smagorinsky", wlb.CLOSURE_SMAG, None, 0.1),
+            ("mlp", wlb.CLOSURE_MLP, params, 0.1)] + list(variants or [])
+    for name, cl, P, cs in runs:
+        r = les_run(wlb, torch, rho_c, u_c, cl, P, csteps, cevery, tau0, cs=cs)
+        res[name] = {"diverged": r["diverged"], "mlups": r.get("mlups"), "energy_err_mean": energy_error(r, ref),
+                     **compare(r, ref, nc // 2)}
         e, er = np.asarray(r["energy"]), np.asarray(ref["energy"])[: len(r["energy"])]
         res[name]["energy_ratio_final"] = float(e[-1] / er[-1])
         if keep_series:
@@ -326,10 +378,16 @@ def main(argv=None):
     ap.add_argument("--test-seed", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--augment", type=int, default=3, help="phase train: symmetry images per training pair")
+    ap.add_argument("--calib-seeds", type=str, default="16-17", help="phase train: seeds of the a-posteriori calibration")
     ap.add_argument("--out", type=str, default="gpurun_out/les")
-    ap.add_argument("--phase", choices=["data", "train", "eval"], default="data")
+    ap.add_argument("--phase", choices=["data", "train", "calib", "eval"], default="data")
+    ap.add_argument("--gains", type=str, default="0.15,0.25,0.35,0.5,0.7,1.0,1.5",
+                    help="calibration: gains of the network's correction")
+    ap.add_argument("--cs-values", type=str, default="0.03,0.045,0.06,0.08,0.1,0.13",
+                    help="calibration: Smagorinsky constants")
     ap.add_argument("--tau-f", type=float, default=TAU_F, help="relaxation time of the fine runs")
-    ap.add_argument("--params", type=str, default="", help="phase eval: network parameters (.npy); default seeded")
+    ap.add_argument("--params", type=str, default="",
+                    help="phase eval / calib: network parameters (.npy); eval defaults to seeded ones")
     ap.add_argument("--data", type=str, default="", help="phase train: comma-separated npz files of pairs")
     args = ap.parse_args(argv)
 
@@ -361,22 +419,37 @@ def main(argv=None):
         with open(os.path.join(args.out, f"eval_seed{args.test_seed}_tauf{args.tau_f}.json"), "w") as fh:
             json.dump(res, fh)
         return 0
-    parts = [np.load(f) for f in args.data.split(",") if f]
-    raw = np.concatenate([p["raw"] for p in parts])
-    tgt = np.concatenate([p["tgt"] for p in parts])
-    sid = np.concatenate([p["seed"] for p in parts])
     tr, va = seeds(args.train_seeds), seeds(args.val_seeds)
-    mt, mv = np.isin(sid, tr), np.isin(sid, va)
-    ra, ta = augment(raw[mt], tgt[mt], args.augment)
-    P, hist, inv_scale = train(wlb, torch, ra, ta, raw[mv], tgt[mv], epochs=args.epochs)
-    np.save(os.path.join(args.out, "mlp_params.npy"), P)
-    res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap, tau_f=args.tau_f,
-                   keep_series=True)
     summary = {"n_fine": args.n, "factor": args.factor, "steps_fine": args.steps, "snap": args.snap,
-               "tau_f": args.tau_f, "tau_coarse": coarse_tau(args.factor, args.tau_f),
-               "train_seeds": tr, "val_seeds": va, "test_seed": args.test_seed, "train_pairs": int(mt.sum()),
-               "augment_images": args.augment,
-               "val_pairs": int(mv.sum()), "history": hist, "inv_scale": inv_scale, "a_posteriori": res}
+               "tau_f": args.tau_f, "tau_coarse": coarse_tau(args.factor, args.tau_f), "train_seeds": tr,
+               "val_seeds": va, "test_seed": args.test_seed}
+    if args.phase == "train":
+        parts = [np.load(f) for f in args.data.split(",") if f]
+        raw = np.concatenate([p["raw"] for p in parts])
+        tgt = np.concatenate([p["tgt"] for p in parts])
+        sid = np.concatenate([p["seed"] for p in parts])
+        mt, mv = np.isin(sid, tr), np.isin(sid, va)
+        ra, ta = augment(raw[mt], tgt[mt], args.augment)
+        P, hist, inv_scale = train(wlb, torch, ra, ta, raw[mv], tgt[mv], epochs=args.epochs)
+        np.save(os.path.join(args.out, "mlp_params_apriori.npy"), P)
+        summary.update({"train_pairs": int(mt.sum()), "val_pairs": int(mv.sum()), "augment_images": args.augment,
+                        "history": hist, "inv_scale": inv_scale})
+    else:  # calib: the a-priori network from an earlier training run
+        P = np.load(args.params)
+        summary["params"] = args.params
+    cal_seeds = seeds(args.calib_seeds)
+    gains = tuple(float(v) for v in args.gains.split(","))
+    cs_values = tuple(float(v) for v in args.cs_values.split(","))
+    g, cs, table = calibrate(wlb, torch, P, cal_seeds, args.n, args.factor, args.steps, args.snap, tau_f=args.tau_f,
+                             gains=gains, cs_values=cs_values)
+    Pc = P.copy()
+    Pc[B3] += np.float32(math.log(g))
+    np.save(os.path.join(args.out, "mlp_params.npy"), Pc)
+    res = evaluate(wlb, torch, args.test_seed, P, args.n, args.factor, args.steps, args.snap, tau_f=args.tau_f,
+                   keep_series=True, variants=[("smagorinsky_calibrated", wlb.CLOSURE_SMAG, None, cs),
+                                               ("mlp_calibrated", wlb.CLOSURE_MLP, Pc, 0.1)])
+    summary.update({"calibration_seeds": cal_seeds, "calibration": table, "gain": g, "cs_calibrated": cs,
+                    "a_posteriori": res})
     with open(os.path.join(args.out, "summary.json"), "w") as fh:
         json.dump(summary, fh, indent=1)
     return 0

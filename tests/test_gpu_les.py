@@ -54,7 +54,41 @@ def test_learned_closure_pipeline_small():
     P, hist, _ = les.train(wlb, torch, raw, tgt, vraw, vtgt, epochs=3, batch=256)
     assert np.all(np.isfinite(P)) and len(hist) == 3
     assert hist[-1]["train_loss"] <= hist[0]["train_loss"] * 1.5
-    res = les.evaluate(wlb, torch, 3, P, n, f, 40, 20)
-    for name in ("none", "smagorinsky", "mlp"):
+    g, cs, table = les.calibrate(wlb, torch, P, [2], n, f, 40, 20, gains=(1.0, 2.0), cs_values=(0.1, 0.2))
+    assert g in (1.0, 2.0) and cs in (0.1, 0.2) and len(table["gain"]) == 2
+    Pc = P.copy()
+    Pc[les.B3] += np.float32(np.log(g))
+    res = les.evaluate(wlb, torch, 3, P, n, f, 40, 20, variants=[("mlp_calibrated", wlb.CLOSURE_MLP, Pc, 0.1)])
+    for name in ("none", "smagorinsky", "mlp", "mlp_calibrated"):
         assert name in res
     assert not res["smagorinsky"]["diverged"]
+
+
+def test_trained_closure_keeps_the_coarse_les_stable():
+    """What the trained network gains over the method without it, at the
+    closure's own working point (128^3, tau0 = 0.5025, decaying turbulence):
+    without a model the coarse run blows up within 2000 steps; with the
+    committed trained network (and with Smagorinsky) it stays healthy and
+    its kinetic energy decays.  The full comparison against the filtered
+    512^3 fine run is recorded in paper_1909_13772_amd/mlp_closure_record.json
+    (written by `python -m paper_1909_13772_amd.les --phase calib`)."""
+    import os
+
+    from paper_1909_13772_amd import les
+    say("case trained closure stability 128^3")
+    path = os.path.join(os.path.dirname(les.__file__), "mlp_closure.npy")
+    P = np.load(path)
+    assert P.shape == (wlb.MLP_NPARAM,)
+    n = 128
+    rho, u = inputs.turbulence_bandlimited(n, 20)
+    tau0 = les.coarse_tau(4)
+    runs = {}
+    for name, cl in (("none", wlb.CLOSURE_NONE), ("smagorinsky", wlb.CLOSURE_SMAG), ("mlp", wlb.CLOSURE_MLP)):
+        runs[name] = les.les_run(wlb, torch, rho, u, cl, P if cl == wlb.CLOSURE_MLP else None, 2000, 100, tau0)
+        say(f"{name}: diverged {runs[name]['diverged']}, energy {runs[name]['energy'][:1]} -> {runs[name]['energy'][-1:]}")
+    assert runs["none"]["diverged"]
+    for name in ("smagorinsky", "mlp"):
+        r = runs[name]
+        assert not r["diverged"] and len(r["energy"]) == 21
+        e = np.asarray(r["energy"])
+        assert np.all(np.isfinite(e)) and e[-1] < 0.5 * e[0]

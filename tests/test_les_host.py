@@ -60,3 +60,18 @@ def test_shell_spectrum_single_mode():
     # mean of u^2 / 2 over the box, all of it in shell k = 3
     assert abs(e[3] - 0.5 * 0.1 ** 2 / 2) < 1e-15
     assert abs(e.sum() - e[3]) < 1e-15
+
+
+def test_output_bias_index_is_the_last_parameter():
+    # packed layout mean[7], inv_std[7], W1[32][7], b1[32], W2[32][32], b2[32], w3[32], b3
+    from paper_1909_13772_amd import inputs
+    P = inputs.mlp_params(0, out_bias=-3.25)
+    assert les.B3 == P.size - 1 == 1358 and P[les.B3] == np.float32(-3.25)
+
+
+def test_gain_as_output_bias_shift():
+    # g softplus(o) ~ softplus(o + ln g) where softplus(o) is small
+    o = np.linspace(-10.0, -5.0, 11)
+    sp = np.log1p(np.exp(o))
+    for g in (0.5, 2.0, 6.0):
+        assert np.all(np.abs(np.log1p(np.exp(o + np.log(g))) / (g * sp) - 1) < 0.02)
