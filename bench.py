@@ -108,6 +108,7 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
             s = np.arange(N) + 0.5
             ref = poiseuille_series(N, nu, FX, warmup + steps, s)
             prof = uu[0].mean(axis=(0, 2))
+            res["profile"] = prof
             res["poiseuille_err"] = float(np.abs(prof - ref).max() / ref.max())
             res["mass_drift"] = float(abs(tot[0] - N ** 3) / N ** 3)
         return res
@@ -226,18 +227,24 @@ def main():
           f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     variants = {}
     if not args.no_variants:
+        # FP64 reference profile after the variants' step count (accuracy of each variant)
+        import numpy as np
+        r64 = run_config(wlb, inputs, wlb.F64, args.variant_steps, args.warmup, check=True, autotune=False)
+        p64 = r64["profile"]
         for name, st, eb, cl, q, coll in (("f32", wlb.F32, 4, 0, 19, None), ("f16dev", wlb.F16DEV, 2, 0, 19, None),
                                           ("bf16dev", wlb.BF16DEV, 2, 0, 19, None),
                                           ("f32_smagorinsky", wlb.F32, 4, 1, 19, None),
                                           ("f32_mlp_closure", wlb.F32, 4, 2, 19, None),
                                           ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT)):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
-                           q=q, coll=coll)
+                           q=q, coll=coll, check=True)
             sm = summarize(r, st, args.variant_steps, eb, q=q)
             variants[name] = {"mlups": round(sm["mlups"], 1), "roofline_frac": round(sm["frac"], 4),
                               "achieved_gbs": round(sm["achieved_gbs"], 1), "sweep_ms": round(sm["sweep_ms"], 4),
                               "even_ms": round(sm["even_ms"], 4), "odd_ms": round(sm["odd_ms"], 4),
-                              "steps": args.variant_steps}
+                              "steps": args.variant_steps,
+                              "profile_rel_err_vs_f64": float(np.linalg.norm(r["profile"] - p64) / np.linalg.norm(p64)),
+                              "poiseuille_rel_err": r["poiseuille_err"]}
             print(f"[bench] {name}: {sm['mlups']:.0f} MLUPS, {sm['achieved_gbs']:.0f} GB/s", file=sys.stderr,
                   flush=True)
     try:

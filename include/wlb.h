@@ -182,7 +182,8 @@ typedef struct {
     int64_t n_fluid;        /* fluid cells */
     int32_t n_tiles;
     int32_t tile[3];        /* tile shape target in use (x, y, z) */
-    int32_t grid;           /* workgroups per sweep launch (0 = one per tile) */
+    int32_t grid;           /* workgroups per sweep launch (0 = one per tile, -1 = one per tile
+                               with XCD-contiguous tile ranges) */
     int32_t lds_staging;    /* 1: the odd sweep stages x-shifted populations in LDS */
     int32_t n_xchg_items;   /* exchange work items per exchange */
     int64_t xchg_elems;     /* populations copied per exchange */
@@ -192,7 +193,13 @@ typedef struct {
 int wlb_info(wlb_blocks_t h, wlb_info_t *out);
 
 /* Use tile shape (tx, ty, tz) (tx*ty*tz <= 256) and `grid` workgroups per
- * sweep launch (0 = one workgroup per tile) from now on. */
+ * sweep launch from now on: 0 = one workgroup per tile (workgroups reach the
+ * 8 XCDs round-robin); -1 = one workgroup per tile, the workgroups of each
+ * XCD taking one contiguous range of tiles (and of exchange items), so that
+ * neighbouring tiles share an L2; > 0 = a persistent grid of that many
+ * workgroups looping over the tiles.  tx = 0 packs whole x rows.
+ * Errors: WLB_ERR_ARG (shape above 256 cells, grid < -1, more tiles than the
+ * arena's tile table holds). */
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid);
 
 /* Stage (1) or not (0, default) the odd sweep's x-shifted populations in LDS

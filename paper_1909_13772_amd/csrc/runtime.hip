@@ -46,7 +46,9 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Tile-shape candidates of the autotuner; (0,0,0) packs whole rows.
 const int kShapes[][3] = {{0, 0, 0}, {64, 4, 1}, {32, 8, 1}, {32, 4, 2}, {16, 16, 1}, {16, 4, 4},
                           {128, 2, 1}, {256, 1, 1}, {64, 2, 2}, {8, 8, 4}};
-const int kGrids[] = {0, 1024, 2048, 4096};
+// 0: one workgroup per tile; -1: the same with XCD-contiguous tile ranges;
+// > 0: persistent grid of that many workgroups
+const int kGrids[] = {0, -1, 1024, 2048, 4096};
 
 struct HostBlock {
     int org[3], n[3];
@@ -183,6 +185,7 @@ int set_tiles(wlb_blocks *h, int tx, int ty, int tz, int grid)
     h->shape[1] = ty;
     h->shape[2] = tz;
     h->grid = grid;
+    h->args.xcd_map = grid == -1 ? 1 : 0;
     h->graph_valid = false;
     if (h->bound) return upload_tiles(h);
     return WLB_OK;
@@ -214,11 +217,12 @@ hipError_t exchange_dispatch(const wlb_blocks *h, bool after_odd)
     const uint32_t *masks = reinterpret_cast<const uint32_t *>(h->arena + h->off_mask);
     void *pops = h->arena + h->off_pop;
     const int n = (int)v.size();
+    const int xm = h->args.xcd_map;
     switch (h->storage) {
-    case WLB_F64: return exchange_f64(pops, blocks, masks, items, n, h->stream);
-    case WLB_F32: return exchange_f32(pops, blocks, masks, items, n, h->stream);
-    case WLB_F16DEV: return exchange_f16(pops, blocks, masks, items, n, h->stream);
-    default: return exchange_bf16(pops, blocks, masks, items, n, h->stream);
+    case WLB_F64: return exchange_f64(pops, blocks, masks, items, n, xm, h->stream);
+    case WLB_F32: return exchange_f32(pops, blocks, masks, items, n, xm, h->stream);
+    case WLB_F16DEV: return exchange_f16(pops, blocks, masks, items, n, xm, h->stream);
+    default: return exchange_bf16(pops, blocks, masks, items, n, xm, h->stream);
     }
 }
 
@@ -1030,7 +1034,8 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid)
 {
     if (!h) return fail(WLB_ERR_ARG, "null handle");
-    if (tx < 0 || ty < 0 || tz < 0 || grid < 0) return fail(WLB_ERR_ARG, "negative tile shape");
+    if (tx < 0 || ty < 0 || tz < 0) return fail(WLB_ERR_ARG, "negative tile shape");
+    if (grid < -1) return fail(WLB_ERR_ARG, "grid must be -1, 0 or a workgroup count");
     if (tx != 0 && (ty < 1 || tz < 1 || (int64_t)tx * ty * tz > kWG))
         return fail(WLB_ERR_ARG, "tile shape must have at most %d cells", kWG);
     return set_tiles(h, tx, ty, tz, grid);

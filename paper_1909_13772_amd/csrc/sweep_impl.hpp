@@ -512,6 +512,23 @@ struct CellPos {
     bool valid;
 };
 
+// Item handled by workgroup b when a launch gives every item (tile,
+// exchange chunk) its own workgroup.  Workgroups are dispatched round-robin
+// over the 8 XCDs, each with its own L2; this mapping hands every XCD one
+// contiguous range of items, so that neighbouring tiles, which share cache
+// lines at their edges (packed short rows, row ends), meet in the same L2.
+__device__ __forceinline__ int xcd_item(int b, int n)
+{
+    constexpr int kXcd = 8;
+    const int q = n / kXcd, r = n % kXcd;
+    const int k = b % kXcd, j = b / kXcd;
+    return k * q + (k < r ? k : r) + j;
+}
+__device__ __forceinline__ int first_tile(const SweepArgs &a)
+{
+    return (a.xcd_map && (int)gridDim.x == a.ntiles) ? xcd_item(blockIdx.x, a.ntiles) : (int)blockIdx.x;
+}
+
 __device__ __forceinline__ CellPos tile_cell(const int4 tv, int l)
 {
     const int ex = tv.y >> 16, ey = tv.z >> 16, ez = tv.w >> 16;
@@ -717,7 +734,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
     const SweepArgs a)
 {
     using T = typename Codec<ST>::T;
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    for (int t = first_tile(a); t < a.ntiles; t += gridDim.x) {
         const CollParams<T> cp = coll_params<T>(a);
         const int4 tv = a.tiles[t];
         const CellPos c = tile_cell(tv, threadIdx.x);
@@ -781,7 +798,7 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
     uint32_t *info = reinterpret_cast<uint32_t *>(smem + ((2 * (size_t)NSH * stride * sizeof(Raw) + 15) & ~15ull));
     const CollParams<T> cp = coll_params<T>(a);
     const int l = threadIdx.x;
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    for (int t = first_tile(a); t < a.ntiles; t += gridDim.x) {
         const int4 tv = a.tiles[t];
         const int ex = tv.y >> 16, ey = tv.z >> 16, ez = tv.w >> 16;
         const bool valid = l < ex * ey * ez;
@@ -899,7 +916,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     __shared__ T park[Q][kWG];
     mlp_stage(&net_s, a.mlp);
     const MlpDev *net = &net_s;
-    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    for (int t = first_tile(a); t < a.ntiles; t += gridDim.x) {
         const int4 tv = a.tiles[t];
         const CellPos c = tile_cell(tv, threadIdx.x);
         const DevBlock B = a.blocks[tv.x];
@@ -1179,9 +1196,9 @@ __global__ __launch_bounds__(kWG) void pdfs_kernel(const SweepArgs a, double *bu
 // ---------------------------------------------------------------------------
 template <typename Raw>
 __global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBlock *blocks, const uint32_t *masks,
-                                                       const XItem *items)
+                                                       const XItem *items, int xcd_map)
 {
-    const XItem &it = items[blockIdx.x];
+    const XItem &it = items[xcd_map ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x];
     const int l = threadIdx.x;
     if (l >= it.count) return;
     const int r = it.start + l;
@@ -1323,12 +1340,12 @@ hipError_t WLB_CAT(filter_, WLB_SUFFIX)(int q, const SweepArgs &a, int fac, doub
 }
 
 hipError_t WLB_CAT(exchange_, WLB_SUFFIX)(void *arena, const DevBlock *blocks, const uint32_t *masks,
-                                          const XItem *items, int nitems, hipStream_t st)
+                                          const XItem *items, int nitems, int xcd_map, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
     using Raw = typename Codec<WLB_STORAGE>::Raw;
     hipLaunchKernelGGL((exchange_kernel<Raw>), dim3(nitems), dim3(kWG), 0, st, reinterpret_cast<Raw *>(arena),
-                       blocks, masks, items);
+                       blocks, masks, items, xcd_map);
     return hipGetLastError();
 }
 

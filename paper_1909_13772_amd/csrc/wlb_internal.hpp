@@ -71,6 +71,7 @@ struct SweepArgs {
     int32_t pressure_axis; // -1 or axis
     int32_t closure;
     int32_t lds_stride;    // > 0: odd sweep stages x-shifted populations in LDS rows of this many elements
+    int32_t xcd_map;       // 1: one workgroup per tile, each XCD takes a contiguous range of tiles
     double omega;          // 1 / tau0
     double omega_minus;    // TRT rate of the antisymmetric part at tau0
     double magic;          // TRT Lambda
@@ -100,7 +101,7 @@ struct MomArgs {
     hipError_t pdfs_##S(int q, const SweepArgs &a, double *buf, int z0, int z1, bool to_device, bool swapped, \
                         int grid, hipStream_t st);                                                            \
     hipError_t exchange_##S(void *arena, const DevBlock *blocks, const uint32_t *masks, const XItem *items,   \
-                            int nitems, hipStream_t st);                                                      \
+                            int nitems, int xcd_map, hipStream_t st);                                         \
     hipError_t filter_##S(int q, const SweepArgs &a, int fac, double *out, int64_t ncoarse, bool swapped,       \
                           hipStream_t st);
 WLB_DECLARE_LAUNCHERS(f64)

@@ -234,7 +234,8 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
     blocks = inputs.rectilinear_blocks([16, 24], [24], [12, 8])[0]
     p = wlb.make_params(tau=0.66, magic=3 / 16, force=(1e-5, 0, 0))
     runs = [dict(), dict(tiles=(16, 4, 4, 0)), dict(tiles=(64, 4, 1, 7)), dict(tiles=(8, 8, 4, 3)),
-            dict(graph=False), dict(mode="split"), dict(lds=False), dict(lds=False, tiles=(16, 4, 4, 0))]
+            dict(graph=False), dict(mode="split"), dict(lds=False), dict(lds=False, tiles=(16, 4, 4, 0)),
+            dict(tiles=(0, 0, 0, -1)), dict(tiles=(16, 4, 4, -1), mode="split")]
     ref = None
     for kw in runs:
         d, r, uu, tot, B = gpu_run(blocks, dom, (1, 1, 0), 19, wlb.F32, wlb.TRT, p, rho, u, solid, steps=13, **kw)
