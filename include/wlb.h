@@ -181,7 +181,7 @@ typedef struct {
     int64_t n_cells;        /* interior cells of all blocks */
     int64_t n_fluid;        /* fluid cells */
     int32_t n_tiles;
-    int32_t tile[3];        /* tile shape target in use (x, y, z) */
+    int32_t tile[3];        /* tile shape target in use (x, y, z); -1, 0, 0: fluid-cell lists */
     int32_t grid;           /* workgroups per sweep launch (0 = one per tile, -1 = one per tile
                                with XCD-contiguous tile ranges) */
     int32_t lds_staging;    /* 1: the odd sweep stages x-shifted populations in LDS */
@@ -197,9 +197,13 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *out);
  * 8 XCDs round-robin); -1 = one workgroup per tile, the workgroups of each
  * XCD taking one contiguous range of tiles (and of exchange items), so that
  * neighbouring tiles share an L2; > 0 = a persistent grid of that many
- * workgroups looping over the tiles.  tx = 0 packs whole x rows.
+ * workgroups looping over the tiles.  tx = 0 packs whole x rows; tx = -1
+ * makes the sweeps run over lists of up to 256 fluid cells of one block
+ * (no lanes on solid cells; needs a preceding wlb_lbm_init with solid cells
+ * and blocks of at most 1024 x 1024 x 4096 cells), all other passes over
+ * whole-row tiles.
  * Errors: WLB_ERR_ARG (shape above 256 cells, grid < -1, more tiles than the
- * arena's tile table holds). */
+ * arena's tile table holds), WLB_ERR_STATE (tx = -1 without fluid lists). */
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid);
 
 /* Stage (1) or not (0, default) the odd sweep's x-shifted populations in LDS

@@ -6,6 +6,7 @@
 // same device being a direct copy without buffers (Sec. 3.3).  Host arrays
 // are copied in at set-up and out after many steps (Sec. 4.3).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -68,7 +69,7 @@ struct wlb_blocks {
     // arena layout (bytes)
     size_t off_pop = 0, pop_bytes = 0, off_mask = 0, mask_words = 0, off_blocks = 0, off_tiles = 0,
            tile_cap = 0, off_pull = 0, off_push = 0, off_partials = 0, off_totals = 0, off_stage = 0,
-           stage_bytes = 0, off_mlp = 0, arena_bytes = 0;
+           stage_bytes = 0, off_mlp = 0, arena_bytes = 0, off_cells = 0, off_ltiles = 0, ltile_cap = 0;
     char *arena = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false, inited = false;
@@ -80,6 +81,10 @@ struct wlb_blocks {
     int parity = 0;       // 0 natural layout, 1 swapped (after an even sweep)
     int pending = 0;      // 0 none, 1 pull due (after even), 2 push due (after odd)
     bool any_wrap = false;  // some block wraps its x accesses (no LDS-staged odd sweep then)
+    // sweep tiles as lists of fluid cells (porous media); available after an
+    // init with solid cells when every block fits the 10/10/12-bit packing
+    bool list_ok = false, list_built = false, list_mode = false;
+    std::vector<int4> ltiles;
     int last_sweep = -1;  // parity of the last sweep (-1: none since init / set)
     int shape[3] = {0, 0, 0};
     int grid = 0;
@@ -156,7 +161,7 @@ void update_lds_stride(wlb_blocks *h)
     const int nsh = h->q == 19 ? 10 : 18;
     const size_t bytes = ((2 * (size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
     // the staged odd sweep keeps the ghost-layer addressing along x
-    h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->any_wrap) ? stride : 0;
+    h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->any_wrap && !h->list_mode) ? stride : 0;
     h->graph_valid = false;
 }
 
@@ -171,20 +176,31 @@ int upload_tiles(wlb_blocks *h)
                           hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->args.ntiles = (int)h->tiles.size();
+    if (h->list_mode) {
+        h->args.stiles = reinterpret_cast<const int4 *>(h->arena + h->off_ltiles);
+        h->args.nstiles = (int)h->ltiles.size();
+    } else {
+        h->args.stiles = h->args.tiles;
+        h->args.nstiles = h->args.ntiles;
+    }
     update_lds_stride(h);
     return WLB_OK;
 }
 
 int set_tiles(wlb_blocks *h, int tx, int ty, int tz, int grid)
 {
+    // tx = -1: sweeps over lists of fluid cells, whole-row boxes elsewhere
+    const bool list = tx == -1;
+    if (list && !h->list_built) return fail(WLB_ERR_STATE, "fluid-cell tiles need an init with solid cells");
     std::vector<TileHost> t;
-    build_tiles(h, tx, ty, tz, t);
+    build_tiles(h, list ? 0 : tx, ty, tz, t);
     if (t.size() > h->tile_cap) return fail(WLB_ERR_ARG, "tile shape yields %zu tiles > capacity", t.size());
     h->tiles.swap(t);
     h->shape[0] = tx;
     h->shape[1] = ty;
     h->shape[2] = tz;
     h->grid = grid;
+    h->list_mode = list;
     h->args.xcd_map = grid == -1 ? 1 : 0;
     h->graph_valid = false;
     if (h->bound) return upload_tiles(h);
@@ -193,7 +209,7 @@ int set_tiles(wlb_blocks *h, int tx, int ty, int tz, int grid)
 
 int launch_grid(const wlb_blocks *h)
 {
-    const int n = (int)h->tiles.size();
+    const int n = (int)(h->list_mode ? h->ltiles.size() : h->tiles.size());
     if (h->grid <= 0 || h->grid > n) return n > 0 ? n : 1;
     return h->grid;
 }
@@ -470,8 +486,11 @@ int autotune(wlb_blocks *h)
     const bool log = env && env[0] == '1';
     for (int lds = 0; lds <= 1; ++lds) {
         h->lds_stage = lds != 0;
-        for (const auto &s : kShapes) {
-            if (count_tiles(h, s[0], s[1], s[2]) > h->tile_cap) continue;
+        std::vector<std::array<int, 3>> shapes;
+        for (const auto &s : kShapes) shapes.push_back({s[0], s[1], s[2]});
+        if (h->list_built) shapes.push_back({-1, 0, 0});
+        for (const auto &s : shapes) {
+            if (s[0] >= 0 && count_tiles(h, s[0], s[1], s[2]) > h->tile_cap) continue;
             for (int g : kGrids) {
                 int rc = set_tiles(h, s[0], s[1], s[2], g);
                 if (rc) return rc;
@@ -653,6 +672,17 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     h->tile_cap = cap;
     h->off_tiles = off;
     off += round_up(cap * sizeof(int4), 256);
+    // fluid-cell lists (every interior cell at most once) and their tiles
+    h->list_ok = true;
+    for (const HostBlock &B : h->blocks)
+        if (B.n[0] > 1024 || B.n[1] > 1024 || B.n[2] > 4096) h->list_ok = false;
+    if (h->list_ok) {
+        h->off_cells = off;
+        off += round_up((size_t)h->ncells * 4, 256);
+        h->ltile_cap = (size_t)h->ncells / kWG + n + 1;
+        h->off_ltiles = off;
+        off += round_up(h->ltile_cap * sizeof(int4), 256);
+    }
     // --- exchange work lists
     for (int b = 0; b < n; ++b) {
         const HostBlock &A = h->blocks[b];
@@ -770,6 +800,7 @@ int wlb_blocks_bind(wlb_blocks_t h, void *arena, size_t bytes, void *stream)
     h->args.arena = h->arena + h->off_pop;
     h->args.blocks = reinterpret_cast<const DevBlock *>(h->arena + h->off_blocks);
     h->args.tiles = reinterpret_cast<const int4 *>(h->arena + h->off_tiles);
+    h->args.cells = reinterpret_cast<const uint32_t *>(h->arena + h->off_cells);
     h->args.masks = reinterpret_cast<const uint32_t *>(h->arena + h->off_mask);
     h->args.mlp = h->arena + h->off_mlp;
     for (int a = 0; a < 3; ++a) h->args.dom[a] = h->dom[a];
@@ -857,6 +888,43 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
         HIPCHK(launch_masks(h->args, reinterpret_cast<const uint8_t *>(h->arena + h->off_stage), h->q, aux_grid(h),
                             h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    // fluid-cell lists for list tiles
+    h->list_built = false;
+    h->ltiles.clear();
+    if (solid && nsolid > 0 && h->list_ok) {
+        std::vector<uint32_t> cells;
+        cells.reserve((size_t)h->nfluid);
+        for (size_t b = 0; b < h->blocks.size(); ++b) {
+            const HostBlock &B = h->blocks[b];
+            const size_t first = cells.size();
+            for (int z = 0; z < B.n[2]; ++z)
+                for (int y = 0; y < B.n[1]; ++y)
+                    for (int x = 0; x < B.n[0]; ++x) {
+                        const int64_t g = ((int64_t)(B.org[2] + z) * h->dom[1] + (B.org[1] + y)) * h->dom[0] +
+                                          (B.org[0] + x);
+                        if (!solid[g]) cells.push_back((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20));
+                    }
+            for (size_t k = first; k < cells.size(); k += kWG)
+                h->ltiles.push_back(make_int4((int)b, (int)k, 0, -(int)std::min<size_t>(kWG, cells.size() - k)));
+        }
+        if (h->ltiles.size() <= h->ltile_cap && !cells.empty()) {
+            HIPCHK(hipMemcpyAsync(h->arena + h->off_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice,
+                                  h->stream));
+            HIPCHK(hipMemcpyAsync(h->arena + h->off_ltiles, h->ltiles.data(), h->ltiles.size() * sizeof(int4),
+                                  hipMemcpyHostToDevice, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            h->list_built = true;
+        } else {
+            h->ltiles.clear();
+        }
+    }
+    if (h->list_mode && !h->list_built) {
+        const int rc0 = set_tiles(h, 0, 0, 0, h->grid);
+        if (rc0) return rc0;
+    } else {
+        const int rc0 = upload_tiles(h);  // list tiles may have changed
+        if (rc0) return rc0;
     }
     int rc = do_init_state(h, rho, u);
     if (rc) return rc;
@@ -1020,7 +1088,7 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
     o->n_blocks = (int32_t)h->blocks.size();
     o->n_cells = h->ncells;
     o->n_fluid = h->inited ? h->nfluid : h->ncells;
-    o->n_tiles = (int32_t)h->tiles.size();
+    o->n_tiles = (int32_t)(h->list_mode ? h->ltiles.size() : h->tiles.size());
     for (int a = 0; a < 3; ++a) o->tile[a] = h->shape[a];
     o->grid = h->grid;
     o->lds_staging = h->args.lds_stride > 0 ? 1 : 0;
@@ -1034,9 +1102,9 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid)
 {
     if (!h) return fail(WLB_ERR_ARG, "null handle");
-    if (tx < 0 || ty < 0 || tz < 0) return fail(WLB_ERR_ARG, "negative tile shape");
+    if (tx < -1 || ty < 0 || tz < 0) return fail(WLB_ERR_ARG, "negative tile shape");
     if (grid < -1) return fail(WLB_ERR_ARG, "grid must be -1, 0 or a workgroup count");
-    if (tx != 0 && (ty < 1 || tz < 1 || (int64_t)tx * ty * tz > kWG))
+    if (tx > 0 && (ty < 1 || tz < 1 || (int64_t)tx * ty * tz > kWG))
         return fail(WLB_ERR_ARG, "tile shape must have at most %d cells", kWG);
     return set_tiles(h, tx, ty, tz, grid);
 }

@@ -526,7 +526,7 @@ __device__ __forceinline__ int xcd_item(int b, int n)
 }
 __device__ __forceinline__ int first_tile(const SweepArgs &a)
 {
-    return (a.xcd_map && (int)gridDim.x == a.ntiles) ? xcd_item(blockIdx.x, a.ntiles) : (int)blockIdx.x;
+    return (a.xcd_map && (int)gridDim.x == a.nstiles) ? xcd_item(blockIdx.x, a.nstiles) : (int)blockIdx.x;
 }
 
 __device__ __forceinline__ CellPos tile_cell(const int4 tv, int l)
@@ -538,6 +538,20 @@ __device__ __forceinline__ CellPos tile_cell(const int4 tv, int l)
     c.x = (tv.y & 0xffff) + lx;
     c.y = (tv.z & 0xffff) + r % ey;
     c.z = (tv.w & 0xffff) + r / ey;
+    return c;
+}
+
+// Cell of lane l in a sweep tile: a box tile, or a list tile of fluid cells
+// (porous media: no lanes spent on solid cells, full waves on short rows).
+__device__ __forceinline__ CellPos sweep_cell(const SweepArgs &a, const int4 tv, int l)
+{
+    if (tv.w >= 0) return tile_cell(tv, l);
+    CellPos c;
+    c.valid = l < -tv.w;
+    const uint32_t p = c.valid ? a.cells[tv.y + l] : 0u;
+    c.x = (int)(p & 1023u);
+    c.y = (int)((p >> 10) & 1023u);
+    c.z = (int)(p >> 20);
     return c;
 }
 
@@ -734,10 +748,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
     const SweepArgs a)
 {
     using T = typename Codec<ST>::T;
-    for (int t = first_tile(a); t < a.ntiles; t += gridDim.x) {
+    for (int t = first_tile(a); t < a.nstiles; t += gridDim.x) {
         const CollParams<T> cp = coll_params<T>(a);
-        const int4 tv = a.tiles[t];
-        const CellPos c = tile_cell(tv, threadIdx.x);
+        const int4 tv = a.stiles[t];
+        const CellPos c = sweep_cell(a, tv, threadIdx.x);
         if (!c.valid) continue;
         const DevBlock B = a.blocks[tv.x];
         uint32_t mask = 0;
@@ -798,8 +812,8 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
     uint32_t *info = reinterpret_cast<uint32_t *>(smem + ((2 * (size_t)NSH * stride * sizeof(Raw) + 15) & ~15ull));
     const CollParams<T> cp = coll_params<T>(a);
     const int l = threadIdx.x;
-    for (int t = first_tile(a); t < a.ntiles; t += gridDim.x) {
-        const int4 tv = a.tiles[t];
+    for (int t = first_tile(a); t < a.nstiles; t += gridDim.x) {
+        const int4 tv = a.stiles[t];
         const int ex = tv.y >> 16, ey = tv.z >> 16, ez = tv.w >> 16;
         const bool valid = l < ex * ey * ez;
         const int lx = l % ex, lr = l / ex;  // lr = row within the tile = ly + ey * lz
@@ -916,9 +930,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     __shared__ T park[Q][kWG];
     mlp_stage(&net_s, a.mlp);
     const MlpDev *net = &net_s;
-    for (int t = first_tile(a); t < a.ntiles; t += gridDim.x) {
-        const int4 tv = a.tiles[t];
-        const CellPos c = tile_cell(tv, threadIdx.x);
+    for (int t = first_tile(a); t < a.nstiles; t += gridDim.x) {
+        const int4 tv = a.stiles[t];
+        const CellPos c = sweep_cell(a, tv, threadIdx.x);
         const DevBlock B = a.blocks[tv.x];
         uint32_t mask = 0;
         if (c.valid && B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];

@@ -34,7 +34,9 @@ struct DevBlock {
 static_assert(sizeof(DevBlock) == 80, "DevBlock layout");
 
 // One tile of a sweep: block id and start/extent (extent <= 256 cells).
-// Packed as int4 {block, x0 | ex << 16, y0 | ey << 16, z0 | ez << 16}.
+// Packed as int4 {block, x0 | ex << 16, y0 | ey << 16, z0 | ez << 16}.  A
+// list tile (sweeps only) is {block, first entry in the cell list, 0, -count}
+// with up to 256 fluid cells of the block.
 struct TileHost {
     int32_t b, x0, y0, z0, ex, ey, ez;
 };
@@ -62,10 +64,13 @@ constexpr uint32_t kSolidBit = 0x80000000u;
 struct SweepArgs {
     void *arena;
     const DevBlock *blocks;
-    const int4 *tiles;
+    const int4 *tiles;      // box tiles (every kernel but the sweeps)
+    const int4 *stiles;     // tiles of the sweeps: the box tiles, or lists of fluid cells
+    const uint32_t *cells;  // packed fluid cells x | y << 10 | z << 20 of the list tiles
     const uint32_t *masks;
     const void *mlp;  // MlpDev of the learned closure (closure == 2)
     int32_t ntiles;
+    int32_t nstiles;
     int32_t dom[3];
     int32_t periodic;      // bit a set: axis a wraps
     int32_t pressure_axis; // -1 or axis

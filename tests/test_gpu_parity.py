@@ -235,7 +235,8 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
     p = wlb.make_params(tau=0.66, magic=3 / 16, force=(1e-5, 0, 0))
     runs = [dict(), dict(tiles=(16, 4, 4, 0)), dict(tiles=(64, 4, 1, 7)), dict(tiles=(8, 8, 4, 3)),
             dict(graph=False), dict(mode="split"), dict(lds=False), dict(lds=False, tiles=(16, 4, 4, 0)),
-            dict(tiles=(0, 0, 0, -1)), dict(tiles=(16, 4, 4, -1), mode="split")]
+            dict(tiles=(0, 0, 0, -1)), dict(tiles=(16, 4, 4, -1), mode="split"), dict(tiles=(-1, 0, 0, 0)),
+            dict(tiles=(-1, 0, 0, -1)), dict(tiles=(-1, 0, 0, 5), graph=False)]
     ref = None
     for kw in runs:
         d, r, uu, tot, B = gpu_run(blocks, dom, (1, 1, 0), 19, wlb.F32, wlb.TRT, p, rho, u, solid, steps=13, **kw)
@@ -244,6 +245,38 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
             ref = d
         else:
             assert np.array_equal(d, ref), kw
+
+
+def test_fluid_list_tiles_need_solid_cells():
+    say("case list tiles without solids")
+    dom = (16, 12, 10)
+    rho, u = inputs.random_state(dom, seed=1, umag=0.01)
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 1, 1), stencil=19, storage=wlb.F32)
+    try:
+        B.init(wlb.SRT, wlb.make_params(tau=0.8), rho, u)
+        with pytest.raises(wlb.WlbError) as e:
+            B.set_tiles(-1, 0, 0, 0)
+        assert e.value.code == wlb.WLB_ERR_STATE
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+def test_fluid_list_tiles_fp64_vs_oracle(q, coll):
+    """Sweeps over lists of fluid cells on uneven blocks with spheres and
+    density faces, against the oracle."""
+    say(f"case list tiles q{q} coll{coll}")
+    blocks, dom = inputs.rectilinear_blocks([8, 12, 6], [10, 6], [7, 9])
+    solid, frac, _ = inputs.spheres(dom, seed=3, rmin=2.0, rmax=4.0, solid_fraction=0.2, clear_x=2)
+    rho, u = inputs.random_state(dom, seed=13, umag=0.01)
+    p = wlb.make_params(tau=0.8, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, pressure_axis=0, rho_in=1.002,
+                        rho_out=0.998)
+    gpu = gpu_run(blocks, dom, (0, 1, 1), q, wlb.F64, coll, p, rho, u, solid, steps=9, tiles=(-1, 0, 0, -1))
+    assert gpu[4].info().tile[0] == -1
+    op = oracle_params(q, coll, 0.8, 3 / 16, (0, 1, 1), pressure_axis=0, rho_in=1.002, rho_out=0.998,
+                       omega_bulk=1.2, omega_higher=1.0)
+    orc = oracle_run(op, dom, rho, u, solid, 9)
+    _compare(f"list tiles q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
 
 
 @pytest.mark.parametrize("storage", [0, 2])
