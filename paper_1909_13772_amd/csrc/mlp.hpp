@@ -56,15 +56,9 @@ __device__ __forceinline__ void mlp_stage(MlpDev *dst, const void *src)
 // Host-side: hidden unit held in result register j by lane half h.
 __host__ __device__ constexpr int mlp_unit(int j, int h) { return 8 * (j / 4) + 4 * h + (j % 4); }
 
-__device__ __forceinline__ uint16_t bf16_bits(float v)
-{
-    // round to nearest even; a NaN keeps its sign and top payload bits and
-    // is made quiet (selects, not branches: the whole wave takes this path)
-    const uint32_t u = __float_as_uint(v);
-    const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    const uint32_t nan = (u >> 16) | 0x40u;
-    return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? nan : rne);
-}
+// Round to bf16, nearest even (the hardware conversion of gfx950; a NaN
+// stays a quiet NaN).
+__device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 __device__ __forceinline__ float bf16_round(float v) { return __uint_as_float((uint32_t)bf16_bits(v) << 16); }
 
 // Standard normal CDF Phi(z) = erfc(-z / sqrt 2) / 2 without branches:
@@ -114,7 +108,7 @@ __device__ __forceinline__ bf16x8_t pack_bf16x8(const float *v)
 {
     bf16x8_t r;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) r[t] = __builtin_bit_cast(__bf16, bf16_bits(v[t]));
+    for (int t = 0; t < 8; ++t) r[t] = (__bf16)v[t];
     return r;
 }
 

@@ -86,13 +86,9 @@ template <> struct Codec<bf16_t> {
     using T = float;
     using Raw = uint16_t;
     static __device__ __forceinline__ T dec(Raw r) { return __uint_as_float((uint32_t)r << 16); }
-    static __device__ __forceinline__ Raw enc(T v)
-    {
-        const uint32_t u = __float_as_uint(v);
-        if ((u & 0x7f800000u) == 0x7f800000u)
-            return (Raw)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));  // inf stays inf, nan stays (quiet) nan
-        return (Raw)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);           // round to nearest even
-    }
+    // round to nearest even in the hardware conversion (inf stays inf, a NaN
+    // stays a quiet NaN)
+    static __device__ __forceinline__ Raw enc(T v) { return __builtin_bit_cast(Raw, (__bf16)v); }
 };
 
 // Typed loads / stores through the codec.
