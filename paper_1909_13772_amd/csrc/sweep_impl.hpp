@@ -945,7 +945,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const Macro<Q, T> m0 = moments_of<Q, T>(f, cp.F);
         T P[6];
         pi_pairs<Q, T>(f, m0, P);
-        const T tau_s = tau_smagorinsky<T>(P, m0.rho, cp.tau0, cp.smag_k);
         float x[7];
         bool bad = false;
 #pragma unroll
@@ -964,13 +963,21 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         for (int i = 0; i < Q; ++i) park[i][threadIdx.x] = f[i];
         asm volatile("" ::: "memory");
         const float o = mlp_forward_wave(net, x);
-        const T tau = (bad || !isfinite(o)) ? tau_s : cp.tau0 + softplus_f(o);
-        const T om = recip(tau);
-        const T omm = COLL == 1 ? recip(T(0.5) + cp.magic * recip(tau - T(0.5))) : om;
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = park[i][threadIdx.x];
         const Macro<Q, T> m = moments_of<Q, T>(f, cp.F);
+        T tau;
+        if (bad || !isfinite(o)) {
+            // Smagorinsky fallback (rare lanes): the same Pi and rho as above
+            T Ps[6];
+            pi_pairs<Q, T>(f, m, Ps);
+            tau = tau_smagorinsky<T>(Ps, m.rho, cp.tau0, cp.smag_k);
+        } else {
+            tau = cp.tau0 + softplus_f(o);
+        }
+        const T om = recip(tau);
+        const T omm = COLL == 1 ? recip(T(0.5) + cp.magic * recip(tau - T(0.5))) : om;
         relax_pairs<Q, T, COLL == 0>(f, m, cp.F, om, omm);
         if (!active) continue;
         if (L.alo | L.ahi) {
