@@ -80,7 +80,7 @@ struct wlb_blocks {
     int64_t steps = 0;
     int parity = 0;       // 0 natural layout, 1 swapped (after an even sweep)
     int pending = 0;      // 0 none, 1 pull due (after even), 2 push due (after odd)
-    bool any_wrap = false;  // some block wraps its x accesses (no LDS-staged odd sweep then)
+    bool any_wrap = false;  // some block has an x neighbour (x accesses direct: no LDS-staged odd sweep then)
     // sweep tiles as lists of fluid cells (porous media); available after an
     // init with solid cells when every block fits the 10/10/12-bit packing
     bool list_ok = false, list_built = false, list_mode = false;
@@ -652,7 +652,11 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
         // a block that is its own neighbour on both x faces wraps its x
         // accesses in the kernels and takes no part in x exchanges
         D.wrapx = (B.nbr[12] == b && B.nbr[14] == b) ? B.n[0] : 0;
-        if (D.wrapx) h->any_wrap = true;
+        // other blocks across the x faces: read and written directly by the
+        // kernels, so x crossings never go through ghost columns
+        D.nbx[0] = (B.nbr[12] >= 0 && B.nbr[12] != b) ? B.nbr[12] : -1;
+        D.nbx[1] = (B.nbr[14] >= 0 && B.nbr[14] != b) ? B.nbr[14] : -1;
+        if (B.nbr[12] >= 0 || B.nbr[14] >= 0) h->any_wrap = true;
         D.mpitch = (int32_t)round_up(B.n[0], 32);
         D.mplane = D.mpitch * B.n[1];
         D.mask = (int64_t)mwords;  // provisional; -1 if the block has no solid nearby (set at init)
@@ -686,15 +690,16 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     // --- exchange work lists
     for (int b = 0; b < n; ++b) {
         const HostBlock &A = h->blocks[b];
-        const bool wrapx = h->dev[b].wrapx != 0;
+        // x neighbours (the block itself or another) are addressed directly
+        // by the kernels: no x items, and y/z regions reach the x ends of
+        // the rows on every side that has a neighbour
+        const bool xlo = A.nbr[12] >= 0, xhi = A.nbr[14] >= 0;
         for (int k = 0; k < 27; ++k) {
             const int nb = A.nbr[k];
             if (nb < 0) continue;
             const HostBlock &Bn = h->blocks[nb];
             const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
-            // x-crossing populations of a wrapping block never leave it:
-            // the kernels address the other end of the row directly
-            if (wrapx && o[0] != 0) continue;
+            if (o[0] != 0) continue;
             for (int j = 1; j < stencil; ++j) {
                 bool in = true;
                 for (int a = 0; a < 3; ++a)
@@ -713,11 +718,14 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
                         ext[a] = 1;
                         ghost0[a] = o[a] < 0 ? -1 : A.n[a];
                         inner0[a] = o[a] < 0 ? Bn.n[a] - 1 : 0;
-                    } else if (a == 0 && wrapx) {
-                        // every cell of the row: the reader / writer wraps along x
-                        ext[a] = A.n[a];
-                        ghost0[a] = 0;
-                        inner0[a] = 0;
+                    } else if (a == 0) {
+                        // the reader / writer g - c_j may sit across an x face
+                        // with a neighbour; only a face without one limits the range
+                        const int lo = (cc(j, 0) > 0 && !xlo) ? 1 : 0;
+                        const int hi = (cc(j, 0) < 0 && !xhi) ? A.n[0] - 1 : A.n[0];
+                        ext[a] = hi - lo;
+                        ghost0[a] = lo;
+                        inner0[a] = lo;
                     } else {
                         const int lo = std::max(0, cc(j, a)), hi = std::min(A.n[a], A.n[a] + cc(j, a));
                         ext[a] = hi - lo;

@@ -698,8 +698,8 @@ __device__ __forceinline__ uint32_t xshift(const XOff &o)
 // even sweep) reads slot opp(i) of x - c_i, or slot i of x on bounce-back /
 // anti-bounce-back links.
 template <int Q, typename ST, bool SWAPPED>
-__device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, uint32_t special,
-                                       typename Codec<ST>::T (&f)[Q])
+__device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, int y, int z,
+                                       uint32_t special, typename Codec<ST>::T (&f)[Q])
 {
     const XOff o = xoffsets<ST>(B, off, x);
     sfor<Q>([&](auto I) {
@@ -712,14 +712,39 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
                                                                       : xshift<-cx(i)>(o) + p.add_reg));
         }
     });
+    if constexpr (SWAPPED) {
+        // x faces shared with another block: populations entering through
+        // the face come straight from the neighbour's cells (no x exchange;
+        // the regular loads above read this block's unused ghost column)
+        if (x == 0 && B.nbx[0] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[0]];
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (cx(i) == 1)
+                    if (!((special >> opp(i)) & 1u))
+                        f[i] = ldv<ST, false>(at<ST>(slot_base<ST>(a, N, opp(i)),
+                                                     cell_off(N, N.n[0] - 1, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+            });
+        }
+        if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[1]];
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (cx(i) == -1)
+                    if (!((special >> opp(i)) & 1u))
+                        f[i] = ldv<ST, false>(
+                            at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+            });
+        }
+    }
 }
 
 // Store the post-collision populations of a fluid cell: even sweep into
 // slot opp(i) of x; odd sweep into slot i of x + c_i, or slot opp(i) of x on
 // bounce-back / anti-bounce-back links.
 template <int Q, typename ST, bool ODD>
-__device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, uint32_t special,
-                                        const typename Codec<ST>::T (&f)[Q])
+__device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, int y, int z,
+                                        uint32_t special, const typename Codec<ST>::T (&f)[Q])
 {
     const XOff o = xoffsets<ST>(B, off, x);
     sfor<Q>([&](auto I) {
@@ -731,6 +756,32 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
             stv<ST>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx(i)>(o) + p.add_reg), f[i]);
         }
     });
+    if constexpr (ODD) {
+        // populations leaving through an x face shared with another block go
+        // straight into the neighbour's cells (the regular stores above
+        // wrote this block's unused ghost column)
+        if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[1]];
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (cx(i) == 1)
+                    if (!((special >> i) & 1u))
+                        stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)),
+                                       f[i]);
+            });
+        }
+        if (x == 0 && B.nbx[0] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[0]];
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (cx(i) == -1)
+                    if (!((special >> i) & 1u))
+                        stv<ST, false>(
+                            at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)),
+                            f[i]);
+            });
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -757,7 +808,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         const uint32_t off = cell_off(B, c.x, c.y, c.z);
         const uint32_t special = L.bb | L.alo | L.ahi;
         T f[Q];
-        gather<Q, ST, ODD>(a, B, off, c.x, special, f);
+        gather<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f);
         const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;
@@ -767,7 +818,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
             });
         }
-        scatter<Q, ST, ODD>(a, B, off, c.x, special, f);
+        scatter<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f);
     }
 }
 
@@ -938,7 +989,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const uint32_t off = active ? cell_off(B, c.x, c.y, c.z) : 0u;
         T f[Q];
         if (active) {
-            gather<Q, ST, ODD>(a, B, off, c.x, special, f);
+            gather<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f);
         } else {
             for (int i = 0; i < Q; ++i) f[i] = T(0);
         }
@@ -988,7 +1039,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
             });
         }
-        scatter<Q, ST, ODD>(a, B, off, c.x, special, f);
+        scatter<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f);
     }
 }
 
@@ -1026,7 +1077,7 @@ __global__ __launch_bounds__(kWG) void moments_kernel(const MomArgs ma)
                 const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
                 const uint32_t off = cell_off(B, c.x, c.y, c.z);
                 typename Codec<ST>::T f[Q];
-                gather<Q, ST, SWAPPED>(a, B, off, c.x, L.bb | L.alo | L.ahi, f);
+                gather<Q, ST, SWAPPED>(a, B, off, c.x, c.y, c.z, L.bb | L.alo | L.ahi, f);
                 double drho = 0, j[3] = {0, 0, 0};
                 sfor<Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
@@ -1105,7 +1156,7 @@ __global__ __launch_bounds__(kWG) void filter_kernel(const SweepArgs a, int fac,
                     if (mask & kSolidBit) continue;
                     const Links<Q> L = classify<Q>(mask, B, x, y, z, a);
                     typename Codec<ST>::T f[Q];
-                    gather<Q, ST, SWAPPED>(a, B, cell_off(B, x, y, z), x, L.bb | L.alo | L.ahi, f);
+                    gather<Q, ST, SWAPPED>(a, B, cell_off(B, x, y, z), x, y, z, L.bb | L.alo | L.ahi, f);
                     double drho = 0, j[3] = {0, 0, 0};
                     sfor<Q>([&](auto I) {
                         constexpr int i = decltype(I)::value;
@@ -1201,7 +1252,7 @@ __global__ __launch_bounds__(kWG) void pdfs_kernel(const SweepArgs a, double *bu
         } else {
             const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
             T f[Q];
-            gather<Q, ST, SWAPPED>(a, B, off, c.x, L.bb | L.alo | L.ahi, f);
+            gather<Q, ST, SWAPPED>(a, B, off, c.x, c.y, c.z, L.bb | L.alo | L.ahi, f);
             for (int i = 0; i < Q; ++i) buf[i * S + k] = (double)f[i];
         }
     }

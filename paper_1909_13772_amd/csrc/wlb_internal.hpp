@@ -29,7 +29,7 @@ struct DevBlock {
     int32_t mplane; // mask elements per plane
     int32_t xoff;   // element offset of interior x = 0 within a row
     int32_t wrapx;  // n[0] if the block is its own neighbour along x (periodic), else 0
-    int32_t pad[2];
+    int32_t nbx[2]; // other block across the -x / +x face (accessed directly), else -1
 };
 static_assert(sizeof(DevBlock) == 80, "DevBlock layout");
 

@@ -33,12 +33,12 @@ def test_param_struct_layout_matches_header():
     assert C.sizeof(wlb.wlb_block_desc) == 24
 
 
-def _crossing_links(n, periodic, q, wrapx=False):
+def _crossing_links(n, periodic, q, xnbr=False):
     """Brute force: interior (cell, direction) pairs whose target x + c_i
     leaves the block through a periodic face -- exactly the populations one
-    exchange must move (each once).  A block that is its own neighbour along
-    x (wrapx) addresses the other end of its rows directly, so its targets are
-    first wrapped along x."""
+    exchange must move (each once).  Across x faces that have a neighbour
+    block (itself or another; xnbr) the kernels address the neighbour's cells
+    directly, so only the y/z part of such a target counts."""
     import oracle as O
     c, _, _ = O.stencil(q)
     cnt = 0
@@ -46,7 +46,7 @@ def _crossing_links(n, periodic, q, wrapx=False):
         for z in range(n[2]):
             for y in range(n[1]):
                 for x in range(n[0]):
-                    tx = (x + c[i][0]) % n[0] if wrapx else x + c[i][0]
+                    tx = (x + c[i][0]) % n[0] if xnbr else x + c[i][0]
                     t = (tx, y + c[i][1], z + c[i][2])
                     out = [t[a] < 0 or t[a] >= n[a] for a in range(3)]
                     if any(out) and all(periodic[a] or not out[a] for a in range(3)):
@@ -61,7 +61,7 @@ def test_create_single_block_layout():
         assert info.n_blocks == 1 and info.n_cells == 32 ** 3
         # packed rows: 32 x 8 x 1 tiles
         assert info.n_tiles == 32 * 32 // 8
-        assert info.xchg_elems == _crossing_links((32, 32, 32), (1, 1, 1), 19, wrapx=True)
+        assert info.xchg_elems == _crossing_links((32, 32, 32), (1, 1, 1), 19, xnbr=True)
         # rows padded: x = 0 on a 128-byte boundary, pitch multiple of 16 doubles
         pitch = -(-(16 + 32 + 1) // 16) * 16
         slot = pitch * 34 * 34
@@ -72,12 +72,12 @@ def test_create_single_block_layout():
 
 
 def test_exchange_counts_multi_block_periodic_x():
-    # two blocks along x: each is the other's x neighbour, no wrapping
+    # two blocks along x: each is the other's x neighbour, reached directly
     h, _ = wlb.wlb_blocks_create([((0, 0, 0), (8, 6, 5)), ((8, 0, 0), (8, 6, 5))], (16, 6, 5), (1, 1, 1), 19,
                                  wlb.F32)
     try:
         info = wlb.wlb_info(h)
-        assert info.xchg_elems == 2 * _crossing_links((8, 6, 5), (1, 1, 1), 19)
+        assert info.xchg_elems == 2 * _crossing_links((8, 6, 5), (1, 1, 1), 19, xnbr=True)
     finally:
         wlb.wlb_blocks_destroy(h)
 
@@ -89,6 +89,40 @@ def test_short_rows_are_packed():
         info = wlb.wlb_info(h)
         slot = -(-(18 * 18 * 18) // 32) * 32
         assert info.pop_bytes == -(-(19 * slot * 4) // 256) * 256
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+def _crossing_links_sides(n, periodic, q, xlo, xhi):
+    """As _crossing_links for a block with an x neighbour on the -x side
+    (xlo) and / or the +x side (xhi); targets across an x face without a
+    neighbour are walls."""
+    import oracle as O
+    c, _, _ = O.stencil(q)
+    cnt = 0
+    for i in range(1, q):
+        for z in range(n[2]):
+            for y in range(n[1]):
+                for x in range(n[0]):
+                    tx = x + c[i][0]
+                    if (tx < 0 and not xlo) or (tx >= n[0] and not xhi):
+                        continue
+                    t = (y + c[i][1], z + c[i][2])
+                    out = [t[0] < 0 or t[0] >= n[1], t[1] < 0 or t[1] >= n[2]]
+                    if any(out) and all(periodic[a + 1] or not out[a] for a in range(2)):
+                        cnt += 1
+    return cnt
+
+
+def test_exchange_counts_x_neighbour_on_one_side():
+    # x not periodic: each block has a neighbour on one x side and a wall on the other
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (7, 6, 5)), ((7, 0, 0), (9, 6, 5))], (16, 6, 5), (0, 1, 1), 27,
+                                 wlb.F32)
+    try:
+        info = wlb.wlb_info(h)
+        want = (_crossing_links_sides((7, 6, 5), (0, 1, 1), 27, False, True) +
+                _crossing_links_sides((9, 6, 5), (0, 1, 1), 27, True, False))
+        assert info.xchg_elems == want
     finally:
         wlb.wlb_blocks_destroy(h)
 
