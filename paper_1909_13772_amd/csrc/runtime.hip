@@ -80,7 +80,6 @@ struct wlb_blocks {
     int64_t steps = 0;
     int parity = 0;       // 0 natural layout, 1 swapped (after an even sweep)
     int pending = 0;      // 0 none, 1 pull due (after even), 2 push due (after odd)
-    bool any_wrap = false;  // some block has an x neighbour (x accesses direct: no LDS-staged odd sweep then)
     // sweep tiles as lists of fluid cells (porous media); available after an
     // init with solid cells when every block fits the 10/10/12-bit packing
     bool list_ok = false, list_built = false, list_mode = false;
@@ -159,9 +158,8 @@ void update_lds_stride(wlb_blocks *h)
     int stride = 0;
     for (const TileHost &t : h->tiles) stride = std::max(stride, t.ey * t.ez * (t.ex + 2));
     const int nsh = h->q == 19 ? 10 : 18;
-    const size_t bytes = ((2 * (size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
-    // the staged odd sweep keeps the ghost-layer addressing along x
-    h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->any_wrap && !h->list_mode) ? stride : 0;
+    const size_t bytes = (((size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
+    h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->list_mode) ? stride : 0;
     h->graph_valid = false;
 }
 
@@ -656,7 +654,6 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
         // kernels, so x crossings never go through ghost columns
         D.nbx[0] = (B.nbr[12] >= 0 && B.nbr[12] != b) ? B.nbr[12] : -1;
         D.nbx[1] = (B.nbr[14] >= 0 && B.nbr[14] != b) ? B.nbr[14] : -1;
-        if (B.nbr[12] >= 0 || B.nbr[14] >= 0) h->any_wrap = true;
         D.mpitch = (int32_t)round_up(B.n[0], 32);
         D.mplane = D.mpitch * B.n[1];
         D.mask = (int64_t)mwords;  // provisional; -1 if the block has no solid nearby (set at init)

@@ -784,6 +784,52 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
     }
 }
 
+// Regular incoming access of link i (slot opp(i) of x - c_i) as the direct
+// odd sweep makes it, returned as raw storage bits.
+template <typename ST, int i>
+__device__ __forceinline__ typename Codec<ST>::Raw load_regular_in(const SweepArgs &a, const DevBlock &B, const XOff &o,
+                                                                   int x, int y, int z)
+{
+    if constexpr (cx(i) == 1) {
+        if (x == 0 && B.nbx[0] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[0]];
+            return ldraw<ST, false>(at<ST>(slot_base<ST>(a, N, opp(i)),
+                                           cell_off(N, N.n[0] - 1, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+        }
+    } else {
+        if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[1]];
+            return ldraw<ST, false>(
+                at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+        }
+    }
+    const Alt<ST> p = alt_in<ST, i>(a, B);
+    return ldraw<ST, false>(at<ST>(p.base, xshift<-cx(i)>(o) + p.add_reg));
+}
+// Regular outgoing access of link i (slot i of x + c_i) as the direct odd
+// sweep makes it.
+template <typename ST, int i>
+__device__ __forceinline__ void store_regular_out(const SweepArgs &a, const DevBlock &B, const XOff &o, int x, int y,
+                                                  int z, typename Codec<ST>::T v)
+{
+    if constexpr (cx(i) == 1) {
+        if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[1]];
+            stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)), v);
+            return;
+        }
+    } else {
+        if (x == 0 && B.nbx[0] >= 0) {
+            const DevBlock N = a.blocks[B.nbx[0]];
+            stv<ST, false>(
+                at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)), v);
+            return;
+        }
+    }
+    const Alt<ST> p = alt_out<ST, i>(a, B);
+    stv<ST, false>(at<ST>(p.base, xshift<cx(i)>(o) + p.add_reg), v);
+}
+
 // ---------------------------------------------------------------------------
 // The sweep kernel (one launch covers every tile of every block)
 // ---------------------------------------------------------------------------
@@ -827,10 +873,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
 // of whole x-row segments.  Populations whose link has c_x != 0 would be read
 // from x - c_x and written to x + c_x, one element off the row alignment;
 // instead every lane moves its own aligned element between memory and an
-// LDS row buffer (with one halo element per row segment), and the one-cell
-// shift happens in LDS.  Every global access of the sweep is then a
-// full-line aligned access.  Targets outside the row segment (one lane per
-// row and population) are stored directly.
+// LDS row buffer, and the one-cell shift happens in LDS.  Every global access
+// of the sweep is then a full-line aligned access.
+//  - A segment that is a whole row of a block wrapping onto itself along x
+//    shifts around the row inside LDS: nothing leaves the row buffer.
+//  - Any other segment keeps one halo element per row end, loaded from where
+//    the direct sweep would read it (the next cell, the block's other end,
+//    its ghost column, or an x-neighbour block), and stores the one target
+//    outside the segment directly, to where the direct sweep would write it.
+// One buffer serves the incoming and the outgoing populations.
 // ---------------------------------------------------------------------------
 template <int Q>
 __host__ __device__ constexpr int n_xshift()
@@ -845,6 +896,12 @@ __host__ __device__ constexpr int xshift_index(int i)
     for (int j = 0; j < i; ++j) n += cx(j) != 0;
     return n;
 }
+// LDS bytes of the staged odd sweep for row buffers of `stride` elements.
+template <int Q, typename Raw>
+__host__ __device__ constexpr size_t lds_stage_bytes(int stride)
+{
+    return (((size_t)n_xshift<Q>() * stride * sizeof(Raw) + 15) & ~(size_t)15) + kWG * 4;
+}
 
 template <int Q, int COLL, typename ST>
 __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
@@ -854,9 +911,8 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
     constexpr int NSH = n_xshift<Q>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int stride = a.lds_stride;
-    Raw *lin = reinterpret_cast<Raw *>(smem);  // incoming row buffers [NSH][stride]
-    Raw *lout = lin + (size_t)NSH * stride;     // outgoing row buffers [NSH][stride]
-    uint32_t *info = reinterpret_cast<uint32_t *>(smem + ((2 * (size_t)NSH * stride * sizeof(Raw) + 15) & ~15ull));
+    Raw *buf = reinterpret_cast<Raw *>(smem);  // row buffers [NSH][stride], incoming then outgoing
+    uint32_t *info = reinterpret_cast<uint32_t *>(smem + (((size_t)NSH * stride * sizeof(Raw) + 15) & ~(size_t)15));
     const CollParams<T> cp = coll_params<T>(a);
     const int l = threadIdx.x;
     for (int t = first_tile(a); t < a.nstiles; t += gridDim.x) {
@@ -866,18 +922,28 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
         const int lx = l % ex, lr = l / ex;  // lr = row within the tile = ly + ey * lz
         const int x = (tv.y & 0xffff) + lx, y = (tv.z & 0xffff) + lr % ey, z = (tv.w & 0xffff) + lr / ey;
         const DevBlock B = a.blocks[tv.x];
+        const bool ring = B.wrapx != 0 && ex == B.n[0];  // whole row of a self-wrapping block
         uint32_t mask = 0;
         if (valid && B.mask >= 0) mask = a.masks[B.mask + (int64_t)z * B.mplane + y * B.mpitch + x];
         const bool active = valid && !(mask & kSolidBit);
         const Links<Q> L = classify<Q>(mask, B, x, y, z, a);
         const uint32_t special = L.bb | L.alo | L.ahi;
-        const uint32_t boff = valid ? cell_off(B, x, y, z) * (uint32_t)sizeof(ST) : 0u;
-        const int rb = lr * (ex + 2) + lx + 1;  // this lane's slot in its row buffer
+        const uint32_t off = valid ? cell_off(B, x, y, z) : 0u;
+        const uint32_t boff = off * (uint32_t)sizeof(ST);
+        const XOff o = xoffsets<ST>(B, off, x);
+        const int row = lr * (ex + 2) + 1;  // element 0 of this lane's row segment in its buffer
+        const int rb = row + lx;            // this lane's own element
+        // lane of the same row segment dx cells along x (around the row on a ring)
+        auto lane_at = [&](int dx) {
+            int s = lx + dx;
+            if (ring) s += s < 0 ? ex : (s >= ex ? -ex : 0);
+            return s;
+        };
         info[l] = active ? special : 0xffffffffu;
         // ---- all loads in one phase: the shifted incoming populations are
         // staged (aligned element at (x, y - c_y, z - c_z) of slot opp(i),
-        // plus the halo one cell outside the segment), the others are read
-        // directly (they are row-aligned either way).
+        // plus the halo one cell outside a segment that is not a ring), the
+        // others are read directly (they are row-aligned either way).
         T f[Q];
         if (valid) {
             sfor<Q>([&](auto I) {
@@ -886,10 +952,12 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                     constexpr int k = xshift_index(i);
                     const char *base = slot_base<ST>(a, B, opp(i)) -
                                        (int64_t)(cy(i) * B.pitch + cz(i) * B.plane) * (int64_t)sizeof(ST);
-                    lin[k * stride + rb] = ldraw<ST>(at<ST>(base, boff));
-                    if (cx(i) == 1 && lx == 0) lin[k * stride + rb - 1] = ldraw<ST, false>(at<ST>(base, boff - sizeof(ST)));
-                    if (cx(i) == -1 && lx == ex - 1)
-                        lin[k * stride + rb + 1] = ldraw<ST, false>(at<ST>(base, boff + sizeof(ST)));
+                    buf[k * stride + rb] = ldraw<ST>(at<ST>(base, boff));
+                    if (!ring) {
+                        if (cx(i) == 1 && lx == 0) buf[k * stride + rb - 1] = load_regular_in<ST, i>(a, B, o, x, y, z);
+                        if (cx(i) == -1 && lx == ex - 1)
+                            buf[k * stride + rb + 1] = load_regular_in<ST, i>(a, B, o, x, y, z);
+                    }
                     if ((special >> opp(i)) & 1u) f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
                 } else {
                     const Alt<ST> p = alt_in<ST, i>(a, B);
@@ -903,9 +971,12 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                 constexpr int i = decltype(I)::value;
                 if constexpr (cx(i) != 0) {
                     constexpr int k = xshift_index(i);
-                    if (!((special >> opp(i)) & 1u)) f[i] = Codec<ST>::dec(lin[k * stride + rb - cx(i)]);
+                    if (!((special >> opp(i)) & 1u)) f[i] = Codec<ST>::dec(buf[k * stride + row + lane_at(-cx(i))]);
                 }
             });
+        }
+        __syncthreads();  // the buffer now takes the outgoing populations
+        if (active) {
             const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
             if (L.alo | L.ahi) {
                 const T rin = (T)a.rho_in, rout = (T)a.rho_out;
@@ -925,13 +996,10 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                     constexpr int k = xshift_index(i);
                     if (sp) {
                         stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
-                    } else if ((cx(i) == 1 && lx == ex - 1) || (cx(i) == -1 && lx == 0)) {
-                        // target outside the row segment: direct store
-                        stv<ST, false>(at<ST>(slot_base<ST>(a, B, i),
-                                              boff + (uint32_t)(link_delta<i>(B) * (int)sizeof(ST))),
-                                       f[i]);
+                    } else if (!ring && ((cx(i) == 1 && lx == ex - 1) || (cx(i) == -1 && lx == 0))) {
+                        store_regular_out<ST, i>(a, B, o, x, y, z, f[i]);  // target outside the segment
                     } else {
-                        lout[k * stride + rb + cx(i)] = Codec<ST>::enc(f[i]);
+                        buf[k * stride + row + lane_at(cx(i))] = Codec<ST>::enc(f[i]);
                     }
                 }
             });
@@ -939,18 +1007,18 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
         __syncthreads();
         // ---- aligned stores of the shifted outgoing populations: this lane
         // stores the element at (x, y + c_y, z + c_z) of slot i when its
-        // writer, the lane at x - c_x of the same row, is a fluid cell of the
-        // segment with a regular link i.
+        // writer, the lane c_x cells back along the row segment, is a fluid
+        // cell with a regular link i.
         if (valid) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 if constexpr (cx(i) != 0) {
                     constexpr int k = xshift_index(i);
-                    const int lw = lx - cx(i);
-                    if (lw >= 0 && lw < ex && !((info[l - cx(i)] >> i) & 1u)) {
+                    const int lw = lane_at(-cx(i));
+                    if (lw >= 0 && lw < ex && !((info[l - lx + lw] >> i) & 1u)) {
                         const char *base = slot_base<ST>(a, B, i) +
                                            (int64_t)(cy(i) * B.pitch + cz(i) * B.plane) * (int64_t)sizeof(ST);
-                        straw<ST>(at<ST>(base, boff), lout[k * stride + rb]);
+                        straw<ST>(at<ST>(base, boff), buf[k * stride + rb]);
                     }
                 }
             });
@@ -1292,7 +1360,7 @@ static hipError_t sweep_q(bool odd, const SweepArgs &a, int grid, hipStream_t st
 {
     if (odd && a.lds_stride > 0) {
         using Raw = typename Codec<WLB_STORAGE>::Raw;
-        const size_t bytes = ((2 * (size_t)n_xshift<Q>() * a.lds_stride * sizeof(Raw) + 15) & ~(size_t)15) + kWG * 4;
+        const size_t bytes = lds_stage_bytes<Q, Raw>(a.lds_stride);
         hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE>), dim3(grid), dim3(kWG), bytes, st, a);
         return hipGetLastError();
     }

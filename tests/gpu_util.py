@@ -14,7 +14,7 @@ def say(msg):
 
 
 def gpu_run(blocks, domain, periodic, q, storage, coll, params, rho, u, solid=None, steps=0, tiles=None,
-            graph=True, mode="step", lds=True):
+            graph=True, mode="step", lds=False):
     """Returns (d[q][N] natural-layout deviations, rho, u, totals, Blocks)."""
     from paper_1909_13772_amd import wlb
     B = wlb.Blocks(blocks, domain, periodic, stencil=q, storage=storage)

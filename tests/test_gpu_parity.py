@@ -85,13 +85,13 @@ def test_channel_walls_force_fp64(q, coll):
     _compare(f"channel q{q}", wlb.F64, q, gpu, orc, None, np.prod(shape))
 
 
-def _porous_case(q, coll, storage, steps, seed=1):
+def _porous_case(q, coll, storage, steps, seed=1, **kw):
     blocks, dom = inputs.rectilinear_blocks([8, 12, 6], [10, 6], [7, 9])
     solid, frac, _ = inputs.spheres(dom, seed=seed, rmin=2.0, rmax=4.0, solid_fraction=0.2, clear_x=2)
     rho, u = inputs.random_state(dom, seed=seed + 10, umag=0.01)
     p = wlb.make_params(tau=0.8, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, pressure_axis=0,
                         rho_in=1.002, rho_out=0.998)
-    gpu = gpu_run(blocks, dom, (0, 1, 1), q, storage, coll, p, rho, u, solid, steps=steps)
+    gpu = gpu_run(blocks, dom, (0, 1, 1), q, storage, coll, p, rho, u, solid, steps=steps, **kw)
     op = oracle_params(q, coll, 0.8, 3 / 16, (0, 1, 1), pressure_axis=0, rho_in=1.002, rho_out=0.998,
                        omega_bulk=1.2, omega_higher=1.0)
     orc = oracle_run(op, dom, rho, u, solid, steps)
@@ -107,6 +107,16 @@ def test_porous_uneven_blocks_pressure_fp64(q, coll, steps):
     say(f"case porous q{q} coll{coll} steps{steps}")
     gpu, orc, solid, dom = _porous_case(q, coll, wlb.F64, steps)
     _compare(f"porous q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
+
+
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+def test_porous_uneven_blocks_lds_staged_odd_sweep_fp64(q, coll):
+    """The porous case with the odd sweep staged in LDS: x-neighbour blocks
+    supply the halo elements and take the stores past the row segment."""
+    say(f"case porous lds-staged q{q} coll{coll}")
+    gpu, orc, solid, dom = _porous_case(q, coll, wlb.F64, 11, lds=True)
+    assert gpu[4].info().lds_staging == 1
+    _compare(f"porous lds q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
 
 
 @pytest.mark.parametrize("coll", [0, 1])
@@ -186,10 +196,16 @@ def test_block_decomposition_is_bitwise_invariant(storage):
 
 
 @pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
-def test_x_wrap_with_solids_across_the_periodic_face_fp64(q, coll):
+@pytest.mark.parametrize("variant", ["rows", "segments", "direct", "direct-segments"])
+def test_x_wrap_with_solids_across_the_periodic_face_fp64(q, coll, variant):
     """One block periodic in x (x accesses wrap, no x exchange) with spheres
-    straddling the periodic x face, a body force and walls in y."""
-    say(f"case x-wrap solids q{q} coll{coll}")
+    straddling the periodic x face, a body force and walls in y.  Odd sweep
+    staged in LDS over whole rows (the shift wraps inside the row buffer) or
+    over row segments (halo elements wrap in memory), or direct (lane to
+    lane moves, with several row segments per wavefront)."""
+    say(f"case x-wrap solids q{q} coll{coll} {variant}")
+    kw = {"rows": dict(tiles=(24, 2, 2, 0), lds=True), "segments": dict(tiles=(8, 4, 2, 0), lds=True),
+          "direct": dict(), "direct-segments": dict(tiles=(8, 4, 2, 0))}[variant]
     dom = (24, 14, 12)
     solid, frac, _ = inputs.spheres(dom, seed=5, rmin=2.0, rmax=3.5, solid_fraction=0.15, periodic=(1, 1, 1),
                                     clear_x=0)
@@ -197,7 +213,9 @@ def test_x_wrap_with_solids_across_the_periodic_face_fp64(q, coll):
     rho, u = inputs.random_state(dom, seed=6, umag=0.01)
     F = (1e-5, 0, 2e-6)
     p = wlb.make_params(tau=0.75, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, force=F)
-    gpu = gpu_run(wlb.single_block(dom), dom, (1, 0, 1), q, wlb.F64, coll, p, rho, u, solid, steps=7)
+    gpu = gpu_run(wlb.single_block(dom), dom, (1, 0, 1), q, wlb.F64, coll, p, rho, u, solid, steps=7, **kw)
+    info = gpu[4].info()
+    assert info.lds_staging == (not variant.startswith("direct")), variant
     op = oracle_params(q, coll, 0.75, 3 / 16, (1, 0, 1), F, omega_bulk=1.2, omega_higher=1.0)
     orc = oracle_run(op, dom, rho, u, solid, 7)
     _compare(f"x-wrap q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
@@ -216,15 +234,19 @@ def test_wrapping_and_exchanging_decompositions_agree_bitwise(storage):
     layouts = [wlb.single_block(dom), inputs.rectilinear_blocks([32], [8, 16], [6, 10])[0],
                inputs.rectilinear_blocks([8, 24], [24], [16])[0], inputs.uniform_blocks(dom, (16, 8, 8))[0]]
     ref = {}
+    # odd sweep: direct with the default (whole-row) tiles and over row
+    # segments, staged in LDS likewise
+    variants = [dict(), dict(tiles=(8, 4, 4, 0)), dict(lds=True), dict(lds=True, tiles=(8, 4, 4, 0))]
     for k, bl in enumerate(layouts):
-        for steps in (8, 9):  # ends in the natural and in the swapped layout
-            d, r, uu, tot, B = gpu_run(bl, dom, (1, 1, 1), 19, storage, 1, p, rho, u, solid, steps=steps)
-            B.close()
-            if steps not in ref:
-                ref[steps] = (d, r, uu)
-            else:
-                assert np.array_equal(d, ref[steps][0]), f"layout {k} steps {steps}: populations differ"
-                assert np.array_equal(r, ref[steps][1]) and np.array_equal(uu, ref[steps][2]), f"layout {k} moments"
+        for kw in variants:
+            for steps in (8, 9):  # ends in the natural and in the swapped layout
+                d, r, uu, tot, B = gpu_run(bl, dom, (1, 1, 1), 19, storage, 1, p, rho, u, solid, steps=steps, **kw)
+                B.close()
+                if steps not in ref:
+                    ref[steps] = (d, r, uu)
+                else:
+                    assert np.array_equal(d, ref[steps][0]), f"layout {k} {kw} steps {steps}: populations differ"
+                    assert np.array_equal(r, ref[steps][1]) and np.array_equal(uu, ref[steps][2]), f"layout {k} {kw}"
 
 
 def test_tiles_grid_graph_and_split_are_bitwise_invariant():
@@ -234,7 +256,7 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
     blocks = inputs.rectilinear_blocks([16, 24], [24], [12, 8])[0]
     p = wlb.make_params(tau=0.66, magic=3 / 16, force=(1e-5, 0, 0))
     runs = [dict(), dict(tiles=(16, 4, 4, 0)), dict(tiles=(64, 4, 1, 7)), dict(tiles=(8, 8, 4, 3)),
-            dict(graph=False), dict(mode="split"), dict(lds=False), dict(lds=False, tiles=(16, 4, 4, 0)),
+            dict(graph=False), dict(mode="split"), dict(lds=True), dict(lds=True, tiles=(16, 4, 4, 0)),
             dict(tiles=(0, 0, 0, -1)), dict(tiles=(16, 4, 4, -1), mode="split"), dict(tiles=(-1, 0, 0, 0)),
             dict(tiles=(-1, 0, 0, -1)), dict(tiles=(-1, 0, 0, 5), graph=False)]
     ref = None
