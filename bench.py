@@ -40,15 +40,16 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(storage_name: str):
+def load_traffic(storage_name: str, odd_sweep: str):
     """HBM bytes per sweep launch from a committed rocprofv3 counter summary,
-    only if it was taken on the current sweep source."""
+    only if it was taken on the current sweep source with the same odd-sweep
+    kernel."""
     path = os.path.join(ROOT, "profiles", "sweep_channel256_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("source_hash") != sweep_source_hash():
+    if t.get("source_hash") != sweep_source_hash() or t.get("odd_sweep") != odd_sweep:
         return None
     e = t.get("storage", {}).get(storage_name)
     return None if e is None else e.get("hbm_bytes_per_launch")
@@ -73,7 +74,7 @@ def poiseuille_series(H, nu, g, T, s):
     return u
 
 
-def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True, q=19, coll=None):
+def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True, q=19, coll=None, lds=None):
     import numpy as np
     import torch
 
@@ -87,6 +88,8 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
     B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=q, storage=storage)
     try:
         B.init(wlb.TRT if coll is None else coll, p, rho, u)
+        if lds is not None:  # fixed odd-sweep choice (profiler runs without the autotuner)
+            B.set_lds_staging(bool(lds))
         B.step(warmup)
         B.synchronize()
         B.set_kernel_timing(True)
@@ -101,7 +104,7 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
         B.set_kernel_timing(False)
         info = B.info()
         res = {"seconds": t1 - t0, "kernel_ms": ms, "launches": cnt, "tile": list(info.tile), "grid": info.grid,
-               "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems}
+               "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems, "lds_staging": int(info.lds_staging)}
         if check:
             r, uu, tot = B.moments()
             nu = (TAU - 0.5) / 3
@@ -197,6 +200,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
+    ap.add_argument("--lds-staging", type=int, choices=[0, 1], default=None,
+                    help="with --no-autotune: odd sweep staged in LDS (1) or direct (0) for the headline run")
     ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures"], default="channel",
                     help="channel = the headline configuration; the others print their own JSON line")
     ap.add_argument("--tau", type=float, default=0.5005, help="relaxation time of the turbulence workload")
@@ -221,7 +226,8 @@ def main():
             r = workloads.closure_cost(wlb, steps=args.steps, warmup=args.warmup)
         print(json.dumps(r))
         return
-    res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True, autotune=not args.no_autotune)
+    res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True, autotune=not args.no_autotune,
+                     lds=args.lds_staging)
     head = summarize(res, wlb.F64, args.steps, 8)
     print(f"[bench] f64: {head['mlups']:.0f} MLUPS, sweep {head['sweep_ms']:.3f} ms, "
           f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
@@ -253,7 +259,7 @@ def main():
         print(f"[bench] copy probe failed: {e}", file=sys.stderr)
         copy_gbs = None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
-    traffic = load_traffic("f64")
+    traffic = load_traffic("f64", "lds-staged" if res["lds_staging"] else "direct")
     out = {
         "metric": "MLUPS + % HBM roofline: plain FP64 vs FP32/FP16-store vs learned closure",
         "value": round(head["mlups"], 1),
@@ -270,10 +276,13 @@ def main():
         "config": {"workload": "D3Q19 TRT (Lambda 3/16) channel 256^3, one block, FP64 deviation storage, "
                                "bounce-back walls in y, periodic x/z, Guo force fx=1e-6, tau=0.8, from rest",
                    "cells": N ** 3, "stencil": "D3Q19", "collision": "TRT", "storage": "f64",
-                   "tile": res["tile"], "grid": res["grid"]},
+                   "tile": res["tile"], "grid": res["grid"],
+                   "odd_sweep": "lds-staged" if res["lds_staging"] else "direct"},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["frac"], 4), "traffic": traffic,
-                     "kernel": "sweep_kernel<19,TRT,double> (even and odd AA sweeps)",
+                     "kernel": "sweep_kernel<19,TRT,double> (even AA sweep) and " +
+                               ("sweep_odd_lds_kernel<19,TRT,double>" if res["lds_staging"] else
+                                "sweep_kernel<19,TRT,double>") + " (odd AA sweep)",
                      "algorithmic_bytes_per_launch": head["bytes_per_launch"],
                      "avg_launch_ms": round(head["sweep_ms"], 5), "even_launch_ms": round(head["even_ms"], 5),
                      "odd_launch_ms": round(head["odd_ms"], 5)},

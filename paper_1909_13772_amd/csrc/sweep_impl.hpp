@@ -1023,7 +1023,9 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                 }
             });
         }
-        __syncthreads();  // LDS and info are reused by the next tile
+        // LDS and info are reused by the next tile of this workgroup (t is
+        // the same in all its waves, so all or none of them wait)
+        if (t + (int)gridDim.x < a.nstiles) __syncthreads();
     }
 }
 
