@@ -207,9 +207,15 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *out);
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid);
 
 /* Stage (1) or not (0, default) the odd sweep's x-shifted populations in LDS
- * row buffers so that all its global accesses are row-aligned; staging is
- * skipped automatically when the buffers exceed 64 KiB per workgroup.  The
- * autotuner tries both. */
+ * row buffers so that all its global accesses are row-aligned (the same
+ * populations move; Eq. 2 and the AA scheme of Sec. 4.1 are unchanged).
+ * Tiles that are whole rows of a block wrapping onto itself along x shift
+ * around the row buffer; other row segments load one halo element per row
+ * end and store one element past it, through the block's other end, its
+ * ghost column or an x-neighbour block.  Staging is skipped automatically
+ * with fluid-cell list tiles and when the buffers exceed 64 KiB per
+ * workgroup (see wlb_info_t.lds_staging).  The autotuner tries both.
+ * Errors: WLB_ERR_ARG for a null handle. */
 int wlb_set_lds_staging(wlb_blocks_t h, int32_t on);
 
 /* Use (1) or bypass (0) the captured HIP graph in wlb_lbm_step. */
