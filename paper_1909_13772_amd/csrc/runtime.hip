@@ -156,7 +156,12 @@ size_t count_tiles(const wlb_blocks *h, int tx, int ty, int tz)
 void update_lds_stride(wlb_blocks *h)
 {
     int stride = 0;
-    for (const TileHost &t : h->tiles) stride = std::max(stride, t.ey * t.ez * (t.ex + 2));
+    bool ring = true;
+    for (const TileHost &t : h->tiles) {
+        stride = std::max(stride, t.ey * t.ez * (t.ex + 2));
+        ring = ring && t.ex == h->blocks[t.b].n[0] && h->dev[t.b].wrapx != 0;
+    }
+    h->args.lds_ring = ring ? 1 : 0;
     const int nsh = h->q == 19 ? 10 : 18;
     const size_t bytes = (((size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
     h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->list_mode) ? stride : 0;

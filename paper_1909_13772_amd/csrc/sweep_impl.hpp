@@ -903,7 +903,9 @@ __host__ __device__ constexpr size_t lds_stage_bytes(int stride)
     return (((size_t)n_xshift<Q>() * stride * sizeof(Raw) + 15) & ~(size_t)15) + kWG * 4;
 }
 
-template <int Q, int COLL, typename ST>
+// RING: every tile is a whole row of a self-wrapping block (chosen on the
+// host), so the halo and out-of-segment paths are compiled out.
+template <int Q, int COLL, typename ST, bool RING>
 __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
 {
     using T = typename Codec<ST>::T;
@@ -922,7 +924,7 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
         const int lx = l % ex, lr = l / ex;  // lr = row within the tile = ly + ey * lz
         const int x = (tv.y & 0xffff) + lx, y = (tv.z & 0xffff) + lr % ey, z = (tv.w & 0xffff) + lr / ey;
         const DevBlock B = a.blocks[tv.x];
-        const bool ring = B.wrapx != 0 && ex == B.n[0];  // whole row of a self-wrapping block
+        const bool ring = RING || (B.wrapx != 0 && ex == B.n[0]);  // whole row of a self-wrapping block
         uint32_t mask = 0;
         if (valid && B.mask >= 0) mask = a.masks[B.mask + (int64_t)z * B.mplane + y * B.mpitch + x];
         const bool active = valid && !(mask & kSolidBit);
@@ -953,7 +955,7 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                     const char *base = slot_base<ST>(a, B, opp(i)) -
                                        (int64_t)(cy(i) * B.pitch + cz(i) * B.plane) * (int64_t)sizeof(ST);
                     buf[k * stride + rb] = ldraw<ST>(at<ST>(base, boff));
-                    if (!ring) {
+                    if (!RING && !ring) {
                         if (cx(i) == 1 && lx == 0) buf[k * stride + rb - 1] = load_regular_in<ST, i>(a, B, o, x, y, z);
                         if (cx(i) == -1 && lx == ex - 1)
                             buf[k * stride + rb + 1] = load_regular_in<ST, i>(a, B, o, x, y, z);
@@ -996,7 +998,7 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                     constexpr int k = xshift_index(i);
                     if (sp) {
                         stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
-                    } else if (!ring && ((cx(i) == 1 && lx == ex - 1) || (cx(i) == -1 && lx == 0))) {
+                    } else if (!RING && !ring && ((cx(i) == 1 && lx == ex - 1) || (cx(i) == -1 && lx == 0))) {
                         store_regular_out<ST, i>(a, B, o, x, y, z, f[i]);  // target outside the segment
                     } else {
                         buf[k * stride + row + lane_at(cx(i))] = Codec<ST>::enc(f[i]);
@@ -1363,7 +1365,10 @@ static hipError_t sweep_q(bool odd, const SweepArgs &a, int grid, hipStream_t st
     if (odd && a.lds_stride > 0) {
         using Raw = typename Codec<WLB_STORAGE>::Raw;
         const size_t bytes = lds_stage_bytes<Q, Raw>(a.lds_stride);
-        hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE>), dim3(grid), dim3(kWG), bytes, st, a);
+        if (a.lds_ring)
+            hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE, true>), dim3(grid), dim3(kWG), bytes, st, a);
+        else
+            hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE, false>), dim3(grid), dim3(kWG), bytes, st, a);
         return hipGetLastError();
     }
     if (odd)

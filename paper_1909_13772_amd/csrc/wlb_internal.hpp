@@ -76,6 +76,7 @@ struct SweepArgs {
     int32_t pressure_axis; // -1 or axis
     int32_t closure;
     int32_t lds_stride;    // > 0: odd sweep stages x-shifted populations in LDS rows of this many elements
+    int32_t lds_ring;      // 1: every tile is a whole row of a self-wrapping block (staged sweep without halos)
     int32_t xcd_map;       // 1: one workgroup per tile, each XCD takes a contiguous range of tiles
     double omega;          // 1 / tau0
     double omega_minus;    // TRT rate of the antisymmetric part at tau0
