@@ -136,6 +136,7 @@ def lib():
         L.orc_run.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_void_p, dp, C.c_int, C.c_int]
         L.orc_moments.argtypes = [C.c_int, dp, C.c_int, C.c_int, C.c_int, C.c_void_p, dp, C.c_void_p,
                                   C.c_void_p, C.c_void_p]
+        L.orc_momentum_exchange.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_void_p, dp, dp]
         L.orc_bf16_round.argtypes = [C.c_double]
         L.orc_bf16_round.restype = C.c_double
         L.orc_mlp_forward.argtypes = [dp, C.c_int64, dp, dp, ip]
@@ -264,6 +265,22 @@ def moments(q: int, force, shape, d, solid=None):
                            rho.ctypes.data_as(C.c_void_p), u.ctypes.data_as(C.c_void_p),
                            tot.ctypes.data_as(C.c_void_p)), "moments")
     return rho, u.reshape(3, N), tot
+
+
+def momentum_exchange(p: Params, shape, d, solid=None):
+    """Force handed to the obstacles during the step that starts from state d
+    (momentum exchange over the half-way bounce-back links): the step's
+    collision, then 2 c_j f*_j summed over links whose target is a solid cell
+    or beyond a wall.  Returns [F_solid x, y, z, F_wall x, y, z, n_solid_links,
+    n_wall_links]."""
+    nx, ny, nz = shape
+    post, _ = collide(p, shape, d, solid)
+    s, sp = _solid_ptr(solid)
+    out = np.zeros(8)
+    _chk(lib().orc_momentum_exchange(C.byref(p.to_c()), nx, ny, nz, sp,
+                                     np.ascontiguousarray(post, np.float64).reshape(-1), out),
+         "momentum_exchange")
+    return out
 
 
 def bf16_round(v: float) -> float:

@@ -330,6 +330,77 @@ def test_mass_conserved_with_walls_and_spheres(q, coll):
 
 
 # --------------------------------------------------------------------------
+# Momentum exchange on bounce-back links (Sec. "Geometrically fully resolved
+# simulations"; Ladd 1994)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("q,coll", [(19, O.SRT), (19, O.TRT), (27, O.MRT)])
+def test_momentum_exchange_at_rest_is_the_static_pressure(q, coll):
+    """Fluid at rest with no force is a fixed point of the collision, so an
+    obstacle cell face receives the static pressure rho c_s^2 = rho / 3 of
+    the fluid cell next to it, pointing out of the fluid.  Channel with walls
+    in y whose upper part is solid: the fluid touches the lower wall (density
+    rho_lo in the bottom row) and the face of the solid slab (rho_hi in the
+    top fluid row), so neither force cancels against another."""
+    shape = (5, 8, 4)
+    nx, ny, nz = shape
+    top = 4  # last fluid row; rows above are solid
+    rho_lo, rho_hi = 0.97, 1.05
+    rho = np.full((nz, ny, nx), 1.01)
+    rho[:, 0, :] = rho_lo
+    rho[:, top, :] = rho_hi
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[:, top + 1:, :] = 1
+    u = np.zeros((3, nz, ny, nx))
+    p = O.Params(q=q, collision=coll, tau=0.8, magic=0.1, omega_bulk=1.3, omega_higher=1.1, periodic=(1, 0, 1))
+    out = O.momentum_exchange(p, shape, O.init(q, shape, rho, u, solid), solid)
+    area = nx * nz
+    links = 5 if q == 19 else 9  # links with c_y = -1 (or +1)
+    assert abs(out[4] + area * rho_lo / 3.0) < 1e-13
+    assert abs(out[1] - area * rho_hi / 3.0) < 1e-13
+    assert max(abs(out[0]), abs(out[2]), abs(out[3]), abs(out[5])) < 1e-14
+    assert out[6] == area * links and out[7] == area * links
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_momentum_exchange_counts_every_link_into_a_lone_solid_cell(q):
+    """One solid cell in a periodic box at rest: every neighbour sends exactly
+    one link into it (q - 1 links) and the pressure forces cancel."""
+    shape = (6, 5, 7)
+    solid = np.zeros((7, 5, 6), np.uint8)
+    solid[3, 2, 4] = 1
+    rho, u = inputs.uniform_state(shape, rho=1.02)
+    p = O.Params(q=q, collision=O.TRT, tau=0.7, magic=3 / 16)
+    out = O.momentum_exchange(p, shape, O.init(q, shape, rho, u, solid), solid)
+    assert out[6] == q - 1 and out[7] == 0
+    assert np.abs(out[:6]).max() < 1e-15
+
+
+@pytest.mark.parametrize("q,coll", [(19, O.SRT), (19, O.TRT), (27, O.MRT)])
+def test_momentum_exchange_balances_the_fluid_momentum(q, coll):
+    """Over one step the fluid gains N F from the body force (the collision
+    with the Guo term adds exactly F per cell) and loses what the bounce-back
+    links hand to the obstacles, while streaming between fluid cells moves
+    momentum without changing its sum.  So the exchanged force equals
+    N F + sum j(t) - sum j(t+1), with the sums taken from the moments alone."""
+    shape = (12, 10, 9)
+    solid, _, _ = inputs.spheres(shape, seed=2, rmin=1.5, rmax=2.5, solid_fraction=0.15, clear_x=0,
+                                 periodic=(1, 0, 1))
+    rho, u = inputs.random_state(shape, seed=7, umag=0.03)
+    F = np.array([2e-5, -1e-5, 3e-6])
+    p = O.Params(q=q, collision=coll, tau=0.66, magic=3 / 16, omega_bulk=1.2, omega_higher=0.9,
+                 periodic=(1, 0, 1), force=tuple(F))
+    d = O.run(p, shape, O.init(q, shape, rho, u, solid), 3, solid)
+    _, _, t0 = O.moments(q, p.force, shape, d, solid)
+    out = O.momentum_exchange(p, shape, d, solid)
+    _, _, t1 = O.moments(q, p.force, shape, O.run(p, shape, d, 1, solid), solid)
+    nfl = t0[6]
+    expect = nfl * F + t0[1:4] - t1[1:4]
+    got = out[:3] + out[3:6]
+    assert out[6] > 0 and out[7] > 0
+    assert np.abs(got - expect).max() < 1e-12 * max(1.0, np.abs(out[3:6]).max()), (got, expect)
+
+
+# --------------------------------------------------------------------------
 # Physics: Taylor-Green decay, Poiseuille (steady and transient), pressure
 # --------------------------------------------------------------------------
 def _energy(q, shape, d):
