@@ -166,6 +166,20 @@ int wlb_ghost_exchange(wlb_blocks_t h);
  * FP64 with a fixed order (deterministic).  Synchronises the stream. */
 int wlb_moments_get(wlb_blocks_t h, double *rho, double *u, double totals[8]);
 
+/* Force handed to the obstacles during the last step by momentum exchange
+ * (section "Geometrically fully resolved simulations": the momentum-exchange
+ * method of Ladd and Aidun et al.).  Every post-collision population f*_i of
+ * a fluid cell whose target x + c_i is a solid cell or lies beyond a wall
+ * (half-way bounce-back) delivers 2 c_i f*_i; links through pressure faces
+ * do not count.  out[8] (host, caller-owned) = force on the solid cells
+ * x/y/z, force on the walls x/y/z, number of solid links, number of wall
+ * links, in lattice units (mass = density x cells, per step).  Reads only
+ * the bounce-back populations of the current state (no exchange needed);
+ * FP64 sums in a fixed order; synchronises the stream.
+ * Errors: WLB_ERR_ARG (null argument), WLB_ERR_STATE (before wlb_lbm_init,
+ * or no step since it), WLB_ERR_HIP. */
+int wlb_force_get(wlb_blocks_t h, double out[8]);
+
 /* Population deviations d_i = f_i - w_i of the current state in natural
  * layout d[q][N] (FP64, host), and the reverse.  set also re-establishes the
  * natural layout so the next sweep is even; solid cells are ignored.  Used

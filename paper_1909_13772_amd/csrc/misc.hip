@@ -85,6 +85,30 @@ hipError_t launch_reduce_totals(const double *partials, int n, double *out8, hip
     return hipGetLastError();
 }
 
+// Second pass of a plain 8-component sum over per-tile partials [n][8], in a
+// fixed order (independent of the first pass's launch configuration).
+__global__ __launch_bounds__(kWG) void reduce_sum8_kernel(const double *p, int n, double *out)
+{
+    __shared__ double s[kWG][8];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += kWG)
+        for (int j = 0; j < 8; ++j) acc[j] += p[(int64_t)k * 8 + j];
+    for (int j = 0; j < 8; ++j) s[threadIdx.x][j] = acc[j];
+    __syncthreads();
+    for (int w = kWG / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int j = 0; j < 8; ++j) s[threadIdx.x][j] += s[threadIdx.x + w][j];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) out[threadIdx.x] = s[0][threadIdx.x];
+}
+
+hipError_t launch_reduce_sum8(const double *partials, int n, double *out8, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_sum8_kernel, dim3(1), dim3(kWG), 0, st, partials, n, out8);
+    return hipGetLastError();
+}
+
 // Plain streaming copy, one 16-byte vector per thread over a grid that
 // covers the buffer (measured on MI355X as the fastest simple copy form):
 // the library's own measure of achievable HBM bandwidth.

@@ -255,6 +255,16 @@ hipError_t moments_dispatch(const wlb_blocks *h, const MomArgs &m, int grid)
     }
 }
 
+hipError_t force_dispatch(const wlb_blocks *h, double *partials, int grid)
+{
+    switch (h->storage) {
+    case WLB_F64: return force_f64(h->q, h->args, partials, grid, h->stream);
+    case WLB_F32: return force_f32(h->q, h->args, partials, grid, h->stream);
+    case WLB_F16DEV: return force_f16(h->q, h->args, partials, grid, h->stream);
+    default: return force_bf16(h->q, h->args, partials, grid, h->stream);
+    }
+}
+
 hipError_t init_dispatch(const wlb_blocks *h, const double *rhou, int z0, int z1, int grid)
 {
     switch (h->storage) {
@@ -1048,6 +1058,20 @@ int wlb_moments_get(wlb_blocks_t h, double *rho, double *u, double totals[8])
             HIPCHK(hipStreamSynchronize(h->stream));
         }
     }
+    return WLB_OK;
+}
+
+int wlb_force_get(wlb_blocks_t h, double out[8])
+{
+    if (!h || !out) return fail(WLB_ERR_ARG, "null argument");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    if (h->steps == 0) return fail(WLB_ERR_STATE, "no step since wlb_lbm_init: the force is that of the last step");
+    double *partials = reinterpret_cast<double *>(h->arena + h->off_partials);
+    HIPCHK(force_dispatch(h, partials, aux_grid(h)));
+    double *tot = reinterpret_cast<double *>(h->arena + h->off_totals);
+    HIPCHK(launch_reduce_sum8(partials, (int)h->tiles.size(), tot, h->stream));
+    HIPCHK(hipMemcpyAsync(out, tot, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     return WLB_OK;
 }
 

@@ -1357,6 +1357,61 @@ __global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBloc
 }
 
 // ---------------------------------------------------------------------------
+// Force on obstacles by momentum exchange (section "Geometrically fully
+// resolved simulations": momentum-exchange method after Ladd and Aidun).  A
+// post-collision population f*_i of a fluid cell whose target x + c_i is a
+// solid cell or lies beyond a wall is bounced back into the cell, handing
+// 2 c_i f*_i to the obstacle.  In both AA layouts, after a step that value
+// sits in slot opp(i) of the cell itself (the even sweep stores every f*_i
+// there; the odd sweep stores bounced populations there), so this pass reads
+// one element per bounce-back link and nothing else.  Per-tile partials:
+// force on solid cells (x, y, z), on walls (x, y, z), solid links, wall
+// links; a fixed-order second pass sums them.
+// ---------------------------------------------------------------------------
+template <int Q, typename ST>
+__global__ __launch_bounds__(kWG) void force_kernel(const SweepArgs a, double *partials)
+{
+    __shared__ double red[kWG / 64][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const int4 tv = a.tiles[t];
+        const CellPos c = tile_cell(tv, threadIdx.x);
+        const DevBlock B = a.blocks[tv.x];
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (c.valid) {
+            uint32_t mask = 0;
+            if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
+            if (!(mask & kSolidBit)) {
+                const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
+                const uint32_t to_solid = mask & ((1u << Q) - 1u);  // targets inside the domain that are solid
+                const uint32_t off = cell_off(B, c.x, c.y, c.z) * (uint32_t)sizeof(ST);
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    if ((L.bb >> i) & 1u) {
+                        const double f = weight<Q, double>(i) + (double)ldv<ST, false>(at<ST>(slot_base<ST>(a, B, opp(i)), off));
+                        const int k = ((to_solid >> i) & 1u) ? 0 : 3;
+                        if constexpr (cx(i) != 0) acc[k + 0] += 2.0 * cx(i) * f;
+                        if constexpr (cy(i) != 0) acc[k + 1] += 2.0 * cy(i) * f;
+                        if constexpr (cz(i) != 0) acc[k + 2] += 2.0 * cz(i) * f;
+                        acc[k == 0 ? 6 : 7] += 1.0;
+                    }
+                });
+            }
+        }
+        for (int k = 0; k < 8; ++k) acc[k] = wave_sum(acc[k]);
+        if (lane == 0)
+            for (int k = 0; k < 8; ++k) red[wv][k] = acc[k];
+        __syncthreads();
+        if (threadIdx.x < 8) {
+            double r = 0.0;
+            for (int w = 0; w < kWG / 64; ++w) r += red[w][threadIdx.x];
+            partials[(int64_t)t * 8 + threadIdx.x] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <int Q, int COLL>
@@ -1419,6 +1474,13 @@ static hipError_t moments_q(const MomArgs &a, int grid, hipStream_t st)
 }
 
 template <int Q>
+static hipError_t force_q(const SweepArgs &a, double *partials, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((force_kernel<Q, WLB_STORAGE>), dim3(grid), dim3(kWG), 0, st, a, partials);
+    return hipGetLastError();
+}
+
+template <int Q>
 static hipError_t pdfs_q(const SweepArgs &a, double *buf, int z0, int z1, bool to_dev, bool swapped, int grid,
                          hipStream_t st)
 {
@@ -1443,6 +1505,11 @@ hipError_t WLB_CAT(sweep_, WLB_SUFFIX)(int q, int coll, bool odd, const SweepArg
 hipError_t WLB_CAT(moments_, WLB_SUFFIX)(int q, const MomArgs &a, int grid, hipStream_t st)
 {
     return q == 19 ? moments_q<19>(a, grid, st) : moments_q<27>(a, grid, st);
+}
+
+hipError_t WLB_CAT(force_, WLB_SUFFIX)(int q, const SweepArgs &a, double *partials, int grid, hipStream_t st)
+{
+    return q == 19 ? force_q<19>(a, partials, grid, st) : force_q<27>(a, partials, grid, st);
 }
 
 hipError_t WLB_CAT(init_, WLB_SUFFIX)(int q, const SweepArgs &a, const double *rhou, int z0, int z1, int grid,

@@ -102,6 +102,7 @@ struct MomArgs {
 #define WLB_DECLARE_LAUNCHERS(S)                                                                              \
     hipError_t sweep_##S(int q, int coll, bool odd, const SweepArgs &a, int grid, hipStream_t st);            \
     hipError_t moments_##S(int q, const MomArgs &a, int grid, hipStream_t st);                               \
+    hipError_t force_##S(int q, const SweepArgs &a, double *partials, int grid, hipStream_t st);              \
     hipError_t init_##S(int q, const SweepArgs &a, const double *rhou, int z0, int z1, int grid,             \
                         hipStream_t st);                                                                      \
     hipError_t pdfs_##S(int q, const SweepArgs &a, double *buf, int z0, int z1, bool to_device, bool swapped, \
@@ -129,6 +130,7 @@ size_t mlp_dev_bytes();
 // Storage-independent kernels (misc.hip).
 hipError_t launch_masks(const SweepArgs &a, const uint8_t *solid, int q, int grid, hipStream_t st);
 hipError_t launch_reduce_totals(const double *partials, int n, double *out8, hipStream_t st);
+hipError_t launch_reduce_sum8(const double *partials, int n, double *out8, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 hipError_t launch_les_targets(const double *filt, const int32_t nc[3], double tau0, float *raw, float *target,
                               hipStream_t st);

@@ -104,6 +104,7 @@ _sig = {
     "wlb_lbm_sweep": (C.c_int, [_h]),
     "wlb_ghost_exchange": (C.c_int, [_h]),
     "wlb_moments_get": (C.c_int, [_h, _vp, _vp, _vp]),
+    "wlb_force_get": (C.c_int, [_h, _vp]),
     "wlb_pdfs_get": (C.c_int, [_h, _vp]),
     "wlb_pdfs_set": (C.c_int, [_h, _vp]),
     "wlb_info": (C.c_int, [_h, C.POINTER(wlb_info_t)]),
@@ -181,6 +182,10 @@ def wlb_ghost_exchange(h):
 
 def wlb_moments_get(h, rho, u, totals):
     _check(_lib.wlb_moments_get(h, _ptr(rho), _ptr(u), _ptr(totals)))
+
+
+def wlb_force_get(h, out):
+    _check(_lib.wlb_force_get(h, _ptr(out)))
 
 
 def wlb_pdfs_get(h, d):
@@ -329,6 +334,13 @@ class Blocks:
 
     def exchange(self):
         wlb_ghost_exchange(self.h)
+
+    def force(self):
+        """Momentum exchanged with the obstacles during the last step:
+        [F_solid x, y, z, F_wall x, y, z, n_solid_links, n_wall_links]."""
+        out = np.zeros(8)
+        wlb_force_get(self.h, out)
+        return out
 
     def moments(self, fields=True):
         nx, ny, nz = self.domain

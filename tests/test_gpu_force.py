@@ -1,0 +1,108 @@
+"""Force on obstacles by momentum exchange (section "Geometrically fully
+resolved simulations"): the GPU's bounce-back populations against the FP64
+oracle, in both AA layouts, and the steady-state momentum balance of a
+body-force-driven channel."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import gpu_run, oracle_params, say
+from paper_1909_13772_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
+
+
+def _oracle_force(op, dom, rho, u, solid, steps):
+    """The force of step `steps` (counted from 1): momentum exchange of the
+    step that starts from the state after steps - 1 updates."""
+    d = O.run(op, dom, O.init(op.q, dom, rho, u, solid), steps - 1, solid)
+    return O.momentum_exchange(op, dom, d, solid)
+
+
+def _check(case, got, ref, tol):
+    say(f"{case}: solid {got[:3]} / {ref[:3]}, wall {got[3:6]} / {ref[3:6]}, links {got[6:]} / {ref[6:]}")
+    assert np.array_equal(got[6:], ref[6:]), case
+    scale = max(1.0, np.abs(ref[:6]).max())
+    assert np.abs(got[:6] - ref[:6]).max() <= tol * scale, (case, got, ref)
+
+
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+@pytest.mark.parametrize("steps", [10, 11])
+def test_force_on_spheres_and_walls_matches_the_oracle_fp64(q, coll, steps):
+    """Uneven blocks, spheres crossing block faces, density faces on x (not
+    counted), walls in y, periodic z, a body force."""
+    say(f"case force porous q{q} coll{coll} steps{steps}")
+    blocks, dom = inputs.rectilinear_blocks([8, 12, 6], [10, 6], [7, 9])
+    solid, _, _ = inputs.spheres(dom, seed=4, rmin=2.0, rmax=3.5, solid_fraction=0.2, clear_x=2)
+    rho, u = inputs.random_state(dom, seed=14, umag=0.01)
+    F = (2e-6, 1e-6, -1e-6)
+    kw = dict(tau=0.8, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, pressure_axis=0, rho_in=1.002,
+              rho_out=0.998, force=F)
+    p = wlb.make_params(**kw)
+    d, r, uu, tot, B = gpu_run(blocks, dom, (0, 0, 1), q, wlb.F64, coll, p, rho, u, solid, steps=steps)
+    got = B.force()
+    B.close()
+    op = oracle_params(q, coll, 0.8, 3 / 16, (0, 0, 1), F, pressure_axis=0, rho_in=1.002, rho_out=0.998,
+                       omega_bulk=1.2, omega_higher=1.0)
+    ref = _oracle_force(op, dom, rho, u, solid, steps)
+    assert ref[6] > 0 and ref[7] > 0
+    _check(f"porous q{q} c{coll} s{steps}", got, ref, 1e-12)
+
+
+@pytest.mark.parametrize("storage,tol", [(wlb.F32, 1e-6), (wlb.F16DEV, 1e-4)])
+def test_force_reduced_precision_storage(storage, tol):
+    say(f"case force storage{storage}")
+    blocks, dom = inputs.rectilinear_blocks([12, 12], [14], [6, 6])
+    solid, _, _ = inputs.spheres(dom, seed=6, rmin=2.0, rmax=3.0, solid_fraction=0.12, periodic=(1, 1, 1),
+                                 clear_x=0)
+    rho, u = inputs.random_state(dom, seed=15, umag=0.01)
+    p = wlb.make_params(tau=0.75, magic=3 / 16, force=(1e-5, 0, 0))
+    d, r, uu, tot, B = gpu_run(blocks, dom, (1, 0, 1), 19, storage, wlb.TRT, p, rho, u, solid, steps=9)
+    got = B.force()
+    B.close()
+    op = oracle_params(19, wlb.TRT, 0.75, 3 / 16, (1, 0, 1), (1e-5, 0, 0))
+    _check(f"storage{storage}", got, _oracle_force(op, dom, rho, u, solid, 9), tol)
+
+
+def test_force_needs_a_step():
+    dom = (8, 6, 4)
+    rho, u = inputs.uniform_state(dom)
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 0, 1), stencil=19, storage=wlb.F64)
+    try:
+        B.init(wlb.TRT, wlb.make_params(tau=0.8), rho, u)
+        with pytest.raises(wlb.WlbError) as e:
+            B.force()
+        assert e.value.code == wlb.WLB_ERR_STATE
+        B.step(1)
+        out = B.force()
+        # fluid at rest: the two walls receive rho c_s^2 per cell in opposite directions
+        assert abs(out[4]) < 1e-14 and out[7] == 2 * 8 * 4 * 5
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+def test_steady_channel_wall_drag_equals_the_body_force(q, coll):
+    """Body-force-driven channel between walls in y: at steady state the
+    fluid's momentum no longer changes, so the walls take exactly the body
+    force on all fluid cells, N f_x, and the pressure forces on the two walls
+    cancel."""
+    say(f"case steady channel drag q{q}")
+    dom = (6, 16, 4)
+    g = 2e-6
+    rho, u = inputs.uniform_state(dom)
+    p = wlb.make_params(tau=0.8, magic=3 / 16, omega_bulk=1.1, omega_higher=1.0, force=(g, 0, 0))
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 0, 1), stencil=q, storage=wlb.F64)
+    try:
+        B.init(coll, p, rho, u)
+        B.step(20000)
+        out = B.force()
+        n = dom[0] * dom[1] * dom[2]
+        say(f"steady channel q{q}: wall force {out[3:6]}, body force {n * g}")
+        assert abs(out[3] - n * g) <= 1e-9 * n * g
+        assert abs(out[4]) < 1e-12 and abs(out[5]) < 1e-14
+        assert np.abs(out[:3]).max() == 0.0 and out[6] == 0
+    finally:
+        B.close()
