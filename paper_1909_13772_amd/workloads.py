@@ -50,10 +50,18 @@ def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0
         B.init(wlb.MRT, p, rho, u, solid)
         secs, ms, cnt = _timed_steps(B, steps, warmup)
         info = B.info()
+        force = B.force()  # momentum exchanged with the spheres in the last step
         r, uu, tot = B.moments()
     finally:
         B.close()
     ncell = dom[0] * dom[1] * dom[2]
+    # Pressure drop across the medium and the drag it drives: at steady state
+    # the drag on the spheres balances c_s^2 (rho_in - rho_out) A (no walls);
+    # before that the ratio shows how far the flow has developed.  Darcy
+    # permeability from the superficial velocity q = mean mass flux / A,
+    # k = nu q L / (c_s^2 (rho_in - rho_out)), lattice units.
+    area = dom[1] * dom[2]
+    dp_force = (1.0005 - 0.9995) / 3.0 * area
     nfl = int(tot[6])
     sweep_ms = (ms[0] + ms[1]) / max(1, cnt[0] + cnt[1])
     xchg_ms = (ms[2] + ms[3]) / max(1, cnt[2] + cnt[3])
@@ -70,6 +78,9 @@ def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0
         "tile": list(info.tile), "grid": info.grid, "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems,
         "flux_x_mean": float(flux.mean()), "flux_x_spread": float((flux.max() - flux.min()) / abs(flux.mean())),
         "max_u": float(tot[5]),
+        "drag_on_spheres": [float(v) for v in force[:3]], "solid_links": int(force[6]),
+        "drag_over_pressure_force": float(force[0] / dp_force),
+        "permeability_lattice": float((0.8 - 0.5) / 3.0 * (flux.mean() / area) * dom[0] / ((1.0005 - 0.9995) / 3.0)),
     }
 
 

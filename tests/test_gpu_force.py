@@ -106,3 +106,36 @@ def test_steady_channel_wall_drag_equals_the_body_force(q, coll):
         assert np.abs(out[:3]).max() == 0.0 and out[6] == 0
     finally:
         B.close()
+
+
+def test_periodic_porous_drag_balances_the_momentum_budget():
+    """Spheres in a fully periodic box driven by a body force.  Over any one
+    step the fluid gains N_fluid g and loses the momentum handed to the
+    spheres, so the force equals N g + sum j(t) - sum j(t+1) with the sums
+    from the separate moments pass (exact up to rounding); near steady state
+    the spheres take the whole body force."""
+    say("case periodic porous momentum budget")
+    dom = (20, 16, 12)
+    solid, frac, _ = inputs.spheres(dom, seed=9, rmin=2.0, rmax=3.5, solid_fraction=0.2, periodic=(1, 1, 1),
+                                    clear_x=0)
+    g = np.array([3e-6, 1e-6, 0.0])
+    rho, u = inputs.uniform_state(dom)
+    p = wlb.make_params(tau=0.8, magic=3 / 16, force=tuple(g))
+    B = wlb.Blocks(inputs.rectilinear_blocks([8, 12], [16], [6, 6])[0], dom, (1, 1, 1), stencil=19,
+                   storage=wlb.F64)
+    try:
+        B.init(wlb.TRT, p, rho, u, solid)
+        for steps in (1, 10, 8000):  # budget after an odd and an even sweep, then near steady state
+            B.step(steps - 1)
+            _, _, t0 = B.moments(fields=False)
+            B.step(1)
+            out = B.force()
+            _, _, t1 = B.moments(fields=False)
+            n = t0[6]
+            budget = n * g + t0[1:4] - t1[1:4]
+            say(f"porous after {steps}: drag {out[:3]}, budget {budget}, body force {n * g}")
+            assert out[7] == 0 and out[6] > 0
+            assert np.abs(out[:3] - budget).max() <= 1e-10 * n * g[0]
+        assert np.abs(out[:3] - n * g).max() <= 1e-3 * n * g[0]
+    finally:
+        B.close()
