@@ -203,6 +203,7 @@ typedef struct {
     int64_t xchg_elems;     /* populations copied per exchange */
     size_t arena_bytes;
     size_t pop_bytes;       /* bytes of population storage incl. ghosts */
+    int32_t overlap;        /* 1: sweeps split into interior and frontier, exchange overlapped */
 } wlb_info_t;
 int wlb_info(wlb_blocks_t h, wlb_info_t *out);
 
@@ -231,6 +232,19 @@ int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t gr
  * workgroup (see wlb_info_t.lds_staging).  The autotuner tries both.
  * Errors: WLB_ERR_ARG for a null handle. */
 int wlb_set_lds_staging(wlb_blocks_t h, int32_t on);
+
+/* Interior/frontier overlap (1) or not (0, default).  Sec. 3.3 and 6: the
+ * paper hides communication behind computation; here each sweep is split
+ * into the cells at least two rows from every y/z block face that has a
+ * neighbour (interior) and the rest (frontier), and in wlb_lbm_step the
+ * frontier part and the ghost exchange run on a second HIP stream (created
+ * by the library, default priority) while the interior part runs on the
+ * bound stream; each step joins both.  Results are bitwise identical to the
+ * sequential order.  With per-kernel timing on, or through wlb_lbm_sweep /
+ * wlb_ghost_exchange, the parts run in turn on the bound stream.  The
+ * autotuner tries it for the best tile configuration when blocks exchange.
+ * Errors: WLB_ERR_ARG (null handle), WLB_ERR_HIP (stream creation). */
+int wlb_set_overlap(wlb_blocks_t h, int32_t on);
 
 /* Use (1) or bypass (0) the captured HIP graph in wlb_lbm_step. */
 int wlb_set_graph(wlb_blocks_t h, int32_t on);

@@ -88,6 +88,16 @@ struct wlb_blocks {
     int shape[3] = {0, 0, 0};
     int grid = 0;
     bool lds_stage = false;  // odd sweep stages x-shifted populations in LDS (autotuner candidate)
+    // interior/frontier overlap: each sweep is split into the cells at least
+    // kFrontier rows away from every y/z face with a neighbour (interior) and
+    // the rest (frontier); the frontier and the exchange run on a second
+    // stream while the interior runs on the bound stream (autotuner candidate)
+    bool overlap = false;
+    int nint_tiles = 0;   // interior box tiles come first in `tiles` when split
+    int nint_ltiles = 0;  // interior fluid-cell tiles come first in `ltiles`
+    bool tiles_split = false;
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool use_graph = true;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -108,45 +118,93 @@ namespace {
 
 int storage_esize(int s) { return s == WLB_F64 ? 8 : (s == WLB_F32 ? 4 : 2); }
 
-void build_tiles(const wlb_blocks *h, int tx, int ty, int tz, std::vector<TileHost> &out)
+// Rows at most this far from a y/z face with a neighbour block form the
+// frontier: the exchange reads and writes the row at the face and its ghost
+// row, and the odd sweep of the next row in touches the row at the face.
+constexpr int kFrontier = 2;
+
+// Interior rectangle (y0, y1) x (z0, z1) of block B: rows of every cell that
+// neither reads a ghost row nor touches the row at a face with a neighbour.
+// Empty when the block is too thin.
+void interior_rows(const HostBlock &B, int &y0, int &y1, int &z0, int &z1)
 {
-    out.clear();
-    for (int b = 0; b < (int)h->blocks.size(); ++b) {
-        const HostBlock &B = h->blocks[b];
-        int ex, ey, ez;
-        if (tx == 0) {
-            ex = std::min(B.n[0], kWG);
-            ey = std::min(B.n[1], std::max(1, kWG / ex));
-            ez = std::min(B.n[2], std::max(1, kWG / (ex * ey)));
-        } else {
-            ex = std::min(tx, B.n[0]);
-            ey = std::min(ty, B.n[1]);
-            ez = std::min(tz, B.n[2]);
-        }
-        for (int z0 = 0; z0 < B.n[2]; z0 += ez)
-            for (int y0 = 0; y0 < B.n[1]; y0 += ey)
-                for (int x0 = 0; x0 < B.n[0]; x0 += ex) {
-                    TileHost t;
-                    t.b = b;
-                    t.x0 = x0;
-                    t.y0 = y0;
-                    t.z0 = z0;
-                    t.ex = std::min(ex, B.n[0] - x0);
-                    t.ey = std::min(ey, B.n[1] - y0);
-                    t.ez = std::min(ez, B.n[2] - z0);
-                    out.push_back(t);
-                }
-    }
-    // longest-processing-time order for the persistent (grid-stride) launch
-    std::stable_sort(out.begin(), out.end(), [](const TileHost &a, const TileHost &b) {
-        return a.ex * a.ey * a.ez > b.ex * b.ey * b.ez;
-    });
+    y0 = B.nbr[10] >= 0 ? kFrontier : 0;  // neighbour at -y
+    y1 = B.n[1] - (B.nbr[16] >= 0 ? kFrontier : 0);
+    z0 = B.nbr[4] >= 0 ? kFrontier : 0;
+    z1 = B.n[2] - (B.nbr[22] >= 0 ? kFrontier : 0);
+    if (y0 >= y1 || z0 >= z1) y0 = y1 = z0 = z1 = 0;
 }
 
-size_t count_tiles(const wlb_blocks *h, int tx, int ty, int tz)
+bool in_interior(int y, int z, int y0, int y1, int z0, int z1) { return y >= y0 && y < y1 && z >= z0 && z < z1; }
+
+// Box tiles of block b over rows [y0, y1) x [z0, z1) (all x).  tx = 0 packs
+// whole rows.
+void tile_region(const HostBlock &B, int b, int tx, int ty, int tz, int y0, int y1, int z0, int z1,
+                 std::vector<TileHost> &out)
+{
+    if (y0 >= y1 || z0 >= z1) return;
+    int ex, ey, ez;
+    if (tx == 0) {
+        ex = std::min(B.n[0], kWG);
+        ey = std::min(y1 - y0, std::max(1, kWG / ex));
+        ez = std::min(z1 - z0, std::max(1, kWG / (ex * ey)));
+    } else {
+        ex = std::min(tx, B.n[0]);
+        ey = std::min(ty, y1 - y0);
+        ez = std::min(tz, z1 - z0);
+    }
+    for (int z = z0; z < z1; z += ez)
+        for (int y = y0; y < y1; y += ey)
+            for (int x = 0; x < B.n[0]; x += ex) {
+                TileHost t;
+                t.b = b;
+                t.x0 = x;
+                t.y0 = y;
+                t.z0 = z;
+                t.ex = std::min(ex, B.n[0] - x);
+                t.ey = std::min(ey, y1 - y);
+                t.ez = std::min(ez, z1 - z);
+                out.push_back(t);
+            }
+}
+
+// Sweep tiles of every block.  split: interior tiles first (their count in
+// *nint), then the frontier, each group in longest-processing-time order
+// for the persistent (grid-stride) launch.
+void build_tiles(const wlb_blocks *h, int tx, int ty, int tz, std::vector<TileHost> &out, bool split = false,
+                 int *nint = nullptr)
+{
+    out.clear();
+    std::vector<TileHost> outer;
+    for (int b = 0; b < (int)h->blocks.size(); ++b) {
+        const HostBlock &B = h->blocks[b];
+        if (!split) {
+            tile_region(B, b, tx, ty, tz, 0, B.n[1], 0, B.n[2], out);
+            continue;
+        }
+        int y0, y1, z0, z1;
+        interior_rows(B, y0, y1, z0, z1);
+        tile_region(B, b, tx, ty, tz, y0, y1, z0, z1, out);
+        if (y0 >= y1) {  // no interior: the whole block is frontier
+            tile_region(B, b, tx, ty, tz, 0, B.n[1], 0, B.n[2], outer);
+            continue;
+        }
+        tile_region(B, b, tx, ty, tz, 0, B.n[1], 0, z0, outer);
+        tile_region(B, b, tx, ty, tz, 0, B.n[1], z1, B.n[2], outer);
+        tile_region(B, b, tx, ty, tz, 0, y0, z0, z1, outer);
+        tile_region(B, b, tx, ty, tz, y1, B.n[1], z0, z1, outer);
+    }
+    auto lpt = [](const TileHost &a, const TileHost &b) { return a.ex * a.ey * a.ez > b.ex * b.ey * b.ez; };
+    std::stable_sort(out.begin(), out.end(), lpt);
+    std::stable_sort(outer.begin(), outer.end(), lpt);
+    if (nint) *nint = (int)out.size();
+    out.insert(out.end(), outer.begin(), outer.end());
+}
+
+size_t count_tiles(const wlb_blocks *h, int tx, int ty, int tz, bool split = false)
 {
     std::vector<TileHost> t;
-    build_tiles(h, tx, ty, tz, t);
+    build_tiles(h, tx, ty, tz, t, split);
     return t.size();
 }
 
@@ -196,9 +254,12 @@ int set_tiles(wlb_blocks *h, int tx, int ty, int tz, int grid)
     const bool list = tx == -1;
     if (list && !h->list_built) return fail(WLB_ERR_STATE, "fluid-cell tiles need an init with solid cells");
     std::vector<TileHost> t;
-    build_tiles(h, list ? 0 : tx, ty, tz, t);
+    int nint = 0;
+    build_tiles(h, list ? 0 : tx, ty, tz, t, h->overlap, &nint);
     if (t.size() > h->tile_cap) return fail(WLB_ERR_ARG, "tile shape yields %zu tiles > capacity", t.size());
     h->tiles.swap(t);
+    h->nint_tiles = nint;
+    h->tiles_split = h->overlap;
     h->shape[0] = tx;
     h->shape[1] = ty;
     h->shape[2] = tz;
@@ -217,19 +278,54 @@ int launch_grid(const wlb_blocks *h)
     return h->grid;
 }
 
-hipError_t sweep_dispatch(const wlb_blocks *h, bool odd)
+hipError_t sweep_launch(const wlb_blocks *h, bool odd, const SweepArgs &a, int g, hipStream_t st)
 {
-    const int g = launch_grid(h);
     switch (h->storage) {
-    case WLB_F64: return sweep_f64(h->q, h->collision, odd, h->args, g, h->stream);
-    case WLB_F32: return sweep_f32(h->q, h->collision, odd, h->args, g, h->stream);
-    case WLB_F16DEV: return sweep_f16(h->q, h->collision, odd, h->args, g, h->stream);
-    default: return sweep_bf16(h->q, h->collision, odd, h->args, g, h->stream);
+    case WLB_F64: return sweep_f64(h->q, h->collision, odd, a, g, st);
+    case WLB_F32: return sweep_f32(h->q, h->collision, odd, a, g, st);
+    case WLB_F16DEV: return sweep_f16(h->q, h->collision, odd, a, g, st);
+    default: return sweep_bf16(h->q, h->collision, odd, a, g, st);
     }
 }
 
-hipError_t exchange_dispatch(const wlb_blocks *h, bool after_odd)
+// The sweep is launched as an interior and a frontier part.
+bool split_sweeps(const wlb_blocks *h) { return h->overlap && (h->list_mode || h->tiles_split); }
+
+// Arguments of one part of a split sweep (its tiles and their count in *n)
+// and its workgroup count.
+SweepArgs part_args(const wlb_blocks *h, bool interior, int *n, int *grid)
 {
+    SweepArgs a = h->args;
+    const int nint = h->list_mode ? h->nint_ltiles : h->nint_tiles;
+    if (interior) {
+        a.nstiles = nint;
+    } else {
+        a.stiles = a.stiles + nint;
+        a.nstiles = a.nstiles - nint;
+    }
+    *n = a.nstiles;
+    *grid = (h->grid <= 0 || h->grid > *n) ? *n : h->grid;
+    return a;
+}
+
+// Whole sweep on the bound stream (both parts in turn when split).
+hipError_t sweep_dispatch(const wlb_blocks *h, bool odd)
+{
+    if (!split_sweeps(h)) return sweep_launch(h, odd, h->args, launch_grid(h), h->stream);
+    for (int part = 0; part < 2; ++part) {
+        int n = 0, g = 0;
+        const SweepArgs a = part_args(h, part == 0, &n, &g);
+        if (n > 0) {
+            const hipError_t e = sweep_launch(h, odd, a, g, h->stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t exchange_dispatch(const wlb_blocks *h, bool after_odd, hipStream_t st = nullptr)
+{
+    if (!st) st = h->stream;
     const std::vector<XItem> &v = after_odd ? h->push : h->pull;
     const XItem *items = reinterpret_cast<const XItem *>(h->arena + (after_odd ? h->off_push : h->off_pull));
     const DevBlock *blocks = reinterpret_cast<const DevBlock *>(h->arena + h->off_blocks);
@@ -238,10 +334,10 @@ hipError_t exchange_dispatch(const wlb_blocks *h, bool after_odd)
     const int n = (int)v.size();
     const int xm = h->args.xcd_map;
     switch (h->storage) {
-    case WLB_F64: return exchange_f64(pops, blocks, masks, items, n, xm, h->stream);
-    case WLB_F32: return exchange_f32(pops, blocks, masks, items, n, xm, h->stream);
-    case WLB_F16DEV: return exchange_f16(pops, blocks, masks, items, n, xm, h->stream);
-    default: return exchange_bf16(pops, blocks, masks, items, n, xm, h->stream);
+    case WLB_F64: return exchange_f64(pops, blocks, masks, items, n, xm, st);
+    case WLB_F32: return exchange_f32(pops, blocks, masks, items, n, xm, st);
+    case WLB_F16DEV: return exchange_f16(pops, blocks, masks, items, n, xm, st);
+    default: return exchange_bf16(pops, blocks, masks, items, n, xm, st);
     }
 }
 
@@ -350,12 +446,54 @@ int run_exchange(wlb_blocks *h, bool after_odd)
     return WLB_OK;
 }
 
+// Second stream and the fork / join events of the overlap (default
+// priority, like the bound stream).
+int ensure_stream2(wlb_blocks *h)
+{
+    if (!h->stream2) HIPCHK(hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking));
+    if (!h->ev_fork) HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    if (!h->ev_join) HIPCHK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    return WLB_OK;
+}
+
+// One step (sweep of the current parity, then its exchange).  With the
+// overlap, the frontier part of the sweep and the exchange run on the second
+// stream while the interior part runs on the bound stream; the step ends
+// when both have finished.  The exchange reads and writes only rows at block
+// faces and ghost rows, which no interior cell touches, and every population
+// location of a sweep belongs to exactly one cell, so the parts need no other
+// ordering.
+int enqueue_step(wlb_blocks *h, bool odd)
+{
+    if (!split_sweeps(h) || !h->stream2) {
+        HIPCHK(sweep_dispatch(h, odd));
+        HIPCHK(exchange_dispatch(h, odd));
+        return WLB_OK;
+    }
+    HIPCHK(hipEventRecord(h->ev_fork, h->stream));
+    HIPCHK(hipStreamWaitEvent(h->stream2, h->ev_fork, 0));
+    int n = 0, g = 0;
+    const SweepArgs af = part_args(h, false, &n, &g);
+    if (n > 0) HIPCHK(sweep_launch(h, odd, af, g, h->stream2));
+    HIPCHK(exchange_dispatch(h, odd, h->stream2));
+    const SweepArgs ai = part_args(h, true, &n, &g);
+    if (n > 0) HIPCHK(sweep_launch(h, odd, ai, g, h->stream));
+    HIPCHK(hipEventRecord(h->ev_join, h->stream2));
+    HIPCHK(hipStreamWaitEvent(h->stream, h->ev_join, 0));
+    return WLB_OK;
+}
+
 int one_step(wlb_blocks *h)
 {
     const bool odd = h->parity == 1;
-    int rc = run_sweep(h, odd);
-    if (rc) return rc;
-    rc = run_exchange(h, odd);
+    int rc;
+    if (h->timing) {  // per-kernel events: the parts run in turn on the bound stream
+        rc = run_sweep(h, odd);
+        if (rc) return rc;
+        rc = run_exchange(h, odd);
+    } else {
+        rc = enqueue_step(h, odd);
+    }
     if (rc) return rc;
     h->parity ^= 1;
     h->pending = 0;
@@ -377,13 +515,11 @@ int capture_graph(wlb_blocks *h)
 {
     drop_graph(h);
     HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = sweep_dispatch(h, false);
-    hipError_t e2 = exchange_dispatch(h, false);
-    hipError_t e3 = sweep_dispatch(h, true);
-    hipError_t e4 = exchange_dispatch(h, true);
+    const int r1 = enqueue_step(h, false);
+    const int r2 = r1 ? r1 : enqueue_step(h, true);
     hipGraph_t g = nullptr;
     hipError_t ec = hipStreamEndCapture(h->stream, &g);
-    if (e1 || e2 || e3 || e4 || ec != hipSuccess) {
+    if (r1 || r2 || ec != hipSuccess) {
         if (g) hipGraphDestroy(g);
         return fail(WLB_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ec != hipSuccess ? ec : hipErrorUnknown));
     }
@@ -466,17 +602,15 @@ int time_pairs(wlb_blocks *h, int reps, float *ms_out)
     HIPCHK(hipEventCreate(&b));
     // warm-up pair
     for (int k = 0; k < 2; ++k) {
-        HIPCHK(sweep_dispatch(h, false));
-        HIPCHK(exchange_dispatch(h, false));
-        HIPCHK(sweep_dispatch(h, true));
-        HIPCHK(exchange_dispatch(h, true));
+        int rc = enqueue_step(h, false);
+        if (!rc) rc = enqueue_step(h, true);
+        if (rc) return rc;
     }
     HIPCHK(hipEventRecord(a, h->stream));
     for (int k = 0; k < reps; ++k) {
-        HIPCHK(sweep_dispatch(h, false));
-        HIPCHK(exchange_dispatch(h, false));
-        HIPCHK(sweep_dispatch(h, true));
-        HIPCHK(exchange_dispatch(h, true));
+        int rc = enqueue_step(h, false);
+        if (!rc) rc = enqueue_step(h, true);
+        if (rc) return rc;
     }
     HIPCHK(hipEventRecord(b, h->stream));
     HIPCHK(hipEventSynchronize(b));
@@ -489,6 +623,7 @@ int time_pairs(wlb_blocks *h, int reps, float *ms_out)
 
 int autotune(wlb_blocks *h)
 {
+    h->overlap = false;  // candidates first without the overlap
     float best = 1e30f;
     int bs[3] = {0, 0, 0}, bg = 0;
     // repetitions scaled so each candidate runs ~ 2e8 cell updates at most
@@ -527,6 +662,23 @@ int autotune(wlb_blocks *h)
         }
     }
     h->lds_stage = blds;
+    h->overlap = false;
+    int rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
+    if (rc || (h->pull.empty() && h->push.empty())) return rc;
+    // the best configuration once more with the exchange overlapped
+    rc = ensure_stream2(h);
+    if (rc) return rc;
+    h->overlap = true;
+    rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
+    if (rc) return rc;
+    float ms = 0.f;
+    rc = time_pairs(h, reps, &ms);
+    if (rc) return rc;
+    if (log)
+        fprintf(stderr, "[wlb autotune] tile %d,%d,%d grid %d lds %d overlap 1: %.4f ms per two steps\n", bs[0], bs[1],
+                bs[2], bg, blds ? 1 : 0, ms);
+    if (ms < 0.99f * best) return WLB_OK;  // kept only for a clear gain (it adds launches and a second stream)
+    h->overlap = false;
     return set_tiles(h, bs[0], bs[1], bs[2], bg);
 }
 
@@ -684,7 +836,8 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     h->off_blocks = off;
     off += round_up(n * sizeof(DevBlock), 256);
     size_t cap = 0;
-    for (const auto &s : kShapes) cap = std::max(cap, count_tiles(h, s[0], s[1], s[2]));
+    for (const auto &s : kShapes)
+        cap = std::max(cap, std::max(count_tiles(h, s[0], s[1], s[2]), count_tiles(h, s[0], s[1], s[2], true)));
     h->tile_cap = cap;
     h->off_tiles = off;
     off += round_up(cap * sizeof(int4), 256);
@@ -695,7 +848,7 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     if (h->list_ok) {
         h->off_cells = off;
         off += round_up((size_t)h->ncells * 4, 256);
-        h->ltile_cap = (size_t)h->ncells / kWG + n + 1;
+        h->ltile_cap = (size_t)h->ncells / kWG + 2 * (size_t)n + 1;  // interior and frontier lists per block
         h->off_ltiles = off;
         off += round_up(h->ltile_cap * sizeof(int4), 256);
     }
@@ -817,6 +970,10 @@ int wlb_blocks_bind(wlb_blocks_t h, void *arena, size_t bytes, void *stream)
     HIPCHK(hipMemcpyAsync(h->arena + h->off_push, h->push.data(), h->push.size() * sizeof(XItem),
                           hipMemcpyHostToDevice, h->stream));
     h->bound = true;
+    if (h->overlap) {
+        int rc = ensure_stream2(h);
+        if (rc) return rc;
+    }
     h->args.arena = h->arena + h->off_pop;
     h->args.blocks = reinterpret_cast<const DevBlock *>(h->arena + h->off_blocks);
     h->args.tiles = reinterpret_cast<const int4 *>(h->arena + h->off_tiles);
@@ -913,20 +1070,30 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
     h->list_built = false;
     h->ltiles.clear();
     if (solid && nsolid > 0 && h->list_ok) {
+        // interior cells of every block first, then the frontier cells (the
+        // split that the interior/frontier overlap launches separately)
         std::vector<uint32_t> cells;
         cells.reserve((size_t)h->nfluid);
-        for (size_t b = 0; b < h->blocks.size(); ++b) {
-            const HostBlock &B = h->blocks[b];
-            const size_t first = cells.size();
-            for (int z = 0; z < B.n[2]; ++z)
-                for (int y = 0; y < B.n[1]; ++y)
-                    for (int x = 0; x < B.n[0]; ++x) {
-                        const int64_t g = ((int64_t)(B.org[2] + z) * h->dom[1] + (B.org[1] + y)) * h->dom[0] +
-                                          (B.org[0] + x);
-                        if (!solid[g]) cells.push_back((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20));
+        for (int pass = 0; pass < 2; ++pass) {
+            for (size_t b = 0; b < h->blocks.size(); ++b) {
+                const HostBlock &B = h->blocks[b];
+                int y0, y1, z0, z1;
+                interior_rows(B, y0, y1, z0, z1);
+                const size_t first = cells.size();
+                for (int z = 0; z < B.n[2]; ++z)
+                    for (int y = 0; y < B.n[1]; ++y) {
+                        if (in_interior(y, z, y0, y1, z0, z1) != (pass == 0)) continue;
+                        for (int x = 0; x < B.n[0]; ++x) {
+                            const int64_t g = ((int64_t)(B.org[2] + z) * h->dom[1] + (B.org[1] + y)) * h->dom[0] +
+                                              (B.org[0] + x);
+                            if (!solid[g]) cells.push_back((uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20));
+                        }
                     }
-            for (size_t k = first; k < cells.size(); k += kWG)
-                h->ltiles.push_back(make_int4((int)b, (int)k, 0, -(int)std::min<size_t>(kWG, cells.size() - k)));
+                for (size_t k = first; k < cells.size(); k += kWG)
+                    h->ltiles.push_back(
+                        make_int4((int)b, (int)k, 0, -(int)std::min<size_t>(kWG, cells.size() - k)));
+            }
+            if (pass == 0) h->nint_ltiles = (int)h->ltiles.size();
         }
         if (h->ltiles.size() <= h->ltile_cap && !cells.empty()) {
             HIPCHK(hipMemcpyAsync(h->arena + h->off_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice,
@@ -1126,6 +1293,7 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
     for (int a = 0; a < 3; ++a) o->tile[a] = h->shape[a];
     o->grid = h->grid;
     o->lds_staging = h->args.lds_stride > 0 ? 1 : 0;
+    o->overlap = split_sweeps(h) ? 1 : 0;
     o->n_xchg_items = (int32_t)h->pull.size();
     o->xchg_elems = h->xchg_elems;
     o->arena_bytes = h->arena_bytes;
@@ -1149,6 +1317,18 @@ int wlb_set_lds_staging(wlb_blocks_t h, int32_t on)
     h->lds_stage = on != 0;
     update_lds_stride(h);
     return WLB_OK;
+}
+
+int wlb_set_overlap(wlb_blocks_t h, int32_t on)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (on && h->bound) {
+        int rc = ensure_stream2(h);
+        if (rc) return rc;
+    }
+    h->overlap = on != 0;
+    h->graph_valid = false;
+    return set_tiles(h, h->shape[0], h->shape[1], h->shape[2], h->grid);
 }
 
 int wlb_set_graph(wlb_blocks_t h, int32_t on)
@@ -1189,7 +1369,11 @@ void wlb_blocks_destroy(wlb_blocks_t h)
 {
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->stream2) hipStreamSynchronize(h->stream2);
     drop_graph(h);
+    if (h->stream2) hipStreamDestroy(h->stream2);
+    if (h->ev_fork) hipEventDestroy(h->ev_fork);
+    if (h->ev_join) hipEventDestroy(h->ev_join);
     for (auto &e : h->ev_pool) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);

@@ -78,6 +78,7 @@ class wlb_info_t(C.Structure):
         ("xchg_elems", C.c_int64),
         ("arena_bytes", C.c_size_t),
         ("pop_bytes", C.c_size_t),
+        ("overlap", C.c_int32),
     ]
 
 
@@ -111,6 +112,7 @@ _sig = {
     "wlb_set_tiles": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "wlb_set_graph": (C.c_int, [_h, C.c_int32]),
     "wlb_set_lds_staging": (C.c_int, [_h, C.c_int32]),
+    "wlb_set_overlap": (C.c_int, [_h, C.c_int32]),
     "wlb_set_kernel_timing": (C.c_int, [_h, C.c_int32]),
     "wlb_kernel_times": (C.c_int, [_h, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "wlb_blocks_destroy": (None, [_h]),
@@ -208,6 +210,10 @@ def wlb_set_tiles(h, tx, ty, tz, grid):
 
 def wlb_set_lds_staging(h, on):
     _check(_lib.wlb_set_lds_staging(h, 1 if on else 0))
+
+
+def wlb_set_overlap(h, on):
+    _check(_lib.wlb_set_overlap(h, 1 if on else 0))
 
 
 def wlb_set_graph(h, on):
@@ -372,6 +378,9 @@ class Blocks:
 
     def set_lds_staging(self, on):
         wlb_set_lds_staging(self.h, on)
+
+    def set_overlap(self, on):
+        wlb_set_overlap(self.h, on)
 
     def set_graph(self, on):
         wlb_set_graph(self.h, on)

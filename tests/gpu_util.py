@@ -14,7 +14,7 @@ def say(msg):
 
 
 def gpu_run(blocks, domain, periodic, q, storage, coll, params, rho, u, solid=None, steps=0, tiles=None,
-            graph=True, mode="step", lds=False):
+            graph=True, mode="step", lds=False, overlap=False):
     """Returns (d[q][N] natural-layout deviations, rho, u, totals, Blocks)."""
     from paper_1909_13772_amd import wlb
     B = wlb.Blocks(blocks, domain, periodic, stencil=q, storage=storage)
@@ -23,6 +23,8 @@ def gpu_run(blocks, domain, periodic, q, storage, coll, params, rho, u, solid=No
         B.set_tiles(*tiles)
     B.set_graph(graph)
     B.set_lds_staging(lds)
+    if overlap:
+        B.set_overlap(True)
     if mode == "step":
         B.step(steps)
     else:

@@ -28,16 +28,18 @@ def _check(case, q, gpu, orc, solid, n):
 
 
 @pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
-def test_one_cell_thick_blocks(q, coll):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_one_cell_thick_blocks(q, coll, overlap):
     """Blocks one cell thick along every axis: ghost regions are whole blocks
-    and every exchange item touches a block's full extent."""
-    say(f"case thin blocks q{q} c{coll}")
+    and every exchange item touches a block's full extent (with the overlap,
+    no block has an interior)."""
+    say(f"case thin blocks q{q} c{coll} overlap {overlap}")
     blocks, dom = inputs.rectilinear_blocks([1, 6, 1], [1, 4], [2, 1, 3])
     rho, u = inputs.random_state(dom, seed=31, umag=0.02)
     F = (1e-5, -1e-5, 2e-6)
     p = wlb.make_params(tau=0.7, magic=3 / 16, omega_bulk=1.1, omega_higher=1.0, force=F)
     for periodic in ((1, 1, 1), (1, 0, 1)):
-        gpu = gpu_run(blocks, dom, periodic, q, wlb.F64, coll, p, rho, u, steps=7)
+        gpu = gpu_run(blocks, dom, periodic, q, wlb.F64, coll, p, rho, u, steps=7, overlap=overlap)
         op = oracle_params(q, coll, 0.7, 3 / 16, periodic, F, omega_bulk=1.1, omega_higher=1.0)
         orc = oracle_run(op, dom, rho, u, None, 7)
         _check(f"thin {periodic}", q, gpu, orc, None, np.prod(dom))

@@ -119,6 +119,16 @@ def test_porous_uneven_blocks_lds_staged_odd_sweep_fp64(q, coll):
     _compare(f"porous lds q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
 
 
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+def test_porous_uneven_blocks_overlapped_exchange_fp64(q, coll):
+    """The porous case with each sweep split into interior and frontier and
+    the frontier plus the exchange on a second stream."""
+    say(f"case porous overlap q{q} coll{coll}")
+    gpu, orc, solid, dom = _porous_case(q, coll, wlb.F64, 11, overlap=True)
+    assert gpu[4].info().overlap == 1
+    _compare(f"porous overlap q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
+
+
 @pytest.mark.parametrize("coll", [0, 1])
 def test_smagorinsky_fp64(coll):
     say(f"case smagorinsky coll{coll}")
@@ -258,10 +268,16 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
     runs = [dict(), dict(tiles=(16, 4, 4, 0)), dict(tiles=(64, 4, 1, 7)), dict(tiles=(8, 8, 4, 3)),
             dict(graph=False), dict(mode="split"), dict(lds=True), dict(lds=True, tiles=(16, 4, 4, 0)),
             dict(tiles=(0, 0, 0, -1)), dict(tiles=(16, 4, 4, -1), mode="split"), dict(tiles=(-1, 0, 0, 0)),
-            dict(tiles=(-1, 0, 0, -1)), dict(tiles=(-1, 0, 0, 5), graph=False)]
+            dict(tiles=(-1, 0, 0, -1)), dict(tiles=(-1, 0, 0, 5), graph=False),
+            # interior/frontier overlap on two streams
+            dict(overlap=True), dict(overlap=True, graph=False), dict(overlap=True, mode="split"),
+            dict(overlap=True, tiles=(16, 4, 4, -1)), dict(overlap=True, tiles=(64, 4, 1, 7)),
+            dict(overlap=True, tiles=(-1, 0, 0, 0)), dict(overlap=True, tiles=(-1, 0, 0, -1), graph=False),
+            dict(overlap=True, lds=True)]
     ref = None
     for kw in runs:
         d, r, uu, tot, B = gpu_run(blocks, dom, (1, 1, 0), 19, wlb.F32, wlb.TRT, p, rho, u, solid, steps=13, **kw)
+        assert B.info().overlap == int(kw.get("overlap", False)), kw
         B.close()
         if ref is None:
             ref = d
