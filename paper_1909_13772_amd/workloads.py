@@ -43,7 +43,7 @@ def _timed_steps(B, steps, warmup, kernel_steps=None):
     return t1 - t0, ms, cnt
 
 
-def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0, seed_spheres=1):
+def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0, seed_spheres=1, overlap=None):
     """512 uneven blocks (rectilinear 8x8x8, edges from {16,24,32,48,64}),
     random spheres (radius 3-8, solid fraction >= 0.3), D3Q27 MRT, tau 0.8,
     density faces on x (1.0005 / 0.9995), periodic y/z, FP32 storage."""
@@ -58,6 +58,8 @@ def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0
     B = wlb.Blocks(blocks, dom, (0, 1, 1), stencil=27, storage=storage)
     try:
         B.init(wlb.MRT, p, rho, u, solid)
+        if overlap is not None:  # override the autotuner's choice
+            B.set_overlap(overlap)
         secs, ms, cnt = _timed_steps(B, steps, warmup, kernel_steps=50)
         info = B.info()
         force = B.force()  # momentum exchanged with the spheres in the last step
