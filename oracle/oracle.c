@@ -12,7 +12,9 @@
  *   - update f_i(x + c_i, t + 1) = f_i(x, t) + Omega_i(f(x, t)):
  *     collision, then streaming to the neighbour                   (Eq. 2)
  *   - MRT collision Omega = -M^{-1} S (M f - m_eq)                   (Eq. 3)
- *     with SRT and TRT as special choices of S (Sec. 5.1.1)
+ *     with SRT and TRT as special choices of S (Sec. 5.1.1), and the KBC
+ *     entropic stabilisation as a per-cell choice of the higher rates
+ *     (Sec. 5.1.1, Boesch et al. 2015)
  *   - locally varying relaxation time from a closure (Sec. 5.1.1,
  *     turbulence models after Yu et al. 2005)
  *   - no-slip / pressure boundaries and body-force driving (Sec. 5.1.1,
@@ -55,7 +57,7 @@
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int q;                /* 19 or 27 */
-    int collision;        /* 0 = SRT, 1 = TRT, 2 = MRT */
+    int collision;        /* 0 = SRT, 1 = TRT, 2 = MRT, 3 = KBC (MRT basis, entropic higher rates) */
     double tau;           /* shear relaxation time tau_0 */
     double magic;         /* TRT magic parameter Lambda */
     double omega_bulk;    /* MRT rate of x2+y2+z2 */
@@ -419,7 +421,7 @@ static int make_ctx(const orc_params *p, ctx_t *cx)
 {
     if (make_lattice(p->q, &cx->L)) return -1;
     cx->have_mrt = 0;
-    if (p->collision == 2) {
+    if (p->collision == 2 || p->collision == 3) {
         if (make_mrt(&cx->L, &cx->B)) return -1;
         cx->have_mrt = 1;
     }
@@ -535,6 +537,39 @@ static void collide_cell(const orc_params *p, const ctx_t *cx, const double *d, 
             case 2: s[r] = p->omega_bulk; break;
             default: s[r] = p->omega_higher; break;
             }
+        }
+        if (p->collision == 3) {
+            /* KBC entropic stabilisation (Sec. 5.1.1; Boesch, Chikatamarla,
+             * Karlin 2015): split f - f_eq by moment class into the kinematic
+             * part k (conserved moments), the shear part s (deviatoric second
+             * moments) and the rest h (trace of the second moments and all
+             * higher moments).  s relaxes at 2 beta = 1/tau; h at gamma beta,
+             * with gamma the stationary point of the quadratic entropy
+             * sum (f* - f_eq)^2 / f_eq of the post-collision state:
+             * gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>,
+             * <x|y> = sum x_i y_i / f_eq_i; gamma = 2 when dh vanishes. */
+            double mneq[OQ], ds[OQ], dh[OQ];
+            for (int r = 0; r < q; ++r) {
+                mneq[r] = 0.0;
+                for (int i = 0; i < q; ++i) mneq[r] += B->M[r][i] * (d[i] - de[i]);
+            }
+            for (int i = 0; i < q; ++i) {
+                ds[i] = dh[i] = 0.0;
+                for (int r = 0; r < q; ++r) {
+                    if (B->kind[r] == 1) ds[i] += B->Minv[i][r] * mneq[r];
+                    else if (B->kind[r] >= 2) dh[i] += B->Minv[i][r] * mneq[r];
+                }
+            }
+            double sh = 0.0, hh = 0.0;
+            for (int i = 0; i < q; ++i) {
+                double feq = L->w[i] + de[i];
+                sh += ds[i] * dh[i] / feq;
+                hh += dh[i] * dh[i] / feq;
+            }
+            double beta = 0.5 / tau;
+            double gamma = hh > 1e-30 ? 1.0 / beta - (2.0 - 1.0 / beta) * sh / hh : 2.0;
+            for (int r = 0; r < q; ++r)
+                if (B->kind[r] >= 2) s[r] = gamma * beta;
         }
         double g[OQ];
         for (int r = 0; r < q; ++r) {

@@ -94,7 +94,7 @@ def _random_cell(q, rng, amp=1e-3):
 
 
 @pytest.mark.parametrize("q", [19, 27])
-@pytest.mark.parametrize("coll", [O.SRT, O.TRT, O.MRT])
+@pytest.mark.parametrize("coll", [O.SRT, O.TRT, O.MRT, O.KBC])
 def test_collision_conserves_mass_and_momentum(q, coll):
     c, w, _ = O.stencil(q)
     rng = np.random.default_rng(3 + q + coll)
@@ -144,6 +144,60 @@ def test_mrt_with_equal_rates_is_srt(q):
         a = O.collide_cell(srt, d)[0]
         b = O.collide_cell(mrt, d)[0]
         assert np.abs(a - b).max() < 1e-13 * np.abs(a).max()
+
+
+def test_kbc_at_tau_one_is_srt():
+    """At tau = 1 (beta = 1/2) the entropic stabiliser is 2 for every state,
+    so every non-conserved moment relaxes at 1/tau: SRT, force included."""
+    rng = np.random.default_rng(12)
+    F = tuple(rng.uniform(-1e-4, 1e-4, 3))
+    srt = O.Params(q=27, collision=O.SRT, tau=1.0, force=F)
+    kbc = O.Params(q=27, collision=O.KBC, tau=1.0, force=F)
+    for _ in range(5):
+        d = _random_cell(27, rng, amp=1e-2)
+        a = O.collide_cell(srt, d)[0]
+        b = O.collide_cell(kbc, d)[0]
+        assert np.abs(a - b).max() < 1e-14 * np.abs(a).max()
+
+
+def _kbc_parts(d, q=27):
+    """Non-equilibrium f - f_eq, its moments and its h part (trace of the
+    second moments and higher moments), from the oracle's moment matrix."""
+    c, w, _ = O.stencil(q)
+    M, Minv, kind = O.mrt_matrix(q)
+    rho = 1.0 + d.sum()
+    u = (c.T @ d) / rho
+    de = O.equilibrium(q, rho, u)
+    neq = d - de
+    m = M @ neq
+    hmask = kind >= 2
+    dh = Minv[:, hmask] @ m[hmask]
+    return M, kind, de, w + de, m, dh
+
+
+@pytest.mark.parametrize("tau", [0.505, 0.6, 0.9])
+def test_kbc_post_collision_state_is_entropy_stationary(tau):
+    """KBC picks the higher-order rate so that the post-collision state is a
+    stationary point of the quadratic entropy sum (f* - f_eq)^2 / f_eq along
+    the higher-order direction: <f* - f_eq | dh> = 0 in the entropic scalar
+    product.  Meanwhile conserved moments stay and the shear moments relax at
+    exactly 1/tau (no force)."""
+    rng = np.random.default_rng(13)
+    p = O.Params(q=27, collision=O.KBC, tau=tau)
+    mrt = O.Params(q=27, collision=O.MRT, tau=tau, omega_bulk=1 / tau, omega_higher=1 / tau)
+    for _ in range(6):
+        d = _random_cell(27, rng, amp=3e-2)
+        M, kind, de, feq, m, dh = _kbc_parts(d)
+        post = O.collide_cell(p, d)[0]
+        pneq = post - de
+        hh = np.sum(dh * dh / feq)
+        assert abs(np.sum(pneq * dh / feq)) < 1e-10 * hh
+        mp = M @ pneq
+        assert np.abs(mp[kind == 0]).max() < 1e-15
+        shear = kind == 1
+        assert np.abs(mp[shear] - (1 - 1 / tau) * m[shear]).max() < 1e-13 * np.abs(m[shear]).max()
+        # and it differs from MRT with every rate 1/tau (the stabiliser acts)
+        assert np.abs(post - O.collide_cell(mrt, d)[0]).max() > 1e-9
 
 
 @pytest.mark.parametrize("q", [19, 27])
