@@ -202,7 +202,8 @@ def main():
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
     ap.add_argument("--lds-staging", type=int, choices=[0, 1], default=None,
                     help="with --no-autotune: odd sweep staged in LDS (1) or direct (0) for the headline run")
-    ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures"], default="channel",
+    ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic"],
+                    default="channel",
                     help="channel = the headline configuration; the others print their own JSON line")
     ap.add_argument("--tau", type=float, default=0.5005, help="relaxation time of the turbulence workload")
     args = ap.parse_args()
@@ -222,6 +223,8 @@ def main():
             r = workloads.porous(wlb, steps=args.steps, warmup=args.warmup, autotune=not args.no_autotune)
         elif args.workload == "turbulence":
             r = workloads.turbulence_precision(wlb, steps=args.steps, tau=args.tau)
+        elif args.workload == "entropic":
+            r = workloads.entropic_stability(wlb, steps=args.steps, tau=args.tau)
         else:
             r = workloads.closure_cost(wlb, steps=args.steps, warmup=args.warmup)
         print(json.dumps(r))
@@ -241,7 +244,8 @@ def main():
                                           ("bf16dev", wlb.BF16DEV, 2, 0, 19, None),
                                           ("f32_smagorinsky", wlb.F32, 4, 1, 19, None),
                                           ("f32_mlp_closure", wlb.F32, 4, 2, 19, None),
-                                          ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT)):
+                                          ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT),
+                                          ("f32_d3q27_kbc", wlb.F32, 4, 0, 27, wlb.KBC)):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
                            q=q, coll=coll, check=True)
             sm = summarize(r, st, args.variant_steps, eb, q=q)

@@ -992,7 +992,8 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
 {
     if (!h || !p || !rho || !u) return fail(WLB_ERR_ARG, "null argument");
     if (!h->bound) return fail(WLB_ERR_STATE, "wlb_blocks_bind must come first");
-    if (collision < WLB_SRT || collision > WLB_MRT) return fail(WLB_ERR_ARG, "bad collision operator");
+    if (collision < WLB_SRT || collision > WLB_KBC) return fail(WLB_ERR_ARG, "bad collision operator");
+    if (collision == WLB_KBC && h->q != WLB_D3Q27) return fail(WLB_ERR_UNSUPPORTED, "KBC runs with D3Q27");
     if (!(p->tau > 0.5)) return fail(WLB_ERR_ARG, "tau must exceed 1/2");
     if (collision == WLB_TRT && !(p->magic > 0.0)) return fail(WLB_ERR_ARG, "TRT needs magic > 0");
     if (p->pressure_axis < -1 || p->pressure_axis > 2) return fail(WLB_ERR_ARG, "bad pressure axis");
@@ -1001,7 +1002,7 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
     if (p->closure < WLB_CLOSURE_NONE || p->closure > WLB_CLOSURE_MLP) return fail(WLB_ERR_ARG, "bad closure");
     if (p->closure == WLB_CLOSURE_MLP) {
         if (!p->mlp) return fail(WLB_ERR_ARG, "the MLP closure needs weights");
-        if (h->q != WLB_D3Q19 || collision == WLB_MRT || h->storage == WLB_F64)
+        if (h->q != WLB_D3Q19 || collision >= WLB_MRT || h->storage == WLB_F64)
             return fail(WLB_ERR_UNSUPPORTED, "the MLP closure runs with D3Q19 SRT/TRT and FP32/FP16/BF16 storage");
     }
     h->collision = collision;

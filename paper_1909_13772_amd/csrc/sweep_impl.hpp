@@ -307,7 +307,16 @@ __device__ __forceinline__ T source_moment(const MomentSources<T> &s)
 // zero: D3Q19 distributions are exactly those whose moments with a factor
 // xyz vanish, a subspace that the relaxation maps into itself.  With the
 // Smagorinsky closure omega comes from the non-equilibrium second moments.
-template <int Q, typename T>
+// KBC (Sec. 5.1.1: entropic stabilisation, Boesch, Chikatamarla and Karlin):
+// the same transform; f - f_eq splits by moment class into the conserved
+// part, the shear part s (deviatoric second moments, relaxed at
+// 2 beta = omega) and the rest h (trace of the second moments and every
+// moment of order >= 3), which relaxes at gamma beta with
+//   gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>,  <x|y> = sum x_i y_i / f_eq_i,
+// the stationary point of the quadratic entropy of the post-collision state
+// (gamma = 2 when dh vanishes).  ds and dh are taken back to populations by
+// the inverse transform for the two entropic products.
+template <int Q, typename T, bool KBC = false>
 __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omb, T omh,
                                             int closure, T tau0, T smag_k)
 {
@@ -331,6 +340,46 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
     if (closure == 1) {
         const T P[6] = {mn[XX], mn[YY], mn[ZZ], mn[XY], mn[XZ], mn[YZ]};
         om = recip(tau_smagorinsky<T>(P, m.rho, tau0, smag_k));
+    }
+    if constexpr (KBC) {
+        static_assert(Q == 27, "KBC runs on D3Q27");
+        T vs[27], vh[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) vs[k] = vh[k] = T(0);
+        const T t3 = (mn[XX] + mn[YY] + mn[ZZ]) * (T(1) / T(3));
+        vs[XX] = mn[XX] - t3;
+        vs[YY] = mn[YY] - t3;
+        vs[ZZ] = mn[ZZ] - t3;
+        vs[XY] = mn[XY];
+        vs[XZ] = mn[XZ];
+        vs[YZ] = mn[YZ];
+        vh[XX] = vh[YY] = vh[ZZ] = t3;
+        sfor<27>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            if constexpr (k % 3 + (k / 3) % 3 + k / 9 >= 3) vh[k] = mn[k];
+        });
+        tvalues<2>(vs);
+        tvalues<1>(vs);
+        tvalues<0>(vs);
+        tvalues<2>(vh);
+        tvalues<1>(vh);
+        tvalues<0>(vh);
+        // f_eq_i = w_i (1 + A + rho c.u (3 + 9/2 c.u)), A = drho - 3/2 rho u.u
+        const T A1 = T(1) + m.drho - T(1.5) * m.rho * m.uu;
+        T sh = T(0), hh = T(0);
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr T w = weight<Q, T>(i);
+            const T cu = cdot<i>(m.u);
+            const T r = recip(w * (A1 + m.rho * cu * (T(3) + T(4.5) * cu)));
+            const T h = vh[tpos(i)];
+            sh += vs[tpos(i)] * h * r;
+            hh += h * h * r;
+        });
+        const T beta = T(0.5) * om, ib = recip(beta);
+        const T gamma = hh > T(1e-30) ? ib - (T(2) - ib) * sh * recip(hh) : T(2);
+        omh = gamma * beta;
+        omb = omh;
     }
     T g[27];
     sfor<27>([&](auto K) {
@@ -484,8 +533,8 @@ __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p
 {
     const Macro<Q, T> m = moments_of<Q, T>(d, p.F);
     T om = p.om, omm = p.omm;
-    if constexpr (COLL == 2) {
-        mrt_collide<Q, T>(d, m, p.F, om, p.omb, p.omh, p.closure, p.tau0, p.smag_k);
+    if constexpr (COLL == 2 || COLL == 3) {
+        mrt_collide<Q, T, COLL == 3>(d, m, p.F, om, p.omb, p.omh, p.closure, p.tau0, p.smag_k);
     } else {
         if (p.closure == 1) {
             T P[6];
@@ -1459,6 +1508,9 @@ static hipError_t sweep_c(int coll, bool odd, const SweepArgs &a, int grid, hipS
     case 0: return sweep_q<Q, 0>(odd, a, grid, st);
     case 1: return sweep_q<Q, 1>(odd, a, grid, st);
     case 2: return sweep_q<Q, 2>(odd, a, grid, st);
+    case 3:
+        if constexpr (Q == 27) return sweep_q<Q, 3>(odd, a, grid, st);
+        return hipErrorNotSupported;
     default: return hipErrorInvalidValue;
     }
 }
