@@ -60,7 +60,9 @@ def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0
         B.init(wlb.MRT, p, rho, u, solid)
         if overlap is not None:  # override the autotuner's choice
             B.set_overlap(overlap)
-        secs, ms, cnt = _timed_steps(B, steps, warmup, kernel_steps=50)
+        # per-kernel events over the timed steps, as for the channel, unless
+        # the sweep parts run concurrently (then timed in a separate run)
+        secs, ms, cnt = _timed_steps(B, steps, warmup, kernel_steps=50 if B.info().overlap else None)
         info = B.info()
         force = B.force()  # momentum exchanged with the spheres in the last step
         r, uu, tot = B.moments()
