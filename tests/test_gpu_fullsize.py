@@ -77,3 +77,23 @@ def test_turbulence_384_fp64_sampled():
     eu, er = crop_compare(op, dom, (1, 1, 1), rho, u, None, r, uu, regions, m, s)
     say(f"turbulence 384 sampled: u rel {eu:.3e}, rho abs {er:.3e}")
     assert eu <= 1e-12 and er <= 1e-13
+
+
+def test_entropic_kbc_384_fp32_sampled():
+    """The entropic-stability configuration (D3Q27 KBC, FP32, tau 0.5005,
+    384^3 decaying turbulence), autotuned as the workload runs it."""
+    say("case full-size kbc 384 fp32")
+    n, s, m = 384, 4, 8
+    dom = (n, n, n)
+    rho, u = inputs.turbulence_bandlimited(n, 0)
+    p = wlb.make_params(tau=0.5005, autotune=1)
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 1, 1), stencil=27, storage=wlb.F32)
+    B.init(wlb.KBC, p, rho, u)
+    B.step(s)
+    r, uu, tot = B.moments()
+    B.close()
+    op = O.Params(q=27, collision=O.KBC, tau=0.5005, periodic=(1, 1, 1))
+    regions = [(0, 0, 0), (200, 300, 31), (380, 5, 190)]
+    eu, er = crop_compare(op, dom, (1, 1, 1), rho, u, None, r, uu, regions, m, s)
+    say(f"kbc 384 sampled: u rel {eu:.3e}, rho abs {er:.3e}")
+    assert eu <= 1e-5 and er <= 1e-6
