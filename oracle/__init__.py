@@ -34,7 +34,7 @@ MLP_OFF_W3 = MLP_OFF_B2 + MLP_H
 MLP_OFF_B3 = MLP_OFF_W3 + MLP_H
 MLP_NPARAM = MLP_OFF_B3 + 1
 
-SRT, TRT, MRT, KBC = 0, 1, 2, 3
+SRT, TRT, MRT, KBC, CUMULANT = 0, 1, 2, 3, 4
 CLOSURE_NONE, CLOSURE_SMAG, CLOSURE_MLP = 0, 1, 2
 
 

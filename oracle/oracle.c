@@ -14,7 +14,8 @@
  *   - MRT collision Omega = -M^{-1} S (M f - m_eq)                   (Eq. 3)
  *     with SRT and TRT as special choices of S (Sec. 5.1.1), and the KBC
  *     entropic stabilisation as a per-cell choice of the higher rates
- *     (Sec. 5.1.1, Boesch et al. 2015)
+ *     (Sec. 5.1.1, Boesch et al. 2015), and the cumulant collision
+ *     (Sec. 5.1.1, Geier et al. 2015)
  *   - locally varying relaxation time from a closure (Sec. 5.1.1,
  *     turbulence models after Yu et al. 2005)
  *   - no-slip / pressure boundaries and body-force driving (Sec. 5.1.1,
@@ -57,7 +58,8 @@
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int q;                /* 19 or 27 */
-    int collision;        /* 0 = SRT, 1 = TRT, 2 = MRT, 3 = KBC (MRT basis, entropic higher rates) */
+    int collision;        /* 0 = SRT, 1 = TRT, 2 = MRT, 3 = KBC (MRT basis, entropic higher rates),
+                             4 = cumulant (D3Q27) */
     double tau;           /* shear relaxation time tau_0 */
     double magic;         /* TRT magic parameter Lambda */
     double omega_bulk;    /* MRT rate of x2+y2+z2 */
@@ -420,6 +422,7 @@ typedef struct {
 static int make_ctx(const orc_params *p, ctx_t *cx)
 {
     if (make_lattice(p->q, &cx->L)) return -1;
+    if (p->collision == 4 && p->q != 27) return -1; /* the cumulant collision needs all 27 central moments */
     cx->have_mrt = 0;
     if (p->collision == 2 || p->collision == 3) {
         if (make_mrt(&cx->L, &cx->B)) return -1;
@@ -478,6 +481,86 @@ static double tau_smag(double tau0, double cs, const double P[6], double rho)
     return 0.5 * (tau0 + sqrt(tau0 * tau0 + 18.0 * sqrt(2.0) * cs * cs * sqrt(Q) / rho));
 }
 
+/* E[X_k1 X_k2 ... X_kn] of a zero-mean Gaussian with covariance S: the sum
+ * over all pairings of the indices of the products of the paired
+ * covariances (Isserlis), by recursion on the first index. */
+static double gauss_moment(const double S[3][3], const int *idx, int n)
+{
+    if (n == 0) return 1.0;
+    if (n % 2) return 0.0;
+    double sum = 0.0;
+    int rest[8];
+    for (int j = 1; j < n; ++j) {
+        int k = 0;
+        for (int t = 1; t < n; ++t)
+            if (t != j) rest[k++] = idx[t];
+        sum += S[idx[0]][idx[j]] * gauss_moment(S, rest, n - 2);
+    }
+    return sum;
+}
+
+/* Cumulant collision (Sec. 5.1.1: cumulants instead of moments relaxed to
+ * their equilibria, Geier et al. 2015), D3Q27, in the form with every
+ * cumulant of order >= 3 relaxed at rate 1 (to zero):
+ *   - u = (j + F/2)/rho; the second-order cumulants are the covariance
+ *     S = sum f (c - u)(c - u) / rho;
+ *   - the deviatoric part of S relaxes at 1/tau, its trace at omega_bulk
+ *     towards 3 c_s^2 = 1;
+ *   - the post-collision distribution has density rho, first-order central
+ *     moments F/2 (the force enters through the velocity shift and these,
+ *     so that sum c f* = j + F), second-order central moments rho S*, and
+ *     higher central moments rho E[X^a Y^b Z^c] of a zero-mean Gaussian with
+ *     covariance S* (all higher cumulants zero);
+ *   - the populations follow from the q central moments by solving the
+ *     linear system V f* = kappa*, V_(abc),i = (c_i - u)^(a,b,c), a,b,c <= 2. */
+static void cumulant_cell(const orc_params *p, const lattice *L, const double *d, double tau, double rho,
+                          const double u[3], double *dout)
+{
+    int q = L->q;
+    double f[OQ], S[3][3];
+    for (int i = 0; i < q; ++i) f[i] = L->w[i] + d[i];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double k2 = 0.0;
+            for (int i = 0; i < q; ++i) k2 += f[i] * (L->c[i][a] - u[a]) * (L->c[i][b] - u[b]);
+            S[a][b] = k2 / rho;
+        }
+    double om = 1.0 / tau, ob = p->omega_bulk;
+    double tr = S[0][0] + S[1][1] + S[2][2];
+    double Sp[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double dev = S[a][b] - (a == b ? tr / 3.0 : 0.0);
+            Sp[a][b] = (1.0 - om) * dev + (a == b ? (tr - ob * (tr - 1.0)) / 3.0 : 0.0);
+        }
+    /* rows (a, b, c) with a, b, c <= 2 in the order a + 3 b + 9 c */
+    double V[OQ][OQ], Vinv[OQ][OQ], kap[OQ];
+    for (int r = 0; r < 27; ++r) {
+        int e[3] = {r % 3, (r / 3) % 3, r / 9};
+        for (int i = 0; i < q; ++i) {
+            double v = 1.0;
+            for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < e[a]; ++k) v *= L->c[i][a] - u[a];
+            V[r][i] = v;
+        }
+        int order = e[0] + e[1] + e[2];
+        if (order == 0) kap[r] = rho;
+        else if (order == 1) kap[r] = 0.5 * p->force[e[0] ? 0 : (e[1] ? 1 : 2)];
+        else {
+            int idx[6], n = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < e[a]; ++k) idx[n++] = a;
+            kap[r] = rho * gauss_moment(Sp, idx, n);
+        }
+    }
+    invert(q, V, Vinv);
+    for (int i = 0; i < q; ++i) {
+        double fi = 0.0;
+        for (int r = 0; r < q; ++r) fi += Vinv[i][r] * kap[r];
+        dout[i] = fi - L->w[i];
+    }
+}
+
 /* Collide one cell: d_in -> d_out (deviations).  Also returns rho, u (Guo
  * velocity) and the relaxation time used. */
 static void collide_cell(const orc_params *p, const ctx_t *cx, const double *d, double *dout,
@@ -513,7 +596,9 @@ static void collide_cell(const orc_params *p, const ctx_t *cx, const double *d, 
     *tau_out = tau;
     *rho_out = rho;
 
-    if (p->collision == 0) { /* SRT */
+    if (p->collision == 4) { /* cumulant (D3Q27) */
+        cumulant_cell(p, L, d, tau, rho, u, dout);
+    } else if (p->collision == 0) { /* SRT */
         double om = 1.0 / tau;
         for (int i = 0; i < q; ++i) dout[i] = d[i] - om * (d[i] - de[i]) + (1.0 - 0.5 * om) * Fi[i];
     } else if (p->collision == 1) { /* TRT */

@@ -200,6 +200,65 @@ def test_kbc_post_collision_state_is_entropy_stationary(tau):
         assert np.abs(post - O.collide_cell(mrt, d)[0]).max() > 1e-9
 
 
+def _central(post_f, u, c):
+    """Central moments sum f (c - u)^(a,b,c) of a cell, computed here."""
+    rel = c - u
+    return lambda a, b, cc: float(np.sum(post_f * rel[:, 0] ** a * rel[:, 1] ** b * rel[:, 2] ** cc))
+
+
+def test_cumulant_at_tau_one_is_the_factorized_equilibrium():
+    """With every rate 1 the post-collision cumulants are those of
+    equilibrium (covariance c_s^2 I, nothing of higher order), which is the
+    product over the axes of the three-velocity weights
+    psi(0) = 2/3 - u^2, psi(+-1) = (1/3 + u^2 +- u) / 2."""
+    rng = np.random.default_rng(14)
+    c, w, _ = O.stencil(27)
+    p = O.Params(q=27, collision=O.CUMULANT, tau=1.0, omega_bulk=1.0)
+    for _ in range(5):
+        d = _random_cell(27, rng, amp=2e-2)
+        rho = 1.0 + d.sum()
+        u = (c.T @ d) / rho
+        post = O.collide_cell(p, d)[0] + w
+        psi = lambda ca, ua: (2.0 / 3.0 - ua * ua) if ca == 0 else 0.5 * (1.0 / 3.0 + ua * ua + ca * ua)
+        feq = np.array([rho * psi(ci[0], u[0]) * psi(ci[1], u[1]) * psi(ci[2], u[2]) for ci in c])
+        assert np.abs(post - feq).max() < 1e-15
+
+
+@pytest.mark.parametrize("tau,ob", [(0.55, 1.0), (0.8, 1.4), (1.3, 0.7)])
+def test_cumulant_relaxes_the_covariance_and_cancels_higher_cumulants(tau, ob):
+    """Measured on the output populations: mass kept, momentum j + F, first
+    central moments F/2, the covariance's deviatoric part scaled by
+    1 - 1/tau and its trace relaxed at omega_bulk towards 1, third-order
+    central moments zero and fourth-order central moments equal to the
+    Gaussian products of the covariance (zero fourth cumulants)."""
+    rng = np.random.default_rng(15)
+    c, w, _ = O.stencil(27)
+    F = np.array([3e-5, -2e-5, 1e-5])
+    p = O.Params(q=27, collision=O.CUMULANT, tau=tau, omega_bulk=ob, force=tuple(F))
+    for _ in range(4):
+        d = _random_cell(27, rng, amp=2e-2)
+        f = d + w
+        rho = f.sum()
+        j = c.T @ f
+        u = (j + 0.5 * F) / rho
+        pre = _central(f, u, c)
+        post = O.collide_cell(p, d)[0] + w
+        k = _central(post, u, c)
+        assert abs(post.sum() - rho) < 1e-15
+        assert np.abs(c.T @ post - (j + F)).max() < 1e-15
+        assert np.abs(np.array([k(1, 0, 0), k(0, 1, 0), k(0, 0, 1)]) - F / 2).max() < 1e-15
+        S0 = np.array([[pre(*(np.eye(3, dtype=int)[a] + np.eye(3, dtype=int)[b])) for b in range(3)]
+                       for a in range(3)]) / rho
+        S1 = np.array([[k(*(np.eye(3, dtype=int)[a] + np.eye(3, dtype=int)[b])) for b in range(3)]
+                       for a in range(3)]) / rho
+        dev0, dev1 = S0 - np.trace(S0) / 3 * np.eye(3), S1 - np.trace(S1) / 3 * np.eye(3)
+        assert np.abs(dev1 - (1 - 1 / tau) * dev0).max() < 1e-14
+        assert abs(np.trace(S1) - (np.trace(S0) - ob * (np.trace(S0) - 1.0))) < 1e-14
+        assert max(abs(k(1, 1, 1)), abs(k(2, 1, 0)), abs(k(0, 1, 2))) < 1e-15
+        assert abs(k(2, 2, 0) / rho - (S1[0, 0] * S1[1, 1] + 2 * S1[0, 1] ** 2)) < 1e-14
+        assert abs(k(2, 1, 1) / rho - (S1[0, 0] * S1[1, 2] + 2 * S1[0, 1] * S1[0, 2])) < 1e-14
+
+
 @pytest.mark.parametrize("q", [19, 27])
 def test_trt_with_equal_times_is_srt(q):
     """Lambda = (tau - 1/2)^2 makes tau- = tau+, which is SRT."""
