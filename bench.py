@@ -245,7 +245,8 @@ def main():
                                           ("f32_smagorinsky", wlb.F32, 4, 1, 19, None),
                                           ("f32_mlp_closure", wlb.F32, 4, 2, 19, None),
                                           ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT),
-                                          ("f32_d3q27_kbc", wlb.F32, 4, 0, 27, wlb.KBC)):
+                                          ("f32_d3q27_kbc", wlb.F32, 4, 0, 27, wlb.KBC),
+                                          ("f32_d3q27_cumulant", wlb.F32, 4, 0, 27, wlb.CUMULANT)):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
                            q=q, coll=coll, check=True)
             sm = summarize(r, st, args.variant_steps, eb, q=q)

@@ -61,10 +61,13 @@ extern "C" {
 #define WLB_ERR_UNSUPPORTED (-5) /* combination not implemented */
 
 enum { WLB_D3Q19 = 19, WLB_D3Q27 = 27 };
-/* SRT, TRT, MRT (Eq. 3) and KBC: the MRT basis with the entropic choice of
- * the trace and higher-order rates per cell (Sec. 5.1.1, Boesch,
- * Chikatamarla, Karlin 2015; D3Q27 only; omega_bulk / omega_higher unused). */
-enum { WLB_SRT = 0, WLB_TRT = 1, WLB_MRT = 2, WLB_KBC = 3 };
+/* SRT, TRT, MRT (Eq. 3); KBC: the MRT basis with the entropic choice of the
+ * trace and higher-order rates per cell (Sec. 5.1.1, Boesch, Chikatamarla,
+ * Karlin 2015; D3Q27 only; omega_bulk / omega_higher unused); CUMULANT:
+ * second-order cumulants relaxed with 1/tau (deviatoric) and omega_bulk
+ * (trace), all higher cumulants with rate 1 (Sec. 5.1.1, Geier et al. 2015;
+ * D3Q27 only; omega_higher unused). */
+enum { WLB_SRT = 0, WLB_TRT = 1, WLB_MRT = 2, WLB_KBC = 3, WLB_CUMULANT = 4 };
 /* storage type of the deviations; collision runs in FP64 for WLB_F64 and in
  * FP32 otherwise; conversions round to nearest even, no denormal flush */
 enum { WLB_F64 = 0, WLB_F32 = 1, WLB_F16DEV = 2, WLB_BF16DEV = 3 };
@@ -138,12 +141,13 @@ int wlb_blocks_bind(wlb_blocks_t h, void *device_arena, size_t bytes, void *hip_
 
 /* Initialise the populations to the equilibrium of rho[N], u[3][N] (host,
  * FP64, global order) and the geometry from solid[N] (host, 1 = solid, may be
- * NULL for no solid cells).  collision = WLB_SRT/TRT/MRT/KBC.  Resets the step
+ * NULL for no solid cells).  collision = WLB_SRT/TRT/MRT/KBC/CUMULANT.  Resets the step
  * counter.  Runs the tile autotuner when p->autotune is set (the state is
  * re-initialised afterwards).  Synchronises the stream.
  * Errors: WLB_ERR_ARG (tau <= 1/2, bad pressure axis, MLP without weights),
- * WLB_ERR_STATE (not bound), WLB_ERR_UNSUPPORTED (MRT or KBC with the MLP
- * closure, KBC without D3Q27). */
+ * WLB_ERR_STATE (not bound), WLB_ERR_UNSUPPORTED (MRT, KBC or the cumulant
+ * collision with the MLP closure; KBC or the cumulant collision without
+ * D3Q27). */
 int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, const double *rho, const double *u,
                  const uint8_t *solid);
 

@@ -992,8 +992,9 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
 {
     if (!h || !p || !rho || !u) return fail(WLB_ERR_ARG, "null argument");
     if (!h->bound) return fail(WLB_ERR_STATE, "wlb_blocks_bind must come first");
-    if (collision < WLB_SRT || collision > WLB_KBC) return fail(WLB_ERR_ARG, "bad collision operator");
-    if (collision == WLB_KBC && h->q != WLB_D3Q27) return fail(WLB_ERR_UNSUPPORTED, "KBC runs with D3Q27");
+    if (collision < WLB_SRT || collision > WLB_CUMULANT) return fail(WLB_ERR_ARG, "bad collision operator");
+    if (collision >= WLB_KBC && h->q != WLB_D3Q27)
+        return fail(WLB_ERR_UNSUPPORTED, "KBC and the cumulant collision run with D3Q27");
     if (!(p->tau > 0.5)) return fail(WLB_ERR_ARG, "tau must exceed 1/2");
     if (collision == WLB_TRT && !(p->magic > 0.0)) return fail(WLB_ERR_ARG, "TRT needs magic > 0");
     if (p->pressure_axis < -1 || p->pressure_axis > 2) return fail(WLB_ERR_ARG, "bad pressure axis");

@@ -418,6 +418,140 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
     });
 }
 
+// Central moments to raw moments along one axis of the 3 x 3 x 3 moment
+// array (index a + 3 b + 9 c): with the shift u, r0 = k0, r1 = k1 + u k0,
+// r2 = k2 + 2 u k1 + u^2 k0.
+template <int AX, typename T>
+__device__ __forceinline__ void central_to_raw(T (&v)[27], T u)
+{
+    constexpr int s = AX == 0 ? 1 : (AX == 1 ? 3 : 9);
+    sfor<9>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        constexpr int a = l % 3, b = l / 3;
+        constexpr int base = AX == 0 ? (3 * a + 9 * b) : (AX == 1 ? (a + 9 * b) : (a + 3 * b));
+        const T k0 = v[base], k1 = v[base + s], k2 = v[base + 2 * s];
+        v[base + s] = k1 + u * k0;
+        v[base + 2 * s] = k2 + u * (T(2) * k1 + u * k0);
+    });
+}
+
+// Raw moment (a, b, c) of rho times the factorised three-velocity
+// distribution at u (per axis: moments 1, u, 1/3 + u^2) minus that of the
+// lattice weights (u = 0, rho = 1), written in small quantities only.
+template <int a, int b, int c, typename T>
+__device__ __forceinline__ T factorised_moment_dev(const T u[3], const T u2[3], T drho)
+{
+    const int e[3] = {a, b, c};
+    T P = T(1);
+    bool odd = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (e[k] == 1) {
+            P *= u[k];
+            odd = true;
+        } else if (e[k] == 2) {
+            P *= T(1) / T(3) + u2[k];
+        }
+    }
+    if (odd) return (T(1) + drho) * P;  // the weights' moment is zero
+    // prod over the axes with exponent 2 of (1/3 + u_k^2) minus (1/3)^n
+    T diff = T(0), lower = T(1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (e[k] == 2) {  // diff' = (1/3 + s) (prev product) - (1/3)^n = diff/3 + s * prev
+            diff = diff * (T(1) / T(3)) + u2[k] * lower;
+            lower *= T(1) / T(3) + u2[k];
+        }
+    }
+    return drho * P + diff;
+}
+
+// Cumulant collision (Sec. 5.1.1: cumulants relaxed instead of moments;
+// Geier et al. 2015) on D3Q27, every cumulant of order >= 3 relaxed at rate
+// 1 (to zero).  With u = (j + F/2)/rho the covariance S of the populations
+// about u (the second-order cumulants) has its deviatoric part relaxed at
+// omega and its trace at omega_bulk towards 1; afterwards the populations
+// have density rho, first-order central moments F/2 (sum c f* = j + F) and
+// the central moments of rho times a zero-mean Gaussian with covariance S*.
+// Computed as S^ = S - I/3 so that nothing of order one is formed: the
+// central moments split into a part in S^ and F (shifted to raw moments
+// axis by axis) and the factorised rest distribution at u, whose raw moments
+// minus the weights' moments have a closed form; the difference is the raw
+// moment array of the deviations, which the inverse transform turns into
+// populations.
+template <int Q, typename T>
+__device__ __forceinline__ void cumulant_collide(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omb)
+{
+    static_assert(Q == 27, "the cumulant collision runs on D3Q27");
+    constexpr int XX = 2, YY = 6, ZZ = 18, XY = 4, XZ = 10, YZ = 12;
+    T mn[27];
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        mn[tpos(i)] = d[i];
+    });
+    tmoments<0>(mn);
+    tmoments<1>(mn);
+    tmoments<2>(mn);
+    const T ir = recip(m.rho), r = m.rho;
+    const T *u = m.u;
+    const T d3 = m.drho * (T(1) / T(3));
+    // S^ = S - I/3 from the raw second moments of the deviations
+    T sxx = (mn[XX] - r * u[0] * u[0] + u[0] * F[0] - d3) * ir;
+    T syy = (mn[YY] - r * u[1] * u[1] + u[1] * F[1] - d3) * ir;
+    T szz = (mn[ZZ] - r * u[2] * u[2] + u[2] * F[2] - d3) * ir;
+    T sxy = (mn[XY] - r * u[0] * u[1] + T(0.5) * (u[0] * F[1] + u[1] * F[0])) * ir;
+    T sxz = (mn[XZ] - r * u[0] * u[2] + T(0.5) * (u[0] * F[2] + u[2] * F[0])) * ir;
+    T syz = (mn[YZ] - r * u[1] * u[2] + T(0.5) * (u[1] * F[2] + u[2] * F[1])) * ir;
+    {
+        const T kd = T(1) - om, kb = T(1) - omb;
+        const T A = kd * (sxx - syy), B = kd * (sxx - szz), Tr = kb * (sxx + syy + szz);
+        sxx = (A + B + Tr) * (T(1) / T(3));
+        syy = (Tr - T(2) * A + B) * (T(1) / T(3));
+        szz = (Tr + A - T(2) * B) * (T(1) / T(3));
+        sxy *= kd;
+        sxz *= kd;
+        syz *= kd;
+    }
+    const T t = T(1) / T(3);
+    const T Sxx = sxx + t, Syy = syy + t, Szz = szz + t;
+    // central moments minus those of rho x (Gaussian with covariance I/3)
+    T k[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) k[q] = T(0);
+    k[1] = T(0.5) * F[0];
+    k[3] = T(0.5) * F[1];
+    k[9] = T(0.5) * F[2];
+    k[XX] = r * sxx;
+    k[YY] = r * syy;
+    k[ZZ] = r * szz;
+    k[XY] = r * sxy;
+    k[XZ] = r * sxz;
+    k[YZ] = r * syz;
+    k[8] = r * (sxx * syy + t * (sxx + syy) + T(2) * sxy * sxy);    // (2,2,0)
+    k[20] = r * (sxx * szz + t * (sxx + szz) + T(2) * sxz * sxz);   // (2,0,2)
+    k[24] = r * (syy * szz + t * (syy + szz) + T(2) * syz * syz);   // (0,2,2)
+    k[14] = r * (Sxx * syz + T(2) * sxy * sxz);                     // (2,1,1)
+    k[16] = r * (Syy * sxz + T(2) * sxy * syz);                     // (1,2,1)
+    k[22] = r * (Szz * sxy + T(2) * sxz * syz);                     // (1,1,2)
+    k[26] = r * (sxx * syy * szz + t * (sxx * syy + sxx * szz + syy * szz) + t * t * (sxx + syy + szz) +
+                 T(2) * (Sxx * syz * syz + Syy * sxz * sxz + Szz * sxy * sxy) + T(8) * sxy * sxz * syz);  // (2,2,2)
+    central_to_raw<0>(k, u[0]);
+    central_to_raw<1>(k, u[1]);
+    central_to_raw<2>(k, u[2]);
+    const T u2[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
+    sfor<27>([&](auto K) {
+        constexpr int q = decltype(K)::value;
+        k[q] += factorised_moment_dev<q % 3, (q / 3) % 3, q / 9, T>(u, u2, m.drho);
+    });
+    tvalues<2>(k);
+    tvalues<1>(k);
+    tvalues<0>(k);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        d[i] = k[tpos(i)];
+    });
+}
+
 template <typename T>
 struct CollParams {
     T om, omm, magic, omb, omh, F[3], tau0, smag_k;
@@ -533,7 +667,14 @@ __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p
 {
     const Macro<Q, T> m = moments_of<Q, T>(d, p.F);
     T om = p.om, omm = p.omm;
-    if constexpr (COLL == 2 || COLL == 3) {
+    if constexpr (COLL == 4) {
+        if (p.closure == 1) {
+            T P[6];
+            pi_pairs<Q, T>(d, m, P);
+            om = recip(tau_smagorinsky<T>(P, m.rho, p.tau0, p.smag_k));
+        }
+        cumulant_collide<Q, T>(d, m, p.F, om, p.omb);
+    } else if constexpr (COLL == 2 || COLL == 3) {
         mrt_collide<Q, T, COLL == 3>(d, m, p.F, om, p.omb, p.omh, p.closure, p.tau0, p.smag_k);
     } else {
         if (p.closure == 1) {
@@ -1510,6 +1651,9 @@ static hipError_t sweep_c(int coll, bool odd, const SweepArgs &a, int grid, hipS
     case 2: return sweep_q<Q, 2>(odd, a, grid, st);
     case 3:
         if constexpr (Q == 27) return sweep_q<Q, 3>(odd, a, grid, st);
+        return hipErrorNotSupported;
+    case 4:
+        if constexpr (Q == 27) return sweep_q<Q, 4>(odd, a, grid, st);
         return hipErrorNotSupported;
     default: return hipErrorInvalidValue;
     }

@@ -182,12 +182,14 @@ def turbulence_precision(wlb, n=384, steps=1000, every=100, seed=0, storages=Non
 def entropic_stability(wlb, n=384, steps=1000, every=100, seed=0, tau=0.5005, umax=0.5):
     """The decaying-turbulence start of the precision ladder (n^3, u_rms 0.05,
     tau 0.5005: far from resolved) advanced in FP32 with D3Q19 TRT, D3Q27 MRT
-    (all non-hydrodynamic rates 1) and D3Q27 KBC, whose per-cell higher-order
-    rate is the entropic stabiliser.  Every `every` steps: kinetic energy,
+    (all non-hydrodynamic rates 1), D3Q27 KBC, whose per-cell higher-order
+    rate is the entropic stabiliser, and the D3Q27 cumulant collision (bulk
+    rate 1, higher cumulants to zero).  Every `every` steps: kinetic energy,
     max |u|, mass drift; the step at which a run first leaves the healthy
     range (non-finite, max |u| >= umax) is recorded."""
     rho, u = inputs.turbulence_bandlimited(n, seed)
-    cases = [("d3q19_trt", 19, wlb.TRT), ("d3q27_mrt", 27, wlb.MRT), ("d3q27_kbc", 27, wlb.KBC)]
+    cases = [("d3q19_trt", 19, wlb.TRT), ("d3q27_mrt", 27, wlb.MRT), ("d3q27_kbc", 27, wlb.KBC),
+             ("d3q27_cumulant", 27, wlb.CUMULANT)]
     out = {}
     for name, q, coll in cases:
         p = wlb.make_params(tau=tau, magic=3.0 / 16.0, omega_bulk=1.0, omega_higher=1.0, autotune=1)

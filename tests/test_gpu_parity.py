@@ -56,7 +56,7 @@ def test_taylor_green_32_fp64_100_steps():
     assert abs(tot[4] / e0 - exact) < 0.02 * exact
 
 
-@pytest.mark.parametrize("q,coll", [(19, 0), (19, 1), (19, 2), (27, 0), (27, 1), (27, 2), (27, 3)])
+@pytest.mark.parametrize("q,coll", [(19, 0), (19, 1), (19, 2), (27, 0), (27, 1), (27, 2), (27, 3), (27, 4)])
 @pytest.mark.parametrize("steps", [6, 7])
 def test_random_state_periodic_fp64(q, coll, steps):
     """Ragged 20x18x17 periodic box, random state, body force, every operator."""
@@ -98,7 +98,7 @@ def _porous_case(q, coll, storage, steps, seed=1, **kw):
     return gpu, orc, solid, dom
 
 
-@pytest.mark.parametrize("q,coll", [(27, 2), (19, 0), (19, 1), (19, 2), (27, 3)])
+@pytest.mark.parametrize("q,coll", [(27, 2), (19, 0), (19, 1), (19, 2), (27, 3), (27, 4)])
 @pytest.mark.parametrize("steps", [10, 11])
 def test_porous_uneven_blocks_pressure_fp64(q, coll, steps):
     """Uneven rectilinear blocks (3 x 2 x 2), spheres, density faces on x,
@@ -142,13 +142,27 @@ def test_kbc_fp32_storage_vs_fp64_oracle():
     _compare("kbc fp32", wlb.F32, 27, gpu, orc, None, np.prod(dom))
 
 
-def test_kbc_needs_d3q27():
+def test_cumulant_fp32_storage_vs_fp64_oracle():
+    """The cumulant collision with FP32 populations against the FP64 oracle
+    on a random periodic state with a body force and a bulk rate."""
+    say("case cumulant fp32")
+    dom = (20, 12, 10)
+    rho, u = inputs.random_state(dom, seed=23, umag=0.05)
+    F = (1e-5, -2e-6, 3e-6)
+    p = wlb.make_params(tau=0.53, omega_bulk=1.3, force=F)
+    gpu = gpu_run(wlb.single_block(dom), dom, (1, 1, 1), 27, wlb.F32, wlb.CUMULANT, p, rho, u, steps=9)
+    orc = oracle_run(oracle_params(27, wlb.CUMULANT, 0.53, 0, (1, 1, 1), F, omega_bulk=1.3), dom, rho, u, None, 9)
+    _compare("cumulant fp32", wlb.F32, 27, gpu, orc, None, np.prod(dom))
+
+
+@pytest.mark.parametrize("coll", [3, 4])
+def test_kbc_and_cumulant_need_d3q27(coll):
     dom = (8, 6, 4)
     rho, u = inputs.uniform_state(dom)
     B = wlb.Blocks(wlb.single_block(dom), dom, (1, 1, 1), stencil=19, storage=wlb.F64)
     try:
         with pytest.raises(wlb.WlbError) as e:
-            B.init(wlb.KBC, wlb.make_params(tau=0.8), rho, u)
+            B.init(coll, wlb.make_params(tau=0.8), rho, u)
         assert e.value.code == wlb.WLB_ERR_UNSUPPORTED
     finally:
         B.close()
