@@ -29,8 +29,9 @@
  * sum w_i = 1 and sum w_i c_i = 0).  Solid cells carry no state (d = 0).
  *
  * Readings where the paper gives a name but not a formula:
- *   velocity sets, weights, c_s^2 = 1/3: textbook D3Q19/D3Q27 (Krueger 2017);
- *   equilibrium: second-order polynomial f_eq (same for D3Q19 and D3Q27);
+ *   velocity sets, weights, c_s^2 = 1/3: textbook D2Q9/D3Q15/D3Q19/D3Q27
+ *        (Krueger 2017); MRT, KBC and cumulant only on D3Q19/D3Q27;
+ *   equilibrium: second-order polynomial f_eq (same for every set);
  *   force: Guo 2002 term, u = (sum c f + F/2)/rho;
  *   TRT: Lambda = (tau+ - 1/2)(tau- - 1/2) (Ginzburg 2008);
  *   MRT: raw-moment monomial basis c_x^a c_y^b c_z^c, second-order
@@ -57,7 +58,7 @@
 /* Parameters                                                               */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int q;                /* 19 or 27 */
+    int q;                /* 9, 15, 19 or 27 */
     int collision;        /* 0 = SRT, 1 = TRT, 2 = MRT, 3 = KBC (MRT basis, entropic higher rates),
                              4 = cumulant (D3Q27) */
     double tau;           /* shear relaxation time tau_0 */
@@ -75,7 +76,8 @@ typedef struct {
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
-/* Velocity sets (textbook, Krueger 2017; the paper names D3Q19 and D3Q27)  */
+/* Velocity sets (textbook, Krueger 2017; the paper names D2Q9, D3Q15,      */
+/* D3Q19 and D3Q27 in Sec. 5.1.1)                                            */
 /* ------------------------------------------------------------------------ */
 /* Order: rest; the six axis directions as +/- pairs; the twelve edge
  * directions as +/- pairs; the eight corners as +/- pairs.  Each odd index
@@ -90,6 +92,21 @@ static const int C27[OQ][3] = {
     {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1},
 };
 
+/* D3Q15: rest, the six axis directions, the eight corners (same pairs and
+ * order as in C27).  D2Q9: rest, (+-1,0), (0,+-1), then (1,1), (-1,-1),
+ * (1,-1), (-1,1); the third component is 0, so a 3D grid holds independent
+ * 2D planes. */
+static const int C15[15][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1},
+};
+static const int C9[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+};
+
 typedef struct {
     int q;
     int c[OQ][3];
@@ -99,15 +116,22 @@ typedef struct {
 
 static int make_lattice(int q, lattice *L)
 {
-    if (q != 19 && q != 27) return -1;
+    if (q != 9 && q != 15 && q != 19 && q != 27) return -1;
     L->q = q;
     for (int i = 0; i < q; ++i) {
+        const int *ci = q == 9 ? C9[i] : (q == 15 ? C15[i] : C27[i]);
         int n2 = 0;
         for (int a = 0; a < 3; ++a) {
-            L->c[i][a] = C27[i][a];
-            n2 += C27[i][a] * C27[i][a];
+            L->c[i][a] = ci[a];
+            n2 += ci[a] * ci[a];
         }
-        if (q == 27) {
+        if (q == 9) {
+            /* D2Q9: 4/9, 1/9, 1/36 for |c|^2 = 0, 1, 2 */
+            L->w[i] = n2 == 0 ? 4.0 / 9.0 : (n2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+        } else if (q == 15) {
+            /* D3Q15: 2/9, 1/9, 1/72 for |c|^2 = 0, 1, 3 */
+            L->w[i] = n2 == 0 ? 2.0 / 9.0 : (n2 == 1 ? 1.0 / 9.0 : 1.0 / 72.0);
+        } else if (q == 27) {
             /* D3Q27 weights: product of the D1Q3 weights 2/3 (rest) and 1/6,
              * i.e. 2^(3 - 2 |c|^2) / 27 = 8/27, 2/27, 1/54, 1/216. */
             L->w[i] = ldexp(1.0, 3 - 2 * n2) / 27.0;

@@ -18,24 +18,28 @@ from paper_1909_13772_amd import inputs
 # --------------------------------------------------------------------------
 # Velocity sets: isotropy conditions fix the weights (textbook D3Q19/D3Q27)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_lattice_isotropy(q):
     c, w, opp = O.stencil(q)
     assert c.shape == (q, 3)
+    if q == 9:  # D2Q9: a plane set; the isotropy conditions hold in x and y
+        assert np.all(c[:, 2] == 0)
+        c = c[:, :2]
     assert len({tuple(v) for v in c}) == q
-    assert tuple(c[0]) == (0, 0, 0)
+    assert not c[0].any()
     for i in range(q):
         assert np.all(c[opp[i]] == -c[i])
         if i % 2 == 1:
             assert opp[i] == i + 1
     assert abs(w.sum() - 1.0) < 1e-15
     assert np.abs(w @ c).max() < 1e-17
+    dim = c.shape[1]
     second = np.einsum("i,ia,ib->ab", w, c, c)
-    assert np.allclose(second, np.eye(3) / 3.0, atol=1e-15, rtol=0)
+    assert np.allclose(second, np.eye(dim) / 3.0, atol=1e-15, rtol=0)
     third = np.einsum("i,ia,ib,ic->abc", w, c, c, c)
     assert np.abs(third).max() < 1e-17
     fourth = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
-    d = np.eye(3)
+    d = np.eye(dim)
     iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
            + np.einsum("ad,bc->abcd", d, d)) / 9.0
     assert np.allclose(fourth, iso, atol=1e-15, rtol=0)
@@ -50,38 +54,80 @@ def test_lattice_order_and_weights_textbook():
     assert np.all(c27[:19] == c)
     assert w27[0] == 8 / 27 and w27[1] == 2 / 27 and w27[7] == 1 / 54 and w27[19] == 1 / 216
     assert np.all(np.abs(c27[19:]).sum(1) == 3)
+    # D3Q15: rest and faces as in D3Q19, then the corners in D3Q27's order
+    c15, w15, _ = O.stencil(15)
+    assert np.all(c15[:7] == c[:7]) and np.all(c15[7:] == c27[19:])
+    assert w15[0] == 2 / 9 and w15[1] == 1 / 9 and w15[7] == 1 / 72
+    # D2Q9: rest, the four x/y axis directions, then the xy diagonals of D3Q19
+    c9, w9, _ = O.stencil(9)
+    assert np.all(c9[:5] == c[:5]) and np.all(c9[5:] == c[7:11])
+    assert w9[0] == 4 / 9 and w9[1] == 1 / 9 and w9[5] == 1 / 36
 
 
 # --------------------------------------------------------------------------
 # Equilibrium and forcing moments
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("q", [19, 27])
+def _plane(q, v):
+    """D2Q9 carries no z component: zero it (its moments hold in x and y)."""
+    v = np.array(v, dtype=np.float64)
+    if q == 9:
+        v[2] = 0.0
+    return v
+
+
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_equilibrium_moments(q):
     c, w, _ = O.stencil(q)
     rng = np.random.default_rng(1)
+    dim = 2 if q == 9 else 3
     for _ in range(5):
         rho = 1.0 + rng.uniform(-0.05, 0.05)
-        u = rng.uniform(-0.1, 0.1, 3)
+        u = _plane(q, rng.uniform(-0.1, 0.1, 3))
         de = O.equilibrium(q, rho, u)
         f = w + de
         assert abs(de.sum() - (rho - 1.0)) < 1e-16
         assert np.allclose(c.T @ de, rho * u, atol=1e-16, rtol=0)
-        P = np.einsum("i,ia,ib->ab", f, c, c)
-        assert np.allclose(P, rho * (np.eye(3) / 3.0 + np.outer(u, u)), atol=2e-16, rtol=0)
+        P = np.einsum("i,ia,ib->ab", f, c, c)[:dim, :dim]
+        assert np.allclose(P, rho * (np.eye(dim) / 3.0 + np.outer(u, u)[:dim, :dim]), atol=2e-16, rtol=0)
 
 
-@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_guo_moments(q):
     c, w, _ = O.stencil(q)
     rng = np.random.default_rng(2)
-    u = rng.uniform(-0.1, 0.1, 3)
-    F = rng.uniform(-1e-3, 1e-3, 3)
+    u = _plane(q, rng.uniform(-0.1, 0.1, 3))
+    F = _plane(q, rng.uniform(-1e-3, 1e-3, 3))
     Fi = O.guo(q, u, F)
     scale = np.abs(F).max()
     assert abs(Fi.sum()) < 1e-15 * scale
     assert np.allclose(c.T @ Fi, F, atol=1e-15 * scale, rtol=0)
     S = np.einsum("i,ia,ib->ab", Fi, c, c)
     assert np.allclose(S, np.outer(u, F) + np.outer(F, u), atol=1e-15 * scale, rtol=0)
+
+
+@pytest.mark.parametrize("q", [9, 15])
+@pytest.mark.parametrize("coll", [O.SRT, O.TRT])
+def test_small_sets_conserve_mass_and_momentum(q, coll):
+    c, w, _ = O.stencil(q)
+    rng = np.random.default_rng(11 + q + coll)
+    F = tuple(_plane(q, rng.uniform(-1e-4, 1e-4, 3)))
+    p = O.Params(q=q, collision=coll, tau=0.7, magic=0.1, force=F)
+    for _ in range(5):
+        de = O.equilibrium(q, 1.0 + rng.uniform(-0.01, 0.01), _plane(q, rng.uniform(-0.05, 0.05, 3)))
+        d = de + 1e-3 * rng.uniform(-1, 1, q) * w
+        dp, rho, u, _ = O.collide_cell(p, d)
+        eps = 1e-14 * np.abs(d).max()
+        assert abs(dp.sum() - d.sum()) < eps
+        assert np.allclose(c.T @ dp, c.T @ d + np.array(F), atol=eps, rtol=0)
+
+
+@pytest.mark.parametrize("q", [9, 15])
+@pytest.mark.parametrize("coll", [O.MRT, O.KBC, O.CUMULANT])
+def test_small_sets_refuse_moment_space_collisions(q, coll):
+    """The moment bases of MRT, KBC and the cumulant operator are built for
+    D3Q19 / D3Q27 only."""
+    with pytest.raises(Exception):
+        O.collide_cell(O.Params(q=q, collision=coll, tau=0.7), np.zeros(q))
 
 
 # --------------------------------------------------------------------------
@@ -329,7 +375,7 @@ def test_uniform_flow_is_fixed_point(coll):
     assert np.abs(O.run(p, shape, d, 50) - d).max() <= 16 * ulp
 
 
-@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_periodic_streaming_is_a_roll(q):
     c, w, _ = O.stencil(q)
     shape = (7, 5, 4)
@@ -344,7 +390,7 @@ def test_periodic_streaming_is_a_roll(q):
         assert np.array_equal(out[i].reshape(nz, ny, nx), exp)
 
 
-@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_wall_streaming_bounces_back(q):
     """Walls in y: populations that would come from y = -1 or y = ny are the
     cell's own opposite post-collision values; interior links are a roll."""
@@ -366,7 +412,7 @@ def test_wall_streaming_bounces_back(q):
         assert np.array_equal(out[i].reshape(nz, ny, nx), exp), i
 
 
-@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_streaming_with_walls_and_solids_is_a_permutation(q):
     shape = (10, 9, 8)
     nx, ny, nz = shape
@@ -474,7 +520,7 @@ def test_momentum_exchange_at_rest_is_the_static_pressure(q, coll):
     assert out[6] == area * links and out[7] == area * links
 
 
-@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_momentum_exchange_counts_every_link_into_a_lone_solid_cell(q):
     """One solid cell in a periodic box at rest: every neighbour sends exactly
     one link into it (q - 1 links) and the pressure forces cancel."""
@@ -521,15 +567,16 @@ def _energy(q, shape, d):
     return tot[4]
 
 
-def test_taylor_green_decay_32():
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
+def test_taylor_green_decay_32(q):
     """z-invariant TGV, tau = 0.8 (nu = 0.1), k = 2 pi / 32: E(t) = E(0) exp(-4 nu k^2 t)."""
     n, steps, tau = 32, 100, 0.8
     rho, u = inputs.taylor_green(n, 0.01, nz=2)
     shape = (n, n, 2)
-    d0 = O.init(19, shape, rho, u)
-    p = O.Params(q=19, collision=O.SRT, tau=tau)
+    d0 = O.init(q, shape, rho, u)
+    p = O.Params(q=q, collision=O.SRT, tau=tau)
     d1 = O.run(p, shape, d0, steps)
-    ratio = _energy(19, shape, d1) / _energy(19, shape, d0)
+    ratio = _energy(q, shape, d1) / _energy(q, shape, d0)
     k = 2 * math.pi / n
     nu = (tau - 0.5) / 3
     exact = math.exp(-4 * nu * k * k * steps)
@@ -557,15 +604,16 @@ def test_taylor_green_second_order_convergence():
     assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, errs
 
 
-def test_trt_magic_poiseuille_is_exact():
+@pytest.mark.parametrize("q", [9, 15, 19])
+def test_trt_magic_poiseuille_is_exact(q):
     """TRT with Lambda = 3/16, half-way bounce-back and Guo force reproduces
     the parabola u(s) = g s (H - s) / (2 nu), s = y + 1/2, exactly."""
     H, tau, g = 16, 0.8, 1e-5
     shape = (1, H, 1)
     rho, u = inputs.uniform_state(shape)
-    p = O.Params(q=19, collision=O.TRT, tau=tau, magic=3 / 16, force=(g, 0, 0), periodic=(1, 0, 1))
-    d = O.run(p, shape, O.init(19, shape, rho, u), 12000)
-    r, uu, _ = O.moments(19, p.force, shape, d)
+    p = O.Params(q=q, collision=O.TRT, tau=tau, magic=3 / 16, force=(g, 0, 0), periodic=(1, 0, 1))
+    d = O.run(p, shape, O.init(q, shape, rho, u), 12000)
+    r, uu, _ = O.moments(q, p.force, shape, d)
     nu = (tau - 0.5) / 3
     s = np.arange(H) + 0.5
     # body force density g with rho ~ 1: exact profile uses rho * u = g s (H - s) / (2 nu rho)
