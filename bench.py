@@ -4,8 +4,10 @@ Workload (headline): D3Q19 TRT (Lambda = 3/16), single block 256^3, FP64
 deviation storage, channel with half-way bounce-back walls in y, periodic
 x/z, Guo body force f_x = 1e-6, tau = 0.8, starting from rest; one step is
 one AA sweep over all cells plus the ghost-layer exchange.  The same
-configuration is also timed with FP32, FP16 and BF16 deviation storage and
-with the Smagorinsky closure (the "variants").
+configuration is also timed with FP32, FP16 and BF16 deviation storage,
+with the Smagorinsky and learned closures, with D3Q27 MRT / KBC / cumulant
+collisions and with the D3Q15 and D2Q9 velocity sets (D2Q9: 256 independent
+xy planes) -- the "variants".
 
 Prints ONE JSON line with MLUPS, the HBM roofline fraction of the sweep
 kernel (algorithmic bytes / measured kernel time, HIP events on the
@@ -246,7 +248,9 @@ def main():
                                           ("f32_mlp_closure", wlb.F32, 4, 2, 19, None),
                                           ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT),
                                           ("f32_d3q27_kbc", wlb.F32, 4, 0, 27, wlb.KBC),
-                                          ("f32_d3q27_cumulant", wlb.F32, 4, 0, 27, wlb.CUMULANT)):
+                                          ("f32_d3q27_cumulant", wlb.F32, 4, 0, 27, wlb.CUMULANT),
+                                          ("f32_d3q15", wlb.F32, 4, 0, 15, None),
+                                          ("f32_d2q9_planes", wlb.F32, 4, 0, 9, None)):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
                            q=q, coll=coll, check=True)
             sm = summarize(r, st, args.variant_steps, eb, q=q)

@@ -19,14 +19,19 @@
  *     from the device only at set-up and after many steps (Sec. 4.3).
  *
  * Conventions
- *   Velocity sets: D3Q19 / D3Q27.  Direction 0 is rest; 1..6 are
- *     (+-1,0,0), (0,+-1,0), (0,0,+-1); 7..18 the edges (1,1,0), (-1,-1,0),
- *     (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1),
- *     (0,-1,-1), (0,1,-1), (0,-1,1); 19..26 (D3Q27 only) the corners
- *     (1,1,1), (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1), (-1,1,-1),
- *     (-1,1,1), (1,-1,-1).  The opposite of an odd direction i is i+1.
- *     Weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216;
- *     c_s^2 = 1/3.
+ *   Velocity sets (Sec. 5.1.1 names all four): D2Q9, D3Q15, D3Q19, D3Q27.
+ *     D3Q27 population order: 0 rest; 1..6 (+-1,0,0), (0,+-1,0), (0,0,+-1);
+ *     7..18 the edges (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1),
+ *     (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1),
+ *     (0,-1,1); 19..26 the corners (1,1,1), (-1,-1,-1), (1,1,-1),
+ *     (-1,-1,1), (1,-1,1), (-1,1,-1), (-1,1,1), (1,-1,-1).  D3Q19 is
+ *     populations 0..18 of that order; D3Q15 is 0..6 followed by the eight
+ *     corners 19..26; D2Q9 is 0..4 followed by the xy edges 7..10 (every
+ *     z component 0: each z plane is an independent 2D lattice).  In every
+ *     set the opposite of an odd population i is i+1.  Weights by |c|^2:
+ *     D2Q9 4/9, 1/9, 1/36; D3Q15 2/9, 1/9, 1/72; D3Q19 1/3, 1/18, 1/36;
+ *     D3Q27 8/27, 2/27, 1/54, 1/216; c_s^2 = 1/3.  MRT needs D3Q19 or
+ *     D3Q27, KBC and the cumulant collision D3Q27.
  *   State: populations are stored as deviations d_i = f_i - w_i.
  *   Global host arrays cover the bounding box `domain` with x fastest,
  *     then y, then z: scalar fields [N], vector fields [3][N] (component
@@ -60,7 +65,7 @@ extern "C" {
 #define WLB_ERR_DIVERGED (-4)    /* health check: non-finite mass or max|u| above the limit */
 #define WLB_ERR_UNSUPPORTED (-5) /* combination not implemented */
 
-enum { WLB_D3Q19 = 19, WLB_D3Q27 = 27 };
+enum { WLB_D2Q9 = 9, WLB_D3Q15 = 15, WLB_D3Q19 = 19, WLB_D3Q27 = 27 };
 /* SRT, TRT, MRT (Eq. 3); KBC: the MRT basis with the entropic choice of the
  * trace and higher-order rates per cell (Sec. 5.1.1, Boesch, Chikatamarla,
  * Karlin 2015; D3Q27 only; omega_bulk / omega_higher unused); CUMULANT:
@@ -124,7 +129,7 @@ typedef struct {
 } wlb_lbm_params;
 
 /* Create a block set.  d[n] describes the blocks, domain[3] the bounding box,
- * periodic[3] which axes wrap.  stencil = WLB_D3Q19/WLB_D3Q27, storage =
+ * periodic[3] which axes wrap.  stencil = WLB_D2Q9/D3Q15/D3Q19/D3Q27, storage =
  * WLB_F64/F32/F16DEV/BF16DEV.  Builds the 26-neighbour table (periodic links
  * included), the tile list and the exchange work list, and returns in
  * *arena_bytes the size of the device arena to bind.
@@ -146,8 +151,8 @@ int wlb_blocks_bind(wlb_blocks_t h, void *device_arena, size_t bytes, void *hip_
  * re-initialised afterwards).  Synchronises the stream.
  * Errors: WLB_ERR_ARG (tau <= 1/2, bad pressure axis, MLP without weights),
  * WLB_ERR_STATE (not bound), WLB_ERR_UNSUPPORTED (MRT, KBC or the cumulant
- * collision with the MLP closure; KBC or the cumulant collision without
- * D3Q27). */
+ * collision with the MLP closure; MRT without D3Q19 / D3Q27; KBC or the
+ * cumulant collision without D3Q27; the MLP closure without D3Q19). */
 int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, const double *rho, const double *u,
                  const uint8_t *solid);
 

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kWG) void masks_kernel(const SweepArgs a, const uin
             int n[3];
             bool inside = true;
             for (int ax = 0; ax < 3; ++ax) {
-                n[ax] = g[ax] + cc(i, ax);
+                n[ax] = g[ax] + ccq(q, i, ax);
                 if (n[ax] < 0 || n[ax] >= a.dom[ax]) {
                     if ((a.periodic >> ax) & 1)
                         n[ax] = (n[ax] + a.dom[ax]) % a.dom[ax];

@@ -220,7 +220,8 @@ void update_lds_stride(wlb_blocks *h)
         ring = ring && t.ex == h->blocks[t.b].n[0] && h->dev[t.b].wrapx != 0;
     }
     h->args.lds_ring = ring ? 1 : 0;
-    const int nsh = h->q == 19 ? 10 : 18;
+    int nsh = 0;  // populations with c_x != 0 (the staged ones)
+    for (int i = 0; i < h->q; ++i) nsh += ccq(h->q, i, 0) != 0;
     const size_t bytes = (((size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
     h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->list_mode) ? stride : 0;
     h->graph_valid = false;
@@ -695,7 +696,8 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
                       int32_t stencil, int32_t storage, size_t *arena_bytes, wlb_blocks_t *out)
 {
     if (!d || n <= 0 || !domain || !periodic || !arena_bytes || !out) return fail(WLB_ERR_ARG, "null argument");
-    if (stencil != WLB_D3Q19 && stencil != WLB_D3Q27) return fail(WLB_ERR_ARG, "stencil must be 19 or 27");
+    if (stencil != WLB_D2Q9 && stencil != WLB_D3Q15 && stencil != WLB_D3Q19 && stencil != WLB_D3Q27)
+        return fail(WLB_ERR_ARG, "stencil must be 9, 15, 19 or 27");
     if (storage < WLB_F64 || storage > WLB_BF16DEV) return fail(WLB_ERR_ARG, "bad storage type");
     for (int a = 0; a < 3; ++a)
         if (domain[a] <= 0 || domain[a] > 32767) return fail(WLB_ERR_ARG, "domain extent out of range");
@@ -868,7 +870,7 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
             for (int j = 1; j < stencil; ++j) {
                 bool in = true;
                 for (int a = 0; a < 3; ++a)
-                    if (o[a] != 0 && cc(j, a) != o[a]) in = false;
+                    if (o[a] != 0 && ccq(stencil, j, a) != o[a]) in = false;
                 if (!in) continue;
                 // Cells of the ghost region on side o for which population j
                 // is used: the cell g - c_j that reads it (after the even
@@ -886,13 +888,13 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
                     } else if (a == 0) {
                         // the reader / writer g - c_j may sit across an x face
                         // with a neighbour; only a face without one limits the range
-                        const int lo = (cc(j, 0) > 0 && !xlo) ? 1 : 0;
-                        const int hi = (cc(j, 0) < 0 && !xhi) ? A.n[0] - 1 : A.n[0];
+                        const int lo = (ccq(stencil, j, 0) > 0 && !xlo) ? 1 : 0;
+                        const int hi = (ccq(stencil, j, 0) < 0 && !xhi) ? A.n[0] - 1 : A.n[0];
                         ext[a] = hi - lo;
                         ghost0[a] = lo;
                         inner0[a] = lo;
                     } else {
-                        const int lo = std::max(0, cc(j, a)), hi = std::min(A.n[a], A.n[a] + cc(j, a));
+                        const int lo = std::max(0, ccq(stencil, j, a)), hi = std::min(A.n[a], A.n[a] + ccq(stencil, j, a));
                         ext[a] = hi - lo;
                         ghost0[a] = lo;
                         inner0[a] = lo;
@@ -995,6 +997,8 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
     if (collision < WLB_SRT || collision > WLB_CUMULANT) return fail(WLB_ERR_ARG, "bad collision operator");
     if (collision >= WLB_KBC && h->q != WLB_D3Q27)
         return fail(WLB_ERR_UNSUPPORTED, "KBC and the cumulant collision run with D3Q27");
+    if (collision == WLB_MRT && h->q != WLB_D3Q19 && h->q != WLB_D3Q27)
+        return fail(WLB_ERR_UNSUPPORTED, "MRT runs with D3Q19 and D3Q27");
     if (!(p->tau > 0.5)) return fail(WLB_ERR_ARG, "tau must exceed 1/2");
     if (collision == WLB_TRT && !(p->magic > 0.0)) return fail(WLB_ERR_ARG, "TRT needs magic > 0");
     if (p->pressure_axis < -1 || p->pressure_axis > 2) return fail(WLB_ERR_ARG, "bad pressure axis");

@@ -136,12 +136,12 @@ __device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         drho += d[i];
-        if constexpr (cx(i) == 1) jx += d[i];
-        if constexpr (cx(i) == -1) jx -= d[i];
-        if constexpr (cy(i) == 1) jy += d[i];
-        if constexpr (cy(i) == -1) jy -= d[i];
-        if constexpr (cz(i) == 1) jz += d[i];
-        if constexpr (cz(i) == -1) jz -= d[i];
+        if constexpr (cx<Q>(i) == 1) jx += d[i];
+        if constexpr (cx<Q>(i) == -1) jx -= d[i];
+        if constexpr (cy<Q>(i) == 1) jy += d[i];
+        if constexpr (cy<Q>(i) == -1) jy -= d[i];
+        if constexpr (cz<Q>(i) == 1) jz += d[i];
+        if constexpr (cz<Q>(i) == -1) jz -= d[i];
     });
     Macro<Q, T> m;
     m.drho = drho;
@@ -154,16 +154,16 @@ __device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
     return m;
 }
 
-template <int i, typename T>
+template <int Q, int i, typename T>
 __device__ __forceinline__ T cdot(const T v[3])
 {
     T r = T(0);
-    if constexpr (cx(i) == 1) r += v[0];
-    if constexpr (cx(i) == -1) r -= v[0];
-    if constexpr (cy(i) == 1) r += v[1];
-    if constexpr (cy(i) == -1) r -= v[1];
-    if constexpr (cz(i) == 1) r += v[2];
-    if constexpr (cz(i) == -1) r -= v[2];
+    if constexpr (cx<Q>(i) == 1) r += v[0];
+    if constexpr (cx<Q>(i) == -1) r -= v[0];
+    if constexpr (cy<Q>(i) == 1) r += v[1];
+    if constexpr (cy<Q>(i) == -1) r -= v[1];
+    if constexpr (cz<Q>(i) == 1) r += v[2];
+    if constexpr (cz<Q>(i) == -1) r -= v[2];
     return r;
 }
 
@@ -208,7 +208,8 @@ __device__ __forceinline__ void tvalues(T (&v)[27])
         v[base + 2 * s] = T(0.5) * (m2 + m1);
     });
 }
-__host__ __device__ constexpr int tpos(int i) { return 9 * (cz(i) + 1) + 3 * (cy(i) + 1) + (cx(i) + 1); }
+template <int Q>
+__host__ __device__ constexpr int tpos(int i) { return 9 * (cz<Q>(i) + 1) + 3 * (cy<Q>(i) + 1) + (cx<Q>(i) + 1); }
 
 // Lattice moment numerator sum_i wnum_i c_x^a c_y^b c_z^c (divide by wden):
 // compile-time constants of the stencil.
@@ -218,9 +219,9 @@ __host__ __device__ constexpr int lmom_num(int a, int b, int c)
     int s = 0;
     for (int i = 0; i < Q; ++i) {
         int t = wnum<Q>(i);
-        for (int k = 0; k < a; ++k) t *= cx(i);
-        for (int k = 0; k < b; ++k) t *= cy(i);
-        for (int k = 0; k < c; ++k) t *= cz(i);
+        for (int k = 0; k < a; ++k) t *= cx<Q>(i);
+        for (int k = 0; k < b; ++k) t *= cy<Q>(i);
+        for (int k = 0; k < c; ++k) t *= cz<Q>(i);
         s += t;
     }
     return s;
@@ -325,7 +326,7 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
     for (int k = 0; k < 27; ++k) mn[k] = T(0);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        mn[tpos(i)] = d[i];
+        mn[tpos<Q>(i)] = d[i];
     });
     tmoments<0>(mn);
     tmoments<1>(mn);
@@ -370,10 +371,10 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
         sfor<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr T w = weight<Q, T>(i);
-            const T cu = cdot<i>(m.u);
+            const T cu = cdot<Q, i>(m.u);
             const T r = recip(w * (A1 + m.rho * cu * (T(3) + T(4.5) * cu)));
-            const T h = vh[tpos(i)];
-            sh += vs[tpos(i)] * h * r;
+            const T h = vh[tpos<Q>(i)];
+            sh += vs[tpos<Q>(i)] * h * r;
             hh += h * h * r;
         });
         const T beta = T(0.5) * om, ib = recip(beta);
@@ -414,7 +415,7 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
     tvalues<0>(g);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        d[i] -= g[tpos(i)];
+        d[i] -= g[tpos<Q>(i)];
     });
 }
 
@@ -487,7 +488,7 @@ __device__ __forceinline__ void cumulant_collide(T (&d)[Q], const Macro<Q, T> &m
     T mn[27];
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        mn[tpos(i)] = d[i];
+        mn[tpos<Q>(i)] = d[i];
     });
     tmoments<0>(mn);
     tmoments<1>(mn);
@@ -548,7 +549,7 @@ __device__ __forceinline__ void cumulant_collide(T (&d)[Q], const Macro<Q, T> &m
     tvalues<0>(k);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        d[i] = k[tpos(i)];
+        d[i] = k[tpos<Q>(i)];
     });
 }
 
@@ -598,17 +599,17 @@ __device__ __forceinline__ void pi_pairs(const T (&d)[Q], const Macro<Q, T> &m, 
     sfor<(Q - 1) / 2>([&](auto K) {
         constexpr int i = 2 * decltype(K)::value + 1, o = i + 1;
         constexpr T w = weight<Q, T>(i);
-        const T cu = cdot<i>(m.u);
+        const T cu = cdot<Q, i>(m.u);
         const T n = d[i] + d[o] - T(2) * w * (A + T(4.5) * m.rho * cu * cu);
-        if constexpr (cx(i) != 0) P[0] += n;
-        if constexpr (cy(i) != 0) P[1] += n;
-        if constexpr (cz(i) != 0) P[2] += n;
-        if constexpr (cx(i) * cy(i) == 1) P[3] += n;
-        if constexpr (cx(i) * cy(i) == -1) P[3] -= n;
-        if constexpr (cx(i) * cz(i) == 1) P[4] += n;
-        if constexpr (cx(i) * cz(i) == -1) P[4] -= n;
-        if constexpr (cy(i) * cz(i) == 1) P[5] += n;
-        if constexpr (cy(i) * cz(i) == -1) P[5] -= n;
+        if constexpr (cx<Q>(i) != 0) P[0] += n;
+        if constexpr (cy<Q>(i) != 0) P[1] += n;
+        if constexpr (cz<Q>(i) != 0) P[2] += n;
+        if constexpr (cx<Q>(i) * cy<Q>(i) == 1) P[3] += n;
+        if constexpr (cx<Q>(i) * cy<Q>(i) == -1) P[3] -= n;
+        if constexpr (cx<Q>(i) * cz<Q>(i) == 1) P[4] += n;
+        if constexpr (cx<Q>(i) * cz<Q>(i) == -1) P[4] -= n;
+        if constexpr (cy<Q>(i) * cz<Q>(i) == 1) P[5] += n;
+        if constexpr (cy<Q>(i) * cz<Q>(i) == -1) P[5] -= n;
     });
 }
 
@@ -647,9 +648,9 @@ __device__ __forceinline__ void relax_pairs(T (&d)[Q], const Macro<Q, T> &m, con
     sfor<(Q - 1) / 2>([&](auto I) {
         constexpr int i = 2 * decltype(I)::value + 1, o = i + 1;
         constexpr T w = weight<Q, T>(i);
-        const T cu = cdot<i>(m.u);
-        const T zp = w * (K + cu * cdot<i>(V));
-        const T zm = w * cdot<i>(W);
+        const T cu = cdot<Q, i>(m.u);
+        const T zp = w * (K + cu * cdot<Q, i>(V));
+        const T zm = w * cdot<Q, i>(W);
         const T di = d[i], dd = d[o];
         if constexpr (SRT) {
             d[i] = al * di + (zp + zm);
@@ -785,7 +786,7 @@ template <int Q, int i, typename T>
 __device__ __forceinline__ T abb_value(T post_i, const Macro<Q, T> &m, T rho_w)
 {
     constexpr T w = weight<Q, T>(i);
-    const T cu = cdot<i>(m.u);
+    const T cu = cdot<Q, i>(m.u);
     return -post_i + T(2) * w * (rho_w * (T(1) + T(4.5) * cu * cu - T(1.5) * m.uu) - T(1));
 }
 
@@ -810,10 +811,10 @@ __device__ __forceinline__ uint32_t cell_off(const DevBlock &B, int x, int y, in
     return (uint32_t)((z + 1) * B.plane + (y + 1) * B.pitch + B.xoff + x);
 }
 
-template <int i>
+template <int Q, int i>
 __device__ __forceinline__ int link_delta(const DevBlock &B)
 {
-    return cx(i) + cy(i) * B.pitch + cz(i) * B.plane;
+    return cx<Q>(i) + cy<Q>(i) * B.pitch + cz<Q>(i) * B.plane;
 }
 
 // Odd-sweep access of link i as one uniform base plus a per-lane choice of
@@ -847,15 +848,15 @@ __device__ __forceinline__ Alt<ST> pick_alt(const SweepArgs &a, const DevBlock &
     return p;
 }
 
-template <typename ST, int i>
+template <int Q, typename ST, int i>
 __device__ __forceinline__ Alt<ST> alt_in(const SweepArgs &a, const DevBlock &B)
 {
-    return pick_alt<ST>(a, B, opp(i), -link_delta<i>(B), i);
+    return pick_alt<ST>(a, B, opp(i), -link_delta<Q, i>(B), i);
 }
-template <typename ST, int i>
+template <int Q, typename ST, int i>
 __device__ __forceinline__ Alt<ST> alt_out(const SweepArgs &a, const DevBlock &B)
 {
-    return pick_alt<ST>(a, B, i, link_delta<i>(B), opp(i));
+    return pick_alt<ST>(a, B, i, link_delta<Q, i>(B), opp(i));
 }
 
 // Byte offsets of a cell for regular accesses shifted by 0, -1 and +1 cells
@@ -897,9 +898,9 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
         if constexpr (!SWAPPED) {
             f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), o.at));
         } else {
-            const Alt<ST> p = alt_in<ST, i>(a, B);
+            const Alt<ST> p = alt_in<Q, ST, i>(a, B);
             f[i] = ldv<ST>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
-                                                                      : xshift<-cx(i)>(o) + p.add_reg));
+                                                                      : xshift<-cx<Q>(i)>(o) + p.add_reg));
         }
     });
     if constexpr (SWAPPED) {
@@ -910,20 +911,20 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
             const DevBlock N = a.blocks[B.nbx[0]];
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if constexpr (cx(i) == 1)
+                if constexpr (cx<Q>(i) == 1)
                     if (!((special >> opp(i)) & 1u))
                         f[i] = ldv<ST, false>(at<ST>(slot_base<ST>(a, N, opp(i)),
-                                                     cell_off(N, N.n[0] - 1, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+                                                     cell_off(N, N.n[0] - 1, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)));
             });
         }
         if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
             const DevBlock N = a.blocks[B.nbx[1]];
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if constexpr (cx(i) == -1)
+                if constexpr (cx<Q>(i) == -1)
                     if (!((special >> opp(i)) & 1u))
                         f[i] = ldv<ST, false>(
-                            at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+                            at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)));
             });
         }
     }
@@ -942,8 +943,8 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
         if constexpr (!ODD) {
             stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i]);
         } else {
-            const Alt<ST> p = alt_out<ST, i>(a, B);
-            stv<ST>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx(i)>(o) + p.add_reg), f[i]);
+            const Alt<ST> p = alt_out<Q, ST, i>(a, B);
+            stv<ST>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg), f[i]);
         }
     });
     if constexpr (ODD) {
@@ -954,9 +955,9 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
             const DevBlock N = a.blocks[B.nbx[1]];
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if constexpr (cx(i) == 1)
+                if constexpr (cx<Q>(i) == 1)
                     if (!((special >> i) & 1u))
-                        stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)),
+                        stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)),
                                        f[i]);
             });
         }
@@ -964,10 +965,10 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
             const DevBlock N = a.blocks[B.nbx[0]];
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if constexpr (cx(i) == -1)
+                if constexpr (cx<Q>(i) == -1)
                     if (!((special >> i) & 1u))
                         stv<ST, false>(
-                            at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)),
+                            at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)),
                             f[i]);
             });
         }
@@ -976,48 +977,48 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
 
 // Regular incoming access of link i (slot opp(i) of x - c_i) as the direct
 // odd sweep makes it, returned as raw storage bits.
-template <typename ST, int i>
+template <int Q, typename ST, int i>
 __device__ __forceinline__ typename Codec<ST>::Raw load_regular_in(const SweepArgs &a, const DevBlock &B, const XOff &o,
                                                                    int x, int y, int z)
 {
-    if constexpr (cx(i) == 1) {
+    if constexpr (cx<Q>(i) == 1) {
         if (x == 0 && B.nbx[0] >= 0) {
             const DevBlock N = a.blocks[B.nbx[0]];
             return ldraw<ST, false>(at<ST>(slot_base<ST>(a, N, opp(i)),
-                                           cell_off(N, N.n[0] - 1, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+                                           cell_off(N, N.n[0] - 1, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)));
         }
     } else {
         if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
             const DevBlock N = a.blocks[B.nbx[1]];
             return ldraw<ST, false>(
-                at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy(i), z - cz(i)) * (uint32_t)sizeof(ST)));
+                at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)));
         }
     }
-    const Alt<ST> p = alt_in<ST, i>(a, B);
-    return ldraw<ST, false>(at<ST>(p.base, xshift<-cx(i)>(o) + p.add_reg));
+    const Alt<ST> p = alt_in<Q, ST, i>(a, B);
+    return ldraw<ST, false>(at<ST>(p.base, xshift<-cx<Q>(i)>(o) + p.add_reg));
 }
 // Regular outgoing access of link i (slot i of x + c_i) as the direct odd
 // sweep makes it.
-template <typename ST, int i>
+template <int Q, typename ST, int i>
 __device__ __forceinline__ void store_regular_out(const SweepArgs &a, const DevBlock &B, const XOff &o, int x, int y,
                                                   int z, typename Codec<ST>::T v)
 {
-    if constexpr (cx(i) == 1) {
+    if constexpr (cx<Q>(i) == 1) {
         if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
             const DevBlock N = a.blocks[B.nbx[1]];
-            stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)), v);
+            stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)), v);
             return;
         }
     } else {
         if (x == 0 && B.nbx[0] >= 0) {
             const DevBlock N = a.blocks[B.nbx[0]];
             stv<ST, false>(
-                at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy(i), z + cz(i)) * (uint32_t)sizeof(ST)), v);
+                at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)), v);
             return;
         }
     }
-    const Alt<ST> p = alt_out<ST, i>(a, B);
-    stv<ST, false>(at<ST>(p.base, xshift<cx(i)>(o) + p.add_reg), v);
+    const Alt<ST> p = alt_out<Q, ST, i>(a, B);
+    stv<ST, false>(at<ST>(p.base, xshift<cx<Q>(i)>(o) + p.add_reg), v);
 }
 
 // ---------------------------------------------------------------------------
@@ -1077,13 +1078,14 @@ template <int Q>
 __host__ __device__ constexpr int n_xshift()
 {
     int n = 0;
-    for (int i = 0; i < Q; ++i) n += cx(i) != 0;
+    for (int i = 0; i < Q; ++i) n += cx<Q>(i) != 0;
     return n;
 }
+template <int Q>
 __host__ __device__ constexpr int xshift_index(int i)
 {
     int n = 0;
-    for (int j = 0; j < i; ++j) n += cx(j) != 0;
+    for (int j = 0; j < i; ++j) n += cx<Q>(j) != 0;
     return n;
 }
 // LDS bytes of the staged odd sweep for row buffers of `stride` elements.
@@ -1140,19 +1142,19 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
         if (valid) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if constexpr (cx(i) != 0) {
-                    constexpr int k = xshift_index(i);
+                if constexpr (cx<Q>(i) != 0) {
+                    constexpr int k = xshift_index<Q>(i);
                     const char *base = slot_base<ST>(a, B, opp(i)) -
-                                       (int64_t)(cy(i) * B.pitch + cz(i) * B.plane) * (int64_t)sizeof(ST);
+                                       (int64_t)(cy<Q>(i) * B.pitch + cz<Q>(i) * B.plane) * (int64_t)sizeof(ST);
                     buf[k * stride + rb] = ldraw<ST>(at<ST>(base, boff));
                     if (!RING && !ring) {
-                        if (cx(i) == 1 && lx == 0) buf[k * stride + rb - 1] = load_regular_in<ST, i>(a, B, o, x, y, z);
-                        if (cx(i) == -1 && lx == ex - 1)
-                            buf[k * stride + rb + 1] = load_regular_in<ST, i>(a, B, o, x, y, z);
+                        if (cx<Q>(i) == 1 && lx == 0) buf[k * stride + rb - 1] = load_regular_in<Q, ST, i>(a, B, o, x, y, z);
+                        if (cx<Q>(i) == -1 && lx == ex - 1)
+                            buf[k * stride + rb + 1] = load_regular_in<Q, ST, i>(a, B, o, x, y, z);
                     }
                     if ((special >> opp(i)) & 1u) f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
                 } else {
-                    const Alt<ST> p = alt_in<ST, i>(a, B);
+                    const Alt<ST> p = alt_in<Q, ST, i>(a, B);
                     f[i] = ldv<ST>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
                 }
             });
@@ -1161,9 +1163,9 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
         if (active) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if constexpr (cx(i) != 0) {
-                    constexpr int k = xshift_index(i);
-                    if (!((special >> opp(i)) & 1u)) f[i] = Codec<ST>::dec(buf[k * stride + row + lane_at(-cx(i))]);
+                if constexpr (cx<Q>(i) != 0) {
+                    constexpr int k = xshift_index<Q>(i);
+                    if (!((special >> opp(i)) & 1u)) f[i] = Codec<ST>::dec(buf[k * stride + row + lane_at(-cx<Q>(i))]);
                 }
             });
         }
@@ -1181,17 +1183,17 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const bool sp = (special >> i) & 1u;
-                if constexpr (cx(i) == 0) {
-                    const Alt<ST> p = alt_out<ST, i>(a, B);
+                if constexpr (cx<Q>(i) == 0) {
+                    const Alt<ST> p = alt_out<Q, ST, i>(a, B);
                     stv<ST>(at<ST>(p.base, boff + (sp ? p.add_sp : p.add_reg)), f[i]);
                 } else {
-                    constexpr int k = xshift_index(i);
+                    constexpr int k = xshift_index<Q>(i);
                     if (sp) {
                         stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
-                    } else if (!RING && !ring && ((cx(i) == 1 && lx == ex - 1) || (cx(i) == -1 && lx == 0))) {
-                        store_regular_out<ST, i>(a, B, o, x, y, z, f[i]);  // target outside the segment
+                    } else if (!RING && !ring && ((cx<Q>(i) == 1 && lx == ex - 1) || (cx<Q>(i) == -1 && lx == 0))) {
+                        store_regular_out<Q, ST, i>(a, B, o, x, y, z, f[i]);  // target outside the segment
                     } else {
-                        buf[k * stride + row + lane_at(cx(i))] = Codec<ST>::enc(f[i]);
+                        buf[k * stride + row + lane_at(cx<Q>(i))] = Codec<ST>::enc(f[i]);
                     }
                 }
             });
@@ -1204,12 +1206,12 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
         if (valid) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if constexpr (cx(i) != 0) {
-                    constexpr int k = xshift_index(i);
-                    const int lw = lane_at(-cx(i));
+                if constexpr (cx<Q>(i) != 0) {
+                    constexpr int k = xshift_index<Q>(i);
+                    const int lw = lane_at(-cx<Q>(i));
                     if (lw >= 0 && lw < ex && !((info[l - lx + lw] >> i) & 1u)) {
                         const char *base = slot_base<ST>(a, B, i) +
-                                           (int64_t)(cy(i) * B.pitch + cz(i) * B.plane) * (int64_t)sizeof(ST);
+                                           (int64_t)(cy<Q>(i) * B.pitch + cz<Q>(i) * B.plane) * (int64_t)sizeof(ST);
                         straw<ST>(at<ST>(base, boff), buf[k * stride + rb]);
                     }
                 }
@@ -1345,9 +1347,9 @@ __global__ __launch_bounds__(kWG) void moments_kernel(const MomArgs ma)
                     constexpr int i = decltype(I)::value;
                     const double v = (double)f[i];
                     drho += v;
-                    if constexpr (cx(i) != 0) j[0] += cx(i) * v;
-                    if constexpr (cy(i) != 0) j[1] += cy(i) * v;
-                    if constexpr (cz(i) != 0) j[2] += cz(i) * v;
+                    if constexpr (cx<Q>(i) != 0) j[0] += cx<Q>(i) * v;
+                    if constexpr (cy<Q>(i) != 0) j[1] += cy<Q>(i) * v;
+                    if constexpr (cz<Q>(i) != 0) j[2] += cz<Q>(i) * v;
                 });
                 rho = 1.0 + drho;
                 double pu[3];
@@ -1424,9 +1426,9 @@ __global__ __launch_bounds__(kWG) void filter_kernel(const SweepArgs a, int fac,
                         constexpr int i = decltype(I)::value;
                         const double v = (double)f[i];
                         drho += v;
-                        if constexpr (cx(i) != 0) j[0] += cx(i) * v;
-                        if constexpr (cy(i) != 0) j[1] += cy(i) * v;
-                        if constexpr (cz(i) != 0) j[2] += cz(i) * v;
+                        if constexpr (cx<Q>(i) != 0) j[0] += cx<Q>(i) * v;
+                        if constexpr (cy<Q>(i) != 0) j[1] += cy<Q>(i) * v;
+                        if constexpr (cz<Q>(i) != 0) j[2] += cz<Q>(i) * v;
                     });
                     const double rho = 1.0 + drho;
                     double u[3];
@@ -1475,7 +1477,7 @@ __global__ __launch_bounds__(kWG) void init_kernel(const SweepArgs a, const doub
         const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         sfor<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const double cu = cdot<i>(u);
+            const double cu = cdot<Q, i>(u);
             const double v = weight<Q, double>(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
             stv<ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)v);
         });
@@ -1580,9 +1582,9 @@ __global__ __launch_bounds__(kWG) void force_kernel(const SweepArgs a, double *p
                     if ((L.bb >> i) & 1u) {
                         const double f = weight<Q, double>(i) + (double)ldv<ST, false>(at<ST>(slot_base<ST>(a, B, opp(i)), off));
                         const int k = ((to_solid >> i) & 1u) ? 0 : 3;
-                        if constexpr (cx(i) != 0) acc[k + 0] += 2.0 * cx(i) * f;
-                        if constexpr (cy(i) != 0) acc[k + 1] += 2.0 * cy(i) * f;
-                        if constexpr (cz(i) != 0) acc[k + 2] += 2.0 * cz(i) * f;
+                        if constexpr (cx<Q>(i) != 0) acc[k + 0] += 2.0 * cx<Q>(i) * f;
+                        if constexpr (cy<Q>(i) != 0) acc[k + 1] += 2.0 * cy<Q>(i) * f;
+                        if constexpr (cz<Q>(i) != 0) acc[k + 2] += 2.0 * cz<Q>(i) * f;
                         acc[k == 0 ? 6 : 7] += 1.0;
                     }
                 });
@@ -1648,7 +1650,9 @@ static hipError_t sweep_c(int coll, bool odd, const SweepArgs &a, int grid, hipS
     switch (coll) {
     case 0: return sweep_q<Q, 0>(odd, a, grid, st);
     case 1: return sweep_q<Q, 1>(odd, a, grid, st);
-    case 2: return sweep_q<Q, 2>(odd, a, grid, st);
+    case 2:
+        if constexpr (Q == 19 || Q == 27) return sweep_q<Q, 2>(odd, a, grid, st);
+        return hipErrorNotSupported;
     case 3:
         if constexpr (Q == 27) return sweep_q<Q, 3>(odd, a, grid, st);
         return hipErrorNotSupported;
@@ -1693,36 +1697,51 @@ static hipError_t pdfs_q(const SweepArgs &a, double *buf, int z0, int z1, bool t
 #define WLB_CAT2(a, b) a##b
 #define WLB_CAT(a, b) WLB_CAT2(a, b)
 
+// Calls f(std::integral_constant<int, Q>{}) for the velocity set with q
+// populations.
+template <typename F>
+static hipError_t by_set(int q, F &&f)
+{
+    switch (q) {
+    case 9: return f(std::integral_constant<int, 9>{});
+    case 15: return f(std::integral_constant<int, 15>{});
+    case 19: return f(std::integral_constant<int, 19>{});
+    case 27: return f(std::integral_constant<int, 27>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t WLB_CAT(sweep_, WLB_SUFFIX)(int q, int coll, bool odd, const SweepArgs &a, int grid, hipStream_t st)
 {
-    return q == 19 ? sweep_c<19>(coll, odd, a, grid, st) : sweep_c<27>(coll, odd, a, grid, st);
+    return by_set(q, [&](auto S) { return sweep_c<decltype(S)::value>(coll, odd, a, grid, st); });
 }
 
 hipError_t WLB_CAT(moments_, WLB_SUFFIX)(int q, const MomArgs &a, int grid, hipStream_t st)
 {
-    return q == 19 ? moments_q<19>(a, grid, st) : moments_q<27>(a, grid, st);
+    return by_set(q, [&](auto S) { return moments_q<decltype(S)::value>(a, grid, st); });
 }
 
 hipError_t WLB_CAT(force_, WLB_SUFFIX)(int q, const SweepArgs &a, double *partials, int grid, hipStream_t st)
 {
-    return q == 19 ? force_q<19>(a, partials, grid, st) : force_q<27>(a, partials, grid, st);
+    return by_set(q, [&](auto S) { return force_q<decltype(S)::value>(a, partials, grid, st); });
 }
 
 hipError_t WLB_CAT(init_, WLB_SUFFIX)(int q, const SweepArgs &a, const double *rhou, int z0, int z1, int grid,
                                       hipStream_t st)
 {
-    if (q == 19)
-        hipLaunchKernelGGL((init_kernel<19, WLB_STORAGE>), dim3(grid), dim3(kWG), 0, st, a, rhou, z0, z1);
-    else
-        hipLaunchKernelGGL((init_kernel<27, WLB_STORAGE>), dim3(grid), dim3(kWG), 0, st, a, rhou, z0, z1);
-    return hipGetLastError();
+    return by_set(q, [&](auto S) {
+        constexpr int Q = decltype(S)::value;
+        hipLaunchKernelGGL((init_kernel<Q, WLB_STORAGE>), dim3(grid), dim3(kWG), 0, st, a, rhou, z0, z1);
+        return hipGetLastError();
+    });
 }
 
 hipError_t WLB_CAT(pdfs_, WLB_SUFFIX)(int q, const SweepArgs &a, double *buf, int z0, int z1, bool to_device,
                                       bool swapped, int grid, hipStream_t st)
 {
-    return q == 19 ? pdfs_q<19>(a, buf, z0, z1, to_device, swapped, grid, st)
-                   : pdfs_q<27>(a, buf, z0, z1, to_device, swapped, grid, st);
+    return by_set(q, [&](auto S) {
+        return pdfs_q<decltype(S)::value>(a, buf, z0, z1, to_device, swapped, grid, st);
+    });
 }
 
 hipError_t WLB_CAT(filter_, WLB_SUFFIX)(int q, const SweepArgs &a, int fac, double *out, int64_t ncoarse,
@@ -1731,18 +1750,14 @@ hipError_t WLB_CAT(filter_, WLB_SUFFIX)(int q, const SweepArgs &a, int fac, doub
     int64_t g = (ncoarse + kWG - 1) / kWG;
     if (g > 16384) g = 16384;
     if (g < 1) g = 1;
-    if (q == 19) {
+    return by_set(q, [&](auto S) {
+        constexpr int Q = decltype(S)::value;
         if (swapped)
-            hipLaunchKernelGGL((filter_kernel<19, WLB_STORAGE, true>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
+            hipLaunchKernelGGL((filter_kernel<Q, WLB_STORAGE, true>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
         else
-            hipLaunchKernelGGL((filter_kernel<19, WLB_STORAGE, false>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
-    } else {
-        if (swapped)
-            hipLaunchKernelGGL((filter_kernel<27, WLB_STORAGE, true>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
-        else
-            hipLaunchKernelGGL((filter_kernel<27, WLB_STORAGE, false>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
-    }
-    return hipGetLastError();
+            hipLaunchKernelGGL((filter_kernel<Q, WLB_STORAGE, false>), dim3((int)g), dim3(kWG), 0, st, a, fac, out);
+        return hipGetLastError();
+    });
 }
 
 hipError_t WLB_CAT(exchange_, WLB_SUFFIX)(void *arena, const DevBlock *blocks, const uint32_t *masks,

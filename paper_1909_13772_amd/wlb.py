@@ -25,7 +25,7 @@ WLB_ERR_STATE = -3
 WLB_ERR_DIVERGED = -4
 WLB_ERR_UNSUPPORTED = -5
 
-D3Q19, D3Q27 = 19, 27
+D2Q9, D3Q15, D3Q19, D3Q27 = 9, 15, 19, 27
 SRT, TRT, MRT, KBC, CUMULANT = 0, 1, 2, 3, 4
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 CLOSURE_NONE, CLOSURE_SMAG, CLOSURE_MLP = 0, 1, 2

@@ -151,7 +151,7 @@ def test_create_rejects_bad_block_lists(bad):
 
 def test_create_rejects_bad_enums():
     with pytest.raises(wlb.WlbError):
-        wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 15, wlb.F64)
+        wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 13, wlb.F64)
     with pytest.raises(wlb.WlbError):
         wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 19, 7)
 
@@ -190,5 +190,20 @@ def test_calls_before_bind_fail_cleanly():
         with pytest.raises(wlb.WlbError) as e:
             wlb.wlb_lbm_step(h, 1)
         assert e.value.code == wlb.WLB_ERR_STATE
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
+@pytest.mark.parametrize("periodic", [(1, 1, 1), (1, 0, 1), (0, 1, 0)])
+def test_exchange_counts_every_velocity_set(q, periodic):
+    """The exchange list moves each population that crosses a periodic y/z
+    face exactly once, for every velocity set (brute force over the oracle's
+    velocities)."""
+    n = (6, 5, 4)
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), n)], n, periodic, q, wlb.F32)
+    try:
+        info = wlb.wlb_info(h)
+        assert info.xchg_elems == _crossing_links(n, periodic, q, xnbr=bool(periodic[0]))
     finally:
         wlb.wlb_blocks_destroy(h)

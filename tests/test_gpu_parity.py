@@ -56,14 +56,25 @@ def test_taylor_green_32_fp64_100_steps():
     assert abs(tot[4] / e0 - exact) < 0.02 * exact
 
 
-@pytest.mark.parametrize("q,coll", [(19, 0), (19, 1), (19, 2), (27, 0), (27, 1), (27, 2), (27, 3), (27, 4)])
+def _plane(q, u, F):
+    """D2Q9 has no z velocities: start it without u_z and F_z."""
+    if q == 9:
+        u = u.copy()
+        u[2] = 0.0
+        F = (F[0], F[1], 0.0)
+    return u, F
+
+
+@pytest.mark.parametrize("q,coll", [(19, 0), (19, 1), (19, 2), (27, 0), (27, 1), (27, 2), (27, 3), (27, 4),
+                                    (9, 0), (9, 1), (15, 0), (15, 1)])
 @pytest.mark.parametrize("steps", [6, 7])
 def test_random_state_periodic_fp64(q, coll, steps):
-    """Ragged 20x18x17 periodic box, random state, body force, every operator."""
+    """Ragged 20x18x17 periodic box, random state, body force, every operator
+    and velocity set."""
     say(f"case random q{q} coll{coll} steps{steps}")
     shape = (20, 18, 17)
     rho, u = inputs.random_state(shape, seed=q + coll)
-    F = (1e-5, -2e-5, 3e-6)
+    u, F = _plane(q, u, (1e-5, -2e-5, 3e-6))
     kw = dict(tau=0.7, magic=0.11, omega_bulk=1.3, omega_higher=1.1, force=F)
     p = wlb.make_params(**kw)
     gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), q, wlb.F64, coll, p, rho, u, steps=steps)
@@ -72,12 +83,12 @@ def test_random_state_periodic_fp64(q, coll, steps):
     _compare(f"random q{q} c{coll} s{steps}", wlb.F64, q, gpu, orc, None, np.prod(shape))
 
 
-@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (9, 1), (15, 1)])
 def test_channel_walls_force_fp64(q, coll):
     say(f"case channel q{q}")
     shape = (24, 20, 12)
     rho, u = inputs.random_state(shape, seed=5, umag=0.01)
-    F = (2e-5, 0, 0)
+    u, F = _plane(q, u, (2e-5, 0, 0))
     p = wlb.make_params(tau=0.8, magic=3 / 16, force=F, omega_bulk=1.2, omega_higher=0.9)
     gpu = gpu_run(wlb.single_block(shape), shape, (1, 0, 1), q, wlb.F64, coll, p, rho, u, steps=9)
     op = oracle_params(q, coll, 0.8, 3 / 16, (1, 0, 1), F, omega_bulk=1.2, omega_higher=0.9)
@@ -89,6 +100,7 @@ def _porous_case(q, coll, storage, steps, seed=1, **kw):
     blocks, dom = inputs.rectilinear_blocks([8, 12, 6], [10, 6], [7, 9])
     solid, frac, _ = inputs.spheres(dom, seed=seed, rmin=2.0, rmax=4.0, solid_fraction=0.2, clear_x=2)
     rho, u = inputs.random_state(dom, seed=seed + 10, umag=0.01)
+    u, _ = _plane(q, u, (0, 0, 0))
     p = wlb.make_params(tau=0.8, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, pressure_axis=0,
                         rho_in=1.002, rho_out=0.998)
     gpu = gpu_run(blocks, dom, (0, 1, 1), q, storage, coll, p, rho, u, solid, steps=steps, **kw)
@@ -98,7 +110,7 @@ def _porous_case(q, coll, storage, steps, seed=1, **kw):
     return gpu, orc, solid, dom
 
 
-@pytest.mark.parametrize("q,coll", [(27, 2), (19, 0), (19, 1), (19, 2), (27, 3), (27, 4)])
+@pytest.mark.parametrize("q,coll", [(27, 2), (19, 0), (19, 1), (19, 2), (27, 3), (27, 4), (9, 1), (15, 0), (15, 1)])
 @pytest.mark.parametrize("steps", [10, 11])
 def test_porous_uneven_blocks_pressure_fp64(q, coll, steps):
     """Uneven rectilinear blocks (3 x 2 x 2), spheres, density faces on x,
@@ -109,7 +121,7 @@ def test_porous_uneven_blocks_pressure_fp64(q, coll, steps):
     _compare(f"porous q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
 
 
-@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (9, 1), (15, 1)])
 def test_porous_uneven_blocks_lds_staged_odd_sweep_fp64(q, coll):
     """The porous case with the odd sweep staged in LDS: x-neighbour blocks
     supply the halo elements and take the stores past the row segment."""
@@ -119,7 +131,7 @@ def test_porous_uneven_blocks_lds_staged_odd_sweep_fp64(q, coll):
     _compare(f"porous lds q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
 
 
-@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (9, 1), (15, 1)])
 def test_porous_uneven_blocks_overlapped_exchange_fp64(q, coll):
     """The porous case with each sweep split into interior and frontier and
     the frontier plus the exchange on a second stream."""
@@ -166,6 +178,33 @@ def test_kbc_and_cumulant_need_d3q27(coll):
         assert e.value.code == wlb.WLB_ERR_UNSUPPORTED
     finally:
         B.close()
+
+
+@pytest.mark.parametrize("q,coll", [(9, 2), (15, 2), (15, 3), (9, 4)])
+def test_moment_space_collisions_need_d3q19_or_d3q27(q, coll):
+    dom = (8, 6, 4)
+    rho, u = inputs.uniform_state(dom)
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 1, 1), stencil=q, storage=wlb.F64)
+    try:
+        with pytest.raises(wlb.WlbError) as e:
+            B.init(coll, wlb.make_params(tau=0.8), rho, u)
+        assert e.value.code == wlb.WLB_ERR_UNSUPPORTED
+    finally:
+        B.close()
+
+
+@pytest.mark.parametrize("q,storage", [(9, 1), (15, 1), (9, 2), (15, 2)])
+def test_small_sets_reduced_precision_vs_fp64_oracle(q, storage):
+    """D2Q9 / D3Q15 TRT with FP32 and FP16 deviation storage, Smagorinsky
+    closure on, against the FP64 oracle."""
+    say(f"case small sets q{q} storage{storage}")
+    shape = (24, 20, 16)
+    rho, u = inputs.random_state(shape, seed=12, umag=0.03)
+    u, _ = _plane(q, u, (0, 0, 0))
+    p = wlb.make_params(tau=0.6, magic=3 / 16, closure=wlb.CLOSURE_SMAG, cs_smag=0.1)
+    gpu = gpu_run(wlb.single_block(shape), shape, (1, 1, 1), q, storage, wlb.TRT, p, rho, u, steps=20)
+    orc = oracle_run(oracle_params(q, 1, 0.6, 3 / 16, (1, 1, 1), closure=1, cs_smag=0.1), shape, rho, u, None, 20)
+    _compare(f"small q{q} {storage}", storage, q, gpu, orc, None, np.prod(shape), check_pops=False)
 
 
 @pytest.mark.parametrize("coll", [0, 1])
@@ -244,7 +283,7 @@ def test_block_decomposition_is_bitwise_invariant(storage):
                 assert np.array_equal(d, ref), f"layout {k} differs"
 
 
-@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (15, 1), (9, 0)])
 @pytest.mark.parametrize("variant", ["rows", "segments", "direct", "direct-segments"])
 def test_x_wrap_with_solids_across_the_periodic_face_fp64(q, coll, variant):
     """One block periodic in x (x accesses wrap, no x exchange) with spheres
@@ -260,7 +299,7 @@ def test_x_wrap_with_solids_across_the_periodic_face_fp64(q, coll, variant):
                                     clear_x=0)
     assert solid[:, :, 0].any() and solid[:, :, -1].any(), "spheres must cross the x face"
     rho, u = inputs.random_state(dom, seed=6, umag=0.01)
-    F = (1e-5, 0, 2e-6)
+    u, F = _plane(q, u, (1e-5, 0, 2e-6))
     p = wlb.make_params(tau=0.75, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, force=F)
     gpu = gpu_run(wlb.single_block(dom), dom, (1, 0, 1), q, wlb.F64, coll, p, rho, u, solid, steps=7, **kw)
     info = gpu[4].info()
