@@ -337,6 +337,74 @@ def calibrate(wlb, torch, params, seeds, n, factor, steps, snap, tau_f=TAU_F,
     return g_best, cs_best, table
 
 
+def spsa_minimise(loss, z0, iters, c=0.1, step0=0.1, alpha=0.602, gamma=0.101, seed=0, log=None):
+    """Simultaneous-perturbation stochastic approximation (Spall 1992):
+    each iteration estimates the gradient of `loss` from two evaluations at
+    z +- c_k Delta (Delta random signs), and steps z -= a_k g.  The gain a is
+    set from the first gradient estimate so that the first step moves each
+    coordinate by about step0.  Returns the best point evaluated and its
+    loss, with the history of (iteration, loss+, loss-)."""
+    rng = np.random.default_rng(seed)
+    z = np.array(z0, np.float64)
+    A = 0.1 * iters
+    best_z, best_l = z.copy(), loss(z)
+    hist = [(0, best_l, best_l)]
+    a = None
+    for k in range(iters):
+        ck = c / (k + 1) ** gamma
+        delta = rng.choice((-1.0, 1.0), size=z.size)
+        lp, lm = loss(z + ck * delta), loss(z - ck * delta)
+        hist.append((k + 1, lp, lm))
+        for zz, ll in ((z + ck * delta, lp), (z - ck * delta, lm)):
+            if ll < best_l:
+                best_z, best_l = zz.copy(), ll
+        if not (math.isfinite(lp) and math.isfinite(lm)):
+            continue  # a divergent probe carries no slope
+        g = (lp - lm) / (2 * ck) * delta
+        if a is None:
+            gm = float(np.abs(g).mean())
+            if gm == 0.0:
+                continue
+            a = step0 * (A + 1) ** alpha / gm
+        z = z - a / (k + 1 + A) ** alpha * g
+        if log:
+            log(f"[les] spsa {k + 1}/{iters}: loss+ {lp:.5f} loss- {lm:.5f} best {best_l:.5f}")
+    return best_z, best_l, hist
+
+
+def train_a_posteriori(wlb, torch, params, seeds, n, factor, steps, snap, tau_f=TAU_F, iters=40, c=0.1, step0=0.1):
+    """Solver-in-the-loop training of the network's output layer (its 32
+    weights and the bias): the loss of a parameter vector is the time-averaged
+    kinetic-energy error of coarse LES runs with that network against the
+    filtered fine runs of the same seeds, minimised by SPSA.  Coordinates are
+    scaled by the spread of the output weights, so one unit moves every
+    weight by about that much."""
+    tau0 = coarse_tau(factor, tau_f)
+    csteps, cevery = steps // factor, snap // factor
+    refs = []
+    for sd in seeds:
+        refs.append(reference(wlb, torch, sd, n, factor, steps, snap, tau_f))
+        _log(f"[les] reference seed {sd} done")
+    lo = B3 - 32
+    theta0 = params[lo:B3 + 1].astype(np.float64)
+    scale = np.full(33, float(np.std(params[lo:B3])) or 1.0)
+
+    def unpack(z):
+        P = params.copy()
+        P[lo:B3 + 1] = (theta0 + scale * z).astype(np.float32)
+        return P
+
+    def loss(z):
+        P = unpack(z)
+        errs = [energy_error(les_run(wlb, torch, rc, uc, wlb.CLOSURE_MLP, P, csteps, cevery, tau0), ref)
+                for rc, uc, ref in refs]
+        m = float(np.mean(errs))
+        return m if math.isfinite(m) else float("inf")
+
+    z, best, hist = spsa_minimise(loss, np.zeros(33), iters, c=c, step0=step0, log=_log)
+    return unpack(z), best, hist
+
+
 def evaluate(wlb, torch, seed, params, n, factor, steps, snap, tau_f=TAU_F, keep_series=False, variants=None):
     """A-posteriori comparison on a held-out seed: the coarse LES without a
     model, with Smagorinsky and with the network (and any extra
@@ -380,7 +448,9 @@ def main(argv=None):
     ap.add_argument("--augment", type=int, default=3, help="phase train: symmetry images per training pair")
     ap.add_argument("--calib-seeds", type=str, default="16-17", help="phase train: seeds of the a-posteriori calibration")
     ap.add_argument("--out", type=str, default="gpurun_out/les")
-    ap.add_argument("--phase", choices=["data", "train", "calib", "eval"], default="data")
+    ap.add_argument("--phase", choices=["data", "train", "calib", "apost", "eval"], default="data")
+    ap.add_argument("--iters", type=int, default=40, help="phase apost: SPSA iterations")
+    ap.add_argument("--cs", type=float, default=0.055, help="phase apost: Smagorinsky constant compared against")
     ap.add_argument("--gains", type=str, default="0.15,0.25,0.35,0.5,0.7,1.0,1.5",
                     help="calibration: gains of the network's correction")
     ap.add_argument("--cs-values", type=str, default="0.03,0.045,0.06,0.08,0.1,0.13",
@@ -418,6 +488,24 @@ def main(argv=None):
                        keep_series=True)
         with open(os.path.join(args.out, f"eval_seed{args.test_seed}_tauf{args.tau_f}.json"), "w") as fh:
             json.dump(res, fh)
+        return 0
+    if args.phase == "apost":
+        # solver-in-the-loop training of the output layer, starting from the
+        # given (a-priori trained, gain-calibrated) network
+        P0 = np.load(args.params)
+        cal = seeds(args.calib_seeds)
+        t0 = time.time()
+        Pa, best, hist = train_a_posteriori(wlb, torch, P0, cal, args.n, args.factor, args.steps, args.snap,
+                                            tau_f=args.tau_f, iters=args.iters)
+        np.save(os.path.join(args.out, "mlp_params_aposteriori.npy"), Pa)
+        res = evaluate(wlb, torch, args.test_seed, P0, args.n, args.factor, args.steps, args.snap, tau_f=args.tau_f,
+                       keep_series=True, variants=[("smagorinsky_calibrated", wlb.CLOSURE_SMAG, None, args.cs),
+                                                   ("mlp_aposteriori", wlb.CLOSURE_MLP, Pa, 0.1)])
+        out = {"start_params": args.params, "train_seeds": cal, "test_seed": args.test_seed, "iters": args.iters,
+               "loss_start": hist[0][1], "loss_best": best, "history": hist, "seconds": time.time() - t0,
+               "a_posteriori": res}
+        with open(os.path.join(args.out, "apost_summary.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
         return 0
     tr, va = seeds(args.train_seeds), seeds(args.val_seeds)
     summary = {"n_fine": args.n, "factor": args.factor, "steps_fine": args.steps, "snap": args.snap,

@@ -27,7 +27,7 @@ def _check(case, q, gpu, orc, solid, n):
     assert abs(tot[0] - to[0]) <= 1e-9 * max(1.0, abs(to[0])), (case, tot[0], to[0])
 
 
-@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (15, 1), (9, 0)])
 @pytest.mark.parametrize("overlap", [False, True])
 def test_one_cell_thick_blocks(q, coll, overlap):
     """Blocks one cell thick along every axis: ghost regions are whole blocks
@@ -37,6 +37,9 @@ def test_one_cell_thick_blocks(q, coll, overlap):
     blocks, dom = inputs.rectilinear_blocks([1, 6, 1], [1, 4], [2, 1, 3])
     rho, u = inputs.random_state(dom, seed=31, umag=0.02)
     F = (1e-5, -1e-5, 2e-6)
+    if q == 9:  # no z velocities in D2Q9
+        u[2] = 0.0
+        F = (1e-5, -1e-5, 0.0)
     p = wlb.make_params(tau=0.7, magic=3 / 16, omega_bulk=1.1, omega_higher=1.0, force=F)
     for periodic in ((1, 1, 1), (1, 0, 1)):
         gpu = gpu_run(blocks, dom, periodic, q, wlb.F64, coll, p, rho, u, steps=7, overlap=overlap)
@@ -45,17 +48,20 @@ def test_one_cell_thick_blocks(q, coll, overlap):
         _check(f"thin {periodic}", q, gpu, orc, None, np.prod(dom))
 
 
+@pytest.mark.parametrize("q", [19, 15, 9])
 @pytest.mark.parametrize("dom", [(1, 1, 1), (2, 1, 3), (1, 5, 1)])
-def test_degenerate_periodic_domains(dom):
+def test_degenerate_periodic_domains(dom, q):
     """Domains with extent 1 or 2: the block is its own neighbour on every
     periodic face (x wraps onto the same cell)."""
-    say(f"case degenerate {dom}")
+    say(f"case degenerate {dom} q{q}")
     rho, u = inputs.random_state(dom, seed=32, umag=0.02)
+    if q == 9:
+        u[2] = 0.0
     p = wlb.make_params(tau=0.9, magic=0.2)
-    gpu = gpu_run(wlb.single_block(dom), dom, (1, 1, 1), 19, wlb.F64, wlb.TRT, p, rho, u, steps=5)
-    op = oracle_params(19, wlb.TRT, 0.9, 0.2, (1, 1, 1))
+    gpu = gpu_run(wlb.single_block(dom), dom, (1, 1, 1), q, wlb.F64, wlb.TRT, p, rho, u, steps=5)
+    op = oracle_params(q, wlb.TRT, 0.9, 0.2, (1, 1, 1))
     orc = oracle_run(op, dom, rho, u, None, 5)
-    _check(f"degenerate {dom}", 19, gpu, orc, None, np.prod(dom))
+    _check(f"degenerate {dom} q{q}", q, gpu, orc, None, np.prod(dom))
 
 
 def test_zero_steps_reproduce_the_initial_state():

@@ -2,6 +2,7 @@
 symmetries used to augment training pairs, the coarse relaxation time of the
 acoustic scaling, and the shell spectrum."""
 import itertools
+import math
 
 import numpy as np
 
@@ -75,3 +76,34 @@ def test_gain_as_output_bias_shift():
     sp = np.log1p(np.exp(o))
     for g in (0.5, 2.0, 6.0):
         assert np.all(np.abs(np.log1p(np.exp(o + np.log(g))) / (g * sp) - 1) < 0.02)
+
+
+def test_spsa_descends_a_quadratic_and_returns_its_best_point():
+    """SPSA on a convex quadratic in 33 dimensions (the size of the output
+    layer) must cut the loss several-fold, and the point it returns must be
+    the best one it evaluated."""
+    rng = np.random.default_rng(0)
+    H = rng.normal(size=(33, 33))
+    H = H @ H.T / 33 + np.eye(33)
+    z0 = rng.normal(size=33)
+    seen = []
+
+    def f(z):
+        v = float(0.5 * z @ H @ z)
+        seen.append(v)
+        return v
+
+    z, best, hist = les.spsa_minimise(f, z0, 60, c=0.1, step0=0.1)
+    assert best < 0.5 * f(z0)
+    assert abs(f(z) - best) < 1e-12 and best <= min(seen) + 1e-12
+    assert len(hist) == 61
+
+
+def test_spsa_skips_divergent_probes():
+    """A probe whose loss is infinite (a coarse run that blew up) gives no
+    slope: the iterate must stay finite and the best point finite."""
+    def f(z):
+        return float("inf") if z[0] > 0.5 else float((z ** 2).sum())
+
+    z, best, _ = les.spsa_minimise(f, np.full(4, 0.4), 30, c=0.2, step0=0.05, seed=3)
+    assert np.all(np.isfinite(z)) and math.isfinite(best) and best <= 4 * 0.16
