@@ -193,6 +193,22 @@ int wlb_moments_get(wlb_blocks_t h, double *rho, double *u, double totals[8]);
  * or no step since it), WLB_ERR_HIP. */
 int wlb_force_get(wlb_blocks_t h, double out[8]);
 
+/* Debug check of the AA pattern's race freedom (Sec. 5.1.1 update rule, in
+ * place): every (cell, population slot) must be written by exactly one
+ * thread per sweep.  Zeroes the populations and runs one sweep of the given
+ * parity (odd = 0: even sweep and the exchange after it; odd = 1: odd sweep
+ * and the exchange after it) with the handle's tiles, grid and overlap
+ * setting, in kernels where each population store adds 1 to a counter in
+ * its place and each exchange copy adds the ghost cell's counter to its
+ * target.  counts[q][N] (host, caller-owned, global order, storage slots)
+ * receives the counters of every interior (cell, slot): a correct sweep
+ * leaves 1 in every slot of a fluid cell and 0 in solid cells.  Needs FP32
+ * storage (the counters use its 4-byte slots).  Leaves counters in place of
+ * the state: call wlb_lbm_init before the next step.  Synchronises the stream.
+ * Errors: WLB_ERR_ARG, WLB_ERR_STATE (before wlb_lbm_init),
+ * WLB_ERR_UNSUPPORTED (storage other than FP32), WLB_ERR_HIP. */
+int wlb_debug_write_coverage(wlb_blocks_t h, int32_t odd, uint32_t *counts);
+
 /* Population deviations d_i = f_i - w_i of the current state in natural
  * layout d[q][N] (FP64, host), and the reverse.  set also re-establishes the
  * natural layout so the next sweep is even; solid cells are ignored.  Used

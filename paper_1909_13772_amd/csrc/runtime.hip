@@ -93,6 +93,7 @@ struct wlb_blocks {
     // the rest (frontier); the frontier and the exchange run on a second
     // stream while the interior runs on the bound stream (autotuner candidate)
     bool overlap = false;
+    bool cover = false;   // sweeps and exchanges count writes (wlb_debug_write_coverage)
     int nint_tiles = 0;   // interior box tiles come first in `tiles` when split
     int nint_ltiles = 0;  // interior fluid-cell tiles come first in `ltiles`
     bool tiles_split = false;
@@ -281,6 +282,7 @@ int launch_grid(const wlb_blocks *h)
 
 hipError_t sweep_launch(const wlb_blocks *h, bool odd, const SweepArgs &a, int g, hipStream_t st)
 {
+    if (h->cover) return sweep_cover(h->q, h->collision, odd, a, g, st);
     switch (h->storage) {
     case WLB_F64: return sweep_f64(h->q, h->collision, odd, a, g, st);
     case WLB_F32: return sweep_f32(h->q, h->collision, odd, a, g, st);
@@ -334,6 +336,7 @@ hipError_t exchange_dispatch(const wlb_blocks *h, bool after_odd, hipStream_t st
     void *pops = h->arena + h->off_pop;
     const int n = (int)v.size();
     const int xm = h->args.xcd_map;
+    if (h->cover) return exchange_cover(pops, blocks, masks, items, n, xm, st);
     switch (h->storage) {
     case WLB_F64: return exchange_f64(pops, blocks, masks, items, n, xm, st);
     case WLB_F32: return exchange_f32(pops, blocks, masks, items, n, xm, st);
@@ -1245,6 +1248,33 @@ int wlb_force_get(wlb_blocks_t h, double out[8])
     HIPCHK(launch_reduce_sum8(partials, (int)h->tiles.size(), tot, h->stream));
     HIPCHK(hipMemcpyAsync(out, tot, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    return WLB_OK;
+}
+
+int wlb_debug_write_coverage(wlb_blocks_t h, int32_t odd, uint32_t *counts)
+{
+    if (!h || !counts) return fail(WLB_ERR_ARG, "null argument");
+    if (odd != 0 && odd != 1) return fail(WLB_ERR_ARG, "odd must be 0 or 1");
+    if (!h->inited) return fail(WLB_ERR_STATE, "wlb_lbm_init must come first");
+    if (h->storage != WLB_F32) return fail(WLB_ERR_UNSUPPORTED, "the write-coverage check runs on FP32 storage");
+    HIPCHK(hipMemsetAsync(h->arena + h->off_pop, 0, h->pop_bytes, h->stream));
+    h->inited = false;  // the populations now hold counters
+    h->cover = true;
+    const int rc = enqueue_step(h, odd != 0);
+    h->cover = false;
+    if (rc) return rc;
+    std::vector<uint32_t> raw(h->pop_bytes / sizeof(uint32_t));
+    HIPCHK(hipMemcpyAsync(raw.data(), h->arena + h->off_pop, h->pop_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int64_t nx = h->dom[0], ny = h->dom[1], N = nx * ny * h->dom[2];
+    std::fill(counts, counts + (int64_t)h->q * N, 0u);
+    for (const DevBlock &B : h->dev)
+        for (int i = 0; i < h->q; ++i)
+            for (int z = 0; z < B.n[2]; ++z)
+                for (int y = 0; y < B.n[1]; ++y)
+                    for (int x = 0; x < B.n[0]; ++x)
+                        counts[i * N + ((int64_t)(B.g[2] + z) * ny + B.g[1] + y) * nx + B.g[0] + x] =
+                            raw[B.pop + i * B.slot + (int64_t)(z + 1) * B.plane + (int64_t)(y + 1) * B.pitch + B.xoff + x];
     return WLB_OK;
 }
 

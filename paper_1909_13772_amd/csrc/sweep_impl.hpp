@@ -38,6 +38,12 @@ namespace wlb {
 struct bf16_t {
     uint16_t v;
 };
+// Write-coverage check: a 4-byte "storage" whose every population store adds
+// one to a counter in the population's place (loads read zero), so a sweep
+// run with it counts the writes each (cell, slot) receives.
+struct cover_t {
+    uint32_t v;
+};
 
 template <typename ST> struct Codec;
 
@@ -82,6 +88,12 @@ template <> struct Codec<_Float16> {
     static __device__ __forceinline__ T dec(Raw r) { return (float)__builtin_bit_cast(_Float16, r); }
     static __device__ __forceinline__ Raw enc(T v) { return __builtin_bit_cast(Raw, (_Float16)v); }
 };
+template <> struct Codec<cover_t> {
+    using T = float;
+    using Raw = uint32_t;
+    static __device__ __forceinline__ T dec(Raw) { return 0.0f; }
+    static __device__ __forceinline__ Raw enc(T) { return 0u; }
+};
 template <> struct Codec<bf16_t> {
     using T = float;
     using Raw = uint16_t;
@@ -102,7 +114,10 @@ template <typename ST, bool NT = true>
 __device__ __forceinline__ void stv(ST *p, typename Codec<ST>::T v)
 {
     using Raw = typename Codec<ST>::Raw;
-    mem_st<NT>(reinterpret_cast<Raw *>(p), Codec<ST>::enc(v));
+    if constexpr (std::is_same_v<ST, cover_t>)
+        atomicAdd(reinterpret_cast<uint32_t *>(p), 1u);
+    else
+        mem_st<NT>(reinterpret_cast<Raw *>(p), Codec<ST>::enc(v));
 }
 template <typename ST, bool NT = true>
 __device__ __forceinline__ typename Codec<ST>::Raw ldraw(const ST *p)
@@ -112,7 +127,10 @@ __device__ __forceinline__ typename Codec<ST>::Raw ldraw(const ST *p)
 template <typename ST, bool NT = true>
 __device__ __forceinline__ void straw(ST *p, typename Codec<ST>::Raw r)
 {
-    mem_st<NT>(reinterpret_cast<typename Codec<ST>::Raw *>(p), r);
+    if constexpr (std::is_same_v<ST, cover_t>)
+        atomicAdd(reinterpret_cast<uint32_t *>(p), 1u);
+    else
+        mem_st<NT>(reinterpret_cast<typename Codec<ST>::Raw *>(p), r);
 }
 
 // ---------------------------------------------------------------------------
@@ -1526,7 +1544,9 @@ __global__ __launch_bounds__(kWG) void pdfs_kernel(const SweepArgs a, double *bu
 // Ghost-layer exchange: bitwise copy of one population over a cell region
 // between two blocks (device-local copy without buffers, Sec. 3.3).
 // ---------------------------------------------------------------------------
-template <typename Raw>
+// ADD (write-coverage check): add the source counter to the target instead
+// of copying it.
+template <typename Raw, bool ADD = false>
 __global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBlock *blocks, const uint32_t *masks,
                                                        const XItem *items, int xcd_map)
 {
@@ -1545,7 +1565,10 @@ __global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBloc
     }
     const Raw *src = arena + S.pop + (int64_t)it.slot * S.slot + cell_off(S, it.s0[0] + rx, it.s0[1] + ry, it.s0[2] + rz);
     Raw *dst = arena + D.pop + (int64_t)it.slot * D.slot + cell_off(D, dx, dy, dz);
-    mem_st<true>(dst, mem_ld<true>(src));
+    if constexpr (ADD)
+        atomicAdd(dst, *src);
+    else
+        mem_st<true>(dst, mem_ld<true>(src));
 }
 
 // ---------------------------------------------------------------------------
@@ -1765,7 +1788,8 @@ hipError_t WLB_CAT(exchange_, WLB_SUFFIX)(void *arena, const DevBlock *blocks, c
 {
     if (nitems <= 0) return hipSuccess;
     using Raw = typename Codec<WLB_STORAGE>::Raw;
-    hipLaunchKernelGGL((exchange_kernel<Raw>), dim3(nitems), dim3(kWG), 0, st, reinterpret_cast<Raw *>(arena),
+    constexpr bool add = std::is_same_v<WLB_STORAGE, cover_t>;
+    hipLaunchKernelGGL((exchange_kernel<Raw, add>), dim3(nitems), dim3(kWG), 0, st, reinterpret_cast<Raw *>(arena),
                        blocks, masks, items, xcd_map);
     return hipGetLastError();
 }

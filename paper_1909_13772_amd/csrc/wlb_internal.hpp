@@ -115,6 +115,7 @@ WLB_DECLARE_LAUNCHERS(f64)
 WLB_DECLARE_LAUNCHERS(f32)
 WLB_DECLARE_LAUNCHERS(f16)
 WLB_DECLARE_LAUNCHERS(bf16)
+WLB_DECLARE_LAUNCHERS(cover)  // write-coverage check (4-byte counters in the FP32 layout)
 
 // Learned closure (mlp_train.hip).
 hipError_t launch_mlp_forward(const void *net, const float *raw, int64_t n, float *out, int32_t *flag, hipStream_t st);

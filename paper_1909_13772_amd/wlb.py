@@ -106,6 +106,7 @@ _sig = {
     "wlb_ghost_exchange": (C.c_int, [_h]),
     "wlb_moments_get": (C.c_int, [_h, _vp, _vp, _vp]),
     "wlb_force_get": (C.c_int, [_h, _vp]),
+    "wlb_debug_write_coverage": (C.c_int, [_h, C.c_int32, _vp]),
     "wlb_pdfs_get": (C.c_int, [_h, _vp]),
     "wlb_pdfs_set": (C.c_int, [_h, _vp]),
     "wlb_info": (C.c_int, [_h, C.POINTER(wlb_info_t)]),
@@ -188,6 +189,10 @@ def wlb_moments_get(h, rho, u, totals):
 
 def wlb_force_get(h, out):
     _check(_lib.wlb_force_get(h, _ptr(out)))
+
+
+def wlb_debug_write_coverage(h, odd, counts):
+    _check(_lib.wlb_debug_write_coverage(h, int(odd), _ptr(counts)))
 
 
 def wlb_pdfs_get(h, d):
@@ -347,6 +352,13 @@ class Blocks:
         out = np.zeros(8)
         wlb_force_get(self.h, out)
         return out
+
+    def write_coverage(self, odd):
+        """Writes per (slot, cell) of one sweep of parity `odd` and its
+        exchange, as uint32 [q][N]; the state is gone afterwards (init again)."""
+        counts = np.zeros((self.stencil, self.ncells), np.uint32)
+        wlb_debug_write_coverage(self.h, odd, counts)
+        return counts
 
     def moments(self, fields=True):
         nx, ny, nz = self.domain
