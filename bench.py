@@ -192,6 +192,32 @@ def copy_probe(wlb):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def host_io_probe(wlb, inputs, steps, ms_per_step):
+    """Host-buffer hand-over of the headline configuration: wlb_lbm_init from
+    host rho / u (upload plus initialisation, no autotuner) and
+    wlb_moments_get of rho / u to host, each timed as the best of two, and
+    the whole-job rate of `steps` steps including both transfers."""
+    shape = (N, N, N)
+    rho, u = inputs.uniform_state(shape)
+    p = wlb.make_params(tau=TAU, magic=MAGIC, force=(FX, 0.0, 0.0))
+    B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=19, storage=wlb.F64)
+    try:
+        t_init = t_mom = float("inf")
+        for _ in range(2):
+            t0 = time.perf_counter()
+            B.init(wlb.TRT, p, rho, u)
+            B.synchronize()
+            t_init = min(t_init, time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            B.moments()
+            t_mom = min(t_mom, time.perf_counter() - t0)
+    finally:
+        B.close()
+    job = t_init + steps * ms_per_step * 1e-3 + t_mom
+    return {"init_s": round(t_init, 4), "moments_s": round(t_mom, 4), "steps": steps,
+            "mlups_including_host_io": round(N ** 3 * steps / job / 1e6, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +293,11 @@ def main():
     except Exception as e:  # the probe is context only
         print(f"[bench] copy probe failed: {e}", file=sys.stderr)
         copy_gbs = None
+    try:
+        host_io = host_io_probe(wlb, inputs, args.steps, head["ms_per_step"])
+    except Exception as e:  # context only
+        print(f"[bench] host I/O probe failed: {e}", file=sys.stderr)
+        host_io = None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
     traffic = load_traffic("f64", "lds-staged" if res["lds_staging"] else "direct")
     out = {
@@ -299,6 +330,7 @@ def main():
         "variants": variants,
         "exchange_ms_per_step": round(head["exchange_ms"], 5),
         "copy_probe_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+        "host_io": host_io,
         "check": {"poiseuille_rel_err": res.get("poiseuille_err"), "mass_rel_drift": res.get("mass_drift")},
     }
     print(json.dumps(out))
