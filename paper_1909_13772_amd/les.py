@@ -311,7 +311,7 @@ def energy_error(run, ref):
 
 def calibrate(wlb, torch, params, seeds, n, factor, steps, snap, tau_f=TAU_F,
               gains=(0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0), cs_values=(0.06, 0.08, 0.1, 0.13, 0.16, 0.2, 0.25)):
-    """A-posteriori calibration with the fine solver as judge: on held-out
+    """A-posteriori calibration against the fine solver: on held-out
     seeds, pick the gain g of the network's correction (applied as
     b3 += ln g, which scales softplus(o) by g wherever the correction is
     small, as it is here) and, for a fair comparison, the Smagorinsky
@@ -447,7 +447,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--augment", type=int, default=3, help="phase train: symmetry images per training pair")
     ap.add_argument("--calib-seeds", type=str, default="16-17", help="phase train: seeds of the a-posteriori calibration")
-    ap.add_argument("--out", type=str, default="gpurun_out/les")
+    ap.add_argument("--out", type=str, default="les_out")
     ap.add_argument("--phase", choices=["data", "train", "calib", "apost", "eval"], default="data")
     ap.add_argument("--iters", type=int, default=40, help="phase apost: SPSA iterations")
     ap.add_argument("--cs", type=float, default=0.055, help="phase apost: Smagorinsky constant compared against")
