@@ -236,7 +236,7 @@ def main():
     ap.add_argument("--tau", type=float, default=0.5005, help="relaxation time of the turbulence workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (blocks would shard over GPUs "
+        print("bench.py measures one GPU: the library has no multi-GPU path (blocks would shard over GPUs "
               "by exchanging face slabs; not built).", file=sys.stderr)
         sys.exit(2)
     import torch
