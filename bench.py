@@ -230,7 +230,7 @@ def main():
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
     ap.add_argument("--lds-staging", type=int, choices=[0, 1], default=None,
                     help="with --no-autotune: odd sweep staged in LDS (1) or direct (0) for the headline run")
-    ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic"],
+    ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic", "matrix"],
                     default="channel",
                     help="channel = the headline configuration; the others print their own JSON line")
     ap.add_argument("--tau", type=float, default=0.5005, help="relaxation time of the turbulence workload")
@@ -253,6 +253,8 @@ def main():
             r = workloads.turbulence_precision(wlb, steps=args.steps, tau=args.tau)
         elif args.workload == "entropic":
             r = workloads.entropic_stability(wlb, steps=args.steps, tau=args.tau)
+        elif args.workload == "matrix":
+            r = workloads.matrix(wlb, steps=args.steps, warmup=args.warmup, params=closure_weights(inputs))
         else:
             r = workloads.closure_cost(wlb, steps=args.steps, warmup=args.warmup)
         print(json.dumps(r))

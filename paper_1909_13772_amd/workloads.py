@@ -219,6 +219,43 @@ def entropic_stability(wlb, n=384, steps=1000, every=100, seed=0, tau=0.5005, um
             "steps": steps, "every": every, "runs": out}
 
 
+def matrix(wlb, n=384, steps=200, warmup=10, params=None):
+    """The six forms on one shape: D3Q19 TRT (Lambda 3/16, tau 0.8) on the
+    decaying-turbulence state of an n^3 periodic box, FP64 / FP32 / FP16 /
+    BF16 deviation storage and FP32 with the Smagorinsky and MLP closures,
+    each autotuned; MLUPS, the sweep kernel's achieved bandwidth and roofline
+    fraction, and the velocity error against the FP64 run after `steps`."""
+    rho, u = inputs.turbulence_bandlimited(n, 0)
+    if params is None:
+        params = inputs.mlp_params(0, inv_std=[300.0] * 6 + [100.0], out_bias=-4.0)
+    forms = (("f64", wlb.F64, 8, wlb.CLOSURE_NONE), ("f32", wlb.F32, 4, wlb.CLOSURE_NONE),
+             ("f16dev", wlb.F16DEV, 2, wlb.CLOSURE_NONE), ("bf16dev", wlb.BF16DEV, 2, wlb.CLOSURE_NONE),
+             ("f32_smagorinsky", wlb.F32, 4, wlb.CLOSURE_SMAG), ("f32_mlp_closure", wlb.F32, 4, wlb.CLOSURE_MLP))
+    out, u64 = {}, None
+    for name, st, eb, cl in forms:
+        kw = dict(tau=0.8, magic=3 / 16, closure=cl, cs_smag=0.1, autotune=1)
+        if cl == wlb.CLOSURE_MLP:
+            kw["mlp"] = params
+        B = wlb.Blocks(wlb.single_block((n, n, n)), (n, n, n), (1, 1, 1), stencil=19, storage=st)
+        try:
+            B.init(wlb.TRT, wlb.make_params(**kw), rho, u)
+            secs, ms, cnt = _timed_steps(B, steps, warmup)
+            _, uu, _ = B.moments()
+        finally:
+            B.close()
+        uu = uu.reshape(3, -1)
+        if u64 is None:
+            u64 = uu
+        sweep_ms = (ms[0] + ms[1]) / max(1, cnt[0] + cnt[1])
+        bl = n ** 3 * 2 * 19 * eb
+        out[name] = {"mlups": n ** 3 * steps / secs / 1e6, "sweep_ms": sweep_ms,
+                     "achieved_gbs": bl / (sweep_ms * 1e-3) / 1e9,
+                     "roofline_frac": bl / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "u_rel_err_vs_f64": float(np.linalg.norm(uu - u64) / np.linalg.norm(u64))}
+    return {"workload": f"D3Q19 TRT decaying turbulence {n}^3, tau 0.8, every storage and closure",
+            "steps": steps, "warmup": warmup, "forms": out}
+
+
 def closure_cost(wlb, n=128, steps=500, warmup=10, params=None):
     """D3Q19 SRT FP32 on a periodic turbulent n^3 box with no closure,
     Smagorinsky and the MLP closure (tau0 = 0.5025, the coarse relaxation
