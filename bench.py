@@ -45,7 +45,7 @@ def sweep_source_hash() -> str:
 def load_traffic(storage_name: str, odd_sweep: str):
     """HBM bytes per sweep launch from a committed rocprofv3 counter summary,
     only if it was taken on the current sweep source with the same odd-sweep
-    kernel."""
+    kernel and non-temporal choices."""
     path = os.path.join(ROOT, "profiles", "sweep_channel256_traffic.json")
     if not os.path.exists(path):
         return None
@@ -76,7 +76,8 @@ def poiseuille_series(H, nu, g, T, s):
     return u
 
 
-def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True, q=19, coll=None, lds=None):
+def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True, q=19, coll=None, lds=None,
+               nt=None):
     import numpy as np
     import torch
 
@@ -92,6 +93,8 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
         B.init(wlb.TRT if coll is None else coll, p, rho, u)
         if lds is not None:  # fixed odd-sweep choice (profiler runs without the autotuner)
             B.set_lds_staging(bool(lds))
+        if nt is not None:  # fixed non-temporal choice per parity (profiler runs)
+            B.set_nontemporal(*nt)
         B.step(warmup)
         B.synchronize()
         B.set_kernel_timing(True)
@@ -106,7 +109,8 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
         B.set_kernel_timing(False)
         info = B.info()
         res = {"seconds": t1 - t0, "kernel_ms": ms, "launches": cnt, "tile": list(info.tile), "grid": info.grid,
-               "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems, "lds_staging": int(info.lds_staging)}
+               "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems, "lds_staging": int(info.lds_staging),
+               "nt": [int(info.nt_even), int(info.nt_odd)]}
         if check:
             r, uu, tot = B.moments()
             nu = (TAU - 0.5) / 3
@@ -230,6 +234,8 @@ def main():
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
     ap.add_argument("--lds-staging", type=int, choices=[0, 1], default=None,
                     help="with --no-autotune: odd sweep staged in LDS (1) or direct (0) for the headline run")
+    ap.add_argument("--nontemporal", type=str, default=None,
+                    help="with --no-autotune: 'E,O' non-temporal accesses (1) or cached (0) in the even / odd sweep")
     ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic", "matrix"],
                     default="channel",
                     help="channel = the headline configuration; the others print their own JSON line")
@@ -260,7 +266,8 @@ def main():
         print(json.dumps(r))
         return
     res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True, autotune=not args.no_autotune,
-                     lds=args.lds_staging)
+                     lds=args.lds_staging,
+                     nt=None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")])
     head = summarize(res, wlb.F64, args.steps, 8)
     print(f"[bench] f64: {head['mlups']:.0f} MLUPS, sweep {head['sweep_ms']:.3f} ms, "
           f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
@@ -301,7 +308,8 @@ def main():
         print(f"[bench] host I/O probe failed: {e}", file=sys.stderr)
         host_io = None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
-    traffic = load_traffic("f64", "lds-staged" if res["lds_staging"] else "direct")
+    access = ("lds-staged" if res["lds_staging"] else "direct") + "; non-temporal even %d odd %d" % tuple(res["nt"])
+    traffic = load_traffic("f64", access)
     out = {
         "metric": "MLUPS + % HBM roofline: plain FP64 vs FP32/FP16-store vs learned closure",
         "value": round(head["mlups"], 1),
@@ -319,7 +327,8 @@ def main():
                                "bounce-back walls in y, periodic x/z, Guo force fx=1e-6, tau=0.8, from rest",
                    "cells": N ** 3, "stencil": "D3Q19", "collision": "TRT", "storage": "f64",
                    "tile": res["tile"], "grid": res["grid"],
-                   "odd_sweep": "lds-staged" if res["lds_staging"] else "direct"},
+                   "odd_sweep": "lds-staged" if res["lds_staging"] else "direct",
+                   "nontemporal": {"even": res["nt"][0], "odd": res["nt"][1]}},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["frac"], 4), "traffic": traffic,
                      "kernel": "sweep_kernel<19,TRT,double> (even AA sweep) and " +

@@ -233,6 +233,8 @@ typedef struct {
     size_t arena_bytes;
     size_t pop_bytes;       /* bytes of population storage incl. ghosts */
     int32_t overlap;        /* 1: sweeps split into interior and frontier, exchange overlapped */
+    int32_t nt_even;        /* 1: the even sweep's population accesses are non-temporal */
+    int32_t nt_odd;         /* 1: the odd sweep's population accesses are non-temporal */
 } wlb_info_t;
 int wlb_info(wlb_blocks_t h, wlb_info_t *out);
 
@@ -274,6 +276,16 @@ int wlb_set_lds_staging(wlb_blocks_t h, int32_t on);
  * autotuner tries it for the best tile configuration when blocks exchange.
  * Errors: WLB_ERR_ARG (null handle), WLB_ERR_HIP (stream creation). */
 int wlb_set_overlap(wlb_blocks_t h, int32_t on);
+
+/* Non-temporal hint (1, default) or ordinary cached accesses (0) for the
+ * population loads and stores of the even and of the odd sweep.  Streamed
+ * once per sweep, the populations usually gain from the hint; accesses one
+ * element off the row alignment, and short rows whose cache lines neighbouring
+ * waves share, can gain from the cache instead.  Results are bitwise identical
+ * either way.  The autotuner tries all four settings (with and without LDS
+ * staging) for the best tile configuration.
+ * Errors: WLB_ERR_ARG for a null handle. */
+int wlb_set_nontemporal(wlb_blocks_t h, int32_t even, int32_t odd);
 
 /* Use (1) or bypass (0) the captured HIP graph in wlb_lbm_step. */
 int wlb_set_graph(wlb_blocks_t h, int32_t on);

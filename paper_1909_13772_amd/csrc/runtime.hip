@@ -94,6 +94,7 @@ struct wlb_blocks {
     // stream while the interior runs on the bound stream (autotuner candidate)
     bool overlap = false;
     bool cover = false;   // sweeps and exchanges count writes (wlb_debug_write_coverage)
+    bool nt_even = true, nt_odd = true;  // non-temporal population accesses per parity (autotuner candidate)
     int nint_tiles = 0;   // interior box tiles come first in `tiles` when split
     int nint_ltiles = 0;  // interior fluid-cell tiles come first in `ltiles`
     bool tiles_split = false;
@@ -280,8 +281,10 @@ int launch_grid(const wlb_blocks *h)
     return h->grid;
 }
 
-hipError_t sweep_launch(const wlb_blocks *h, bool odd, const SweepArgs &a, int g, hipStream_t st)
+hipError_t sweep_launch(const wlb_blocks *h, bool odd, const SweepArgs &args, int g, hipStream_t st)
 {
+    SweepArgs a = args;
+    a.nt = (odd ? h->nt_odd : h->nt_even) ? 1 : 0;
     if (h->cover) return sweep_cover(h->q, h->collision, odd, a, g, st);
     switch (h->storage) {
     case WLB_F64: return sweep_f64(h->q, h->collision, odd, a, g, st);
@@ -628,6 +631,7 @@ int time_pairs(wlb_blocks *h, int reps, float *ms_out)
 int autotune(wlb_blocks *h)
 {
     h->overlap = false;  // candidates first without the overlap
+    h->nt_even = h->nt_odd = true;
     float best = 1e30f;
     int bs[3] = {0, 0, 0}, bg = 0;
     // repetitions scaled so each candidate runs ~ 2e8 cell updates at most
@@ -665,6 +669,34 @@ int autotune(wlb_blocks *h)
             }
         }
     }
+    // the best shape and grid once more with each choice of the non-temporal
+    // hint per parity, with and without LDS staging
+    bool bne = true, bno = true;
+    for (int lds = 0; lds <= 1; ++lds)
+        for (int v = 0; v < 4; ++v) {
+            const bool ne = (v & 1) == 0, no = (v & 2) == 0;
+            if (ne && no) continue;  // measured above
+            h->lds_stage = lds != 0;
+            h->nt_even = ne;
+            h->nt_odd = no;
+            int rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
+            if (rc) return rc;
+            if (lds && h->args.lds_stride == 0) continue;
+            float ms = 0.f;
+            rc = time_pairs(h, reps, &ms);
+            if (rc) return rc;
+            if (log)
+                fprintf(stderr, "[wlb autotune] tile %d,%d,%d grid %d lds %d nt %d,%d: %.4f ms per two steps\n", bs[0],
+                        bs[1], bs[2], bg, lds, ne ? 1 : 0, no ? 1 : 0, ms);
+            if (ms < best) {
+                best = ms;
+                blds = lds != 0;
+                bne = ne;
+                bno = no;
+            }
+        }
+    h->nt_even = bne;
+    h->nt_odd = bno;
     h->lds_stage = blds;
     h->overlap = false;
     int rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
@@ -1330,6 +1362,8 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
     o->grid = h->grid;
     o->lds_staging = h->args.lds_stride > 0 ? 1 : 0;
     o->overlap = split_sweeps(h) ? 1 : 0;
+    o->nt_even = h->nt_even ? 1 : 0;
+    o->nt_odd = h->nt_odd ? 1 : 0;
     o->n_xchg_items = (int32_t)h->pull.size();
     o->xchg_elems = h->xchg_elems;
     o->arena_bytes = h->arena_bytes;
@@ -1345,6 +1379,15 @@ int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t gr
     if (tx > 0 && (ty < 1 || tz < 1 || (int64_t)tx * ty * tz > kWG))
         return fail(WLB_ERR_ARG, "tile shape must have at most %d cells", kWG);
     return set_tiles(h, tx, ty, tz, grid);
+}
+
+int wlb_set_nontemporal(wlb_blocks_t h, int32_t even, int32_t odd)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    h->nt_even = even != 0;
+    h->nt_odd = odd != 0;
+    h->graph_valid = false;  // the captured launches hold the old arguments
+    return WLB_OK;
 }
 
 int wlb_set_lds_staging(wlb_blocks_t h, int32_t on)

@@ -906,7 +906,7 @@ __device__ __forceinline__ uint32_t xshift(const XOff &o)
 // natural (after an odd sweep / init) reads slot i of x; swapped (after an
 // even sweep) reads slot opp(i) of x - c_i, or slot i of x on bounce-back /
 // anti-bounce-back links.
-template <int Q, typename ST, bool SWAPPED>
+template <int Q, typename ST, bool SWAPPED, bool NT = true>
 __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, int y, int z,
                                        uint32_t special, typename Codec<ST>::T (&f)[Q])
 {
@@ -914,10 +914,10 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (!SWAPPED) {
-            f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), o.at));
+            f[i] = ldv<ST, NT>(at<ST>(slot_base<ST>(a, B, i), o.at));
         } else {
             const Alt<ST> p = alt_in<Q, ST, i>(a, B);
-            f[i] = ldv<ST>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
+            f[i] = ldv<ST, NT>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
                                                                       : xshift<-cx<Q>(i)>(o) + p.add_reg));
         }
     });
@@ -951,7 +951,7 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
 // Store the post-collision populations of a fluid cell: even sweep into
 // slot opp(i) of x; odd sweep into slot i of x + c_i, or slot opp(i) of x on
 // bounce-back / anti-bounce-back links.
-template <int Q, typename ST, bool ODD>
+template <int Q, typename ST, bool ODD, bool NT = true>
 __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, int y, int z,
                                         uint32_t special, const typename Codec<ST>::T (&f)[Q])
 {
@@ -959,10 +959,10 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (!ODD) {
-            stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i]);
+            stv<ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i]);
         } else {
             const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-            stv<ST>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg), f[i]);
+            stv<ST, NT>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg), f[i]);
         }
     });
     if constexpr (ODD) {
@@ -1045,7 +1045,9 @@ __device__ __forceinline__ void store_regular_out(const SweepArgs &a, const DevB
 #ifndef WLB_WAVES_PER_EU
 #define WLB_WAVES_PER_EU 1
 #endif
-template <int Q, int COLL, typename ST, bool ODD>
+// NT: the population accesses carry the non-temporal hint (the autotuner
+// chooses it per parity).
+template <int Q, int COLL, typename ST, bool ODD, bool NT>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_PER_EU, 8))) void sweep_kernel(
     const SweepArgs a)
 {
@@ -1063,7 +1065,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         const uint32_t off = cell_off(B, c.x, c.y, c.z);
         const uint32_t special = L.bb | L.alo | L.ahi;
         T f[Q];
-        gather<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f);
+        gather<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f);
         const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;
@@ -1073,7 +1075,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
             });
         }
-        scatter<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f);
+        scatter<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f);
     }
 }
 
@@ -1115,7 +1117,7 @@ __host__ __device__ constexpr size_t lds_stage_bytes(int stride)
 
 // RING: every tile is a whole row of a self-wrapping block (chosen on the
 // host), so the halo and out-of-segment paths are compiled out.
-template <int Q, int COLL, typename ST, bool RING>
+template <int Q, int COLL, typename ST, bool RING, bool NT>
 __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
 {
     using T = typename Codec<ST>::T;
@@ -1164,16 +1166,16 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                     constexpr int k = xshift_index<Q>(i);
                     const char *base = slot_base<ST>(a, B, opp(i)) -
                                        (int64_t)(cy<Q>(i) * B.pitch + cz<Q>(i) * B.plane) * (int64_t)sizeof(ST);
-                    buf[k * stride + rb] = ldraw<ST>(at<ST>(base, boff));
+                    buf[k * stride + rb] = ldraw<ST, NT>(at<ST>(base, boff));
                     if (!RING && !ring) {
                         if (cx<Q>(i) == 1 && lx == 0) buf[k * stride + rb - 1] = load_regular_in<Q, ST, i>(a, B, o, x, y, z);
                         if (cx<Q>(i) == -1 && lx == ex - 1)
                             buf[k * stride + rb + 1] = load_regular_in<Q, ST, i>(a, B, o, x, y, z);
                     }
-                    if ((special >> opp(i)) & 1u) f[i] = ldv<ST>(at<ST>(slot_base<ST>(a, B, i), boff));
+                    if ((special >> opp(i)) & 1u) f[i] = ldv<ST, NT>(at<ST>(slot_base<ST>(a, B, i), boff));
                 } else {
                     const Alt<ST> p = alt_in<Q, ST, i>(a, B);
-                    f[i] = ldv<ST>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+                    f[i] = ldv<ST, NT>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
                 }
             });
         }
@@ -1203,11 +1205,11 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                 const bool sp = (special >> i) & 1u;
                 if constexpr (cx<Q>(i) == 0) {
                     const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-                    stv<ST>(at<ST>(p.base, boff + (sp ? p.add_sp : p.add_reg)), f[i]);
+                    stv<ST, NT>(at<ST>(p.base, boff + (sp ? p.add_sp : p.add_reg)), f[i]);
                 } else {
                     constexpr int k = xshift_index<Q>(i);
                     if (sp) {
-                        stv<ST>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
+                        stv<ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
                     } else if (!RING && !ring && ((cx<Q>(i) == 1 && lx == ex - 1) || (cx<Q>(i) == -1 && lx == 0))) {
                         store_regular_out<Q, ST, i>(a, B, o, x, y, z, f[i]);  // target outside the segment
                     } else {
@@ -1230,7 +1232,7 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                     if (lw >= 0 && lw < ex && !((info[l - lx + lw] >> i) & 1u)) {
                         const char *base = slot_base<ST>(a, B, i) +
                                            (int64_t)(cy<Q>(i) * B.pitch + cz<Q>(i) * B.plane) * (int64_t)sizeof(ST);
-                        straw<ST>(at<ST>(base, boff), buf[k * stride + rb]);
+                        straw<ST, NT>(at<ST>(base, boff), buf[k * stride + rb]);
                     }
                 }
             });
@@ -1629,23 +1631,33 @@ __global__ __launch_bounds__(kWG) void force_kernel(const SweepArgs a, double *p
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int Q, int COLL>
-static hipError_t sweep_q(bool odd, const SweepArgs &a, int grid, hipStream_t st)
+template <int Q, int COLL, bool NT>
+static hipError_t sweep_qn(bool odd, const SweepArgs &a, int grid, hipStream_t st)
 {
     if (odd && a.lds_stride > 0) {
         using Raw = typename Codec<WLB_STORAGE>::Raw;
         const size_t bytes = lds_stage_bytes<Q, Raw>(a.lds_stride);
         if (a.lds_ring)
-            hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE, true>), dim3(grid), dim3(kWG), bytes, st, a);
+            hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE, true, NT>), dim3(grid), dim3(kWG), bytes, st,
+                               a);
         else
-            hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE, false>), dim3(grid), dim3(kWG), bytes, st, a);
+            hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE, false, NT>), dim3(grid), dim3(kWG), bytes, st,
+                               a);
         return hipGetLastError();
     }
     if (odd)
-        hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, true>), dim3(grid), dim3(kWG), 0, st, a);
+        hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, true, NT>), dim3(grid), dim3(kWG), 0, st, a);
     else
-        hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, false>), dim3(grid), dim3(kWG), 0, st, a);
+        hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, false, NT>), dim3(grid), dim3(kWG), 0, st, a);
     return hipGetLastError();
+}
+
+template <int Q, int COLL>
+static hipError_t sweep_q(bool odd, const SweepArgs &a, int grid, hipStream_t st)
+{
+    // the counting stores of the write-coverage check ignore the hint
+    if (a.nt || std::is_same_v<WLB_STORAGE, cover_t>) return sweep_qn<Q, COLL, true>(odd, a, grid, st);
+    return sweep_qn<Q, COLL, false>(odd, a, grid, st);
 }
 
 template <int COLL>

@@ -78,6 +78,7 @@ struct SweepArgs {
     int32_t lds_stride;    // > 0: odd sweep stages x-shifted populations in LDS rows of this many elements
     int32_t lds_ring;      // 1: every tile is a whole row of a self-wrapping block (staged sweep without halos)
     int32_t xcd_map;       // 1: one workgroup per tile, each XCD takes a contiguous range of tiles
+    int32_t nt;            // 1: the sweep's population accesses carry the non-temporal hint
     double omega;          // 1 / tau0
     double omega_minus;    // TRT rate of the antisymmetric part at tau0
     double magic;          // TRT Lambda

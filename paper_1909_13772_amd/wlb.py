@@ -79,6 +79,8 @@ class wlb_info_t(C.Structure):
         ("arena_bytes", C.c_size_t),
         ("pop_bytes", C.c_size_t),
         ("overlap", C.c_int32),
+        ("nt_even", C.c_int32),
+        ("nt_odd", C.c_int32),
     ]
 
 
@@ -113,6 +115,7 @@ _sig = {
     "wlb_set_tiles": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "wlb_set_graph": (C.c_int, [_h, C.c_int32]),
     "wlb_set_lds_staging": (C.c_int, [_h, C.c_int32]),
+    "wlb_set_nontemporal": (C.c_int, [_h, C.c_int32, C.c_int32]),
     "wlb_set_overlap": (C.c_int, [_h, C.c_int32]),
     "wlb_set_kernel_timing": (C.c_int, [_h, C.c_int32]),
     "wlb_kernel_times": (C.c_int, [_h, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -390,6 +393,9 @@ class Blocks:
 
     def set_lds_staging(self, on):
         wlb_set_lds_staging(self.h, on)
+
+    def set_nontemporal(self, even, odd):
+        _check(_lib.wlb_set_nontemporal(self.h, int(bool(even)), int(bool(odd))))
 
     def set_overlap(self, on):
         wlb_set_overlap(self.h, on)

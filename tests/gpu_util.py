@@ -14,7 +14,7 @@ def say(msg):
 
 
 def gpu_run(blocks, domain, periodic, q, storage, coll, params, rho, u, solid=None, steps=0, tiles=None,
-            graph=True, mode="step", lds=False, overlap=False):
+            graph=True, mode="step", lds=False, overlap=False, nt=None):
     """Returns (d[q][N] natural-layout deviations, rho, u, totals, Blocks)."""
     from paper_1909_13772_amd import wlb
     B = wlb.Blocks(blocks, domain, periodic, stencil=q, storage=storage)
@@ -25,6 +25,8 @@ def gpu_run(blocks, domain, periodic, q, storage, coll, params, rho, u, solid=No
     B.set_lds_staging(lds)
     if overlap:
         B.set_overlap(True)
+    if nt is not None:
+        B.set_nontemporal(*nt)
     if mode == "step":
         B.step(steps)
     else:

@@ -131,6 +131,18 @@ def test_porous_uneven_blocks_lds_staged_odd_sweep_fp64(q, coll):
     _compare(f"porous lds q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
 
 
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+@pytest.mark.parametrize("nt,lds", [((0, 0), False), ((0, 0), True), ((1, 0), False)])
+def test_porous_uneven_blocks_cached_accesses_fp64(q, coll, nt, lds):
+    """The porous case with ordinary (cached) instead of non-temporal
+    population accesses in one or both sweeps."""
+    say(f"case porous nt{nt} lds{lds} q{q} coll{coll}")
+    gpu, orc, solid, dom = _porous_case(q, coll, wlb.F64, 11, nt=nt, lds=lds)
+    i = gpu[4].info()
+    assert (i.nt_even, i.nt_odd) == nt
+    _compare(f"porous nt{nt} q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
+
+
 @pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (9, 1), (15, 1)])
 def test_porous_uneven_blocks_overlapped_exchange_fp64(q, coll):
     """The porous case with each sweep split into interior and frontier and
@@ -351,7 +363,10 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
             dict(overlap=True), dict(overlap=True, graph=False), dict(overlap=True, mode="split"),
             dict(overlap=True, tiles=(16, 4, 4, -1)), dict(overlap=True, tiles=(64, 4, 1, 7)),
             dict(overlap=True, tiles=(-1, 0, 0, 0)), dict(overlap=True, tiles=(-1, 0, 0, -1), graph=False),
-            dict(overlap=True, lds=True)]
+            dict(overlap=True, lds=True),
+            # cached instead of non-temporal population accesses
+            dict(nt=(0, 0)), dict(nt=(1, 0), lds=True), dict(nt=(0, 1), tiles=(-1, 0, 0, 0)),
+            dict(nt=(0, 0), overlap=True)]
     ref = None
     for kw in runs:
         d, r, uu, tot, B = gpu_run(blocks, dom, (1, 1, 0), 19, wlb.F32, wlb.TRT, p, rho, u, solid, steps=13, **kw)
