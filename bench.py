@@ -235,7 +235,8 @@ def main():
     ap.add_argument("--lds-staging", type=int, choices=[0, 1], default=None,
                     help="with --no-autotune: odd sweep staged in LDS (1) or direct (0) for the headline run")
     ap.add_argument("--nontemporal", type=str, default=None,
-                    help="with --no-autotune: 'E,O' non-temporal accesses (1) or cached (0) in the even / odd sweep")
+                    help="with --no-autotune: 'E,O' non-temporal accesses (1) or cached (0) in the even / odd sweep "
+                         "(headline and variant runs)")
     ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic", "matrix"],
                     default="channel",
                     help="channel = the headline configuration; the others print their own JSON line")
@@ -265,9 +266,10 @@ def main():
             r = workloads.closure_cost(wlb, steps=args.steps, warmup=args.warmup)
         print(json.dumps(r))
         return
+    head_nt = None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")]
     res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True, autotune=not args.no_autotune,
                      lds=args.lds_staging,
-                     nt=None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")])
+                     nt=head_nt)
     head = summarize(res, wlb.F64, args.steps, 8)
     print(f"[bench] f64: {head['mlups']:.0f} MLUPS, sweep {head['sweep_ms']:.3f} ms, "
           f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
@@ -287,7 +289,7 @@ def main():
                                           ("f32_d3q15", wlb.F32, 4, 0, 15, None),
                                           ("f32_d2q9_planes", wlb.F32, 4, 0, 9, None)):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
-                           q=q, coll=coll, check=True)
+                           q=q, coll=coll, check=True, nt=head_nt if args.no_autotune else None)
             sm = summarize(r, st, args.variant_steps, eb, q=q)
             variants[name] = {"mlups": round(sm["mlups"], 1), "roofline_frac": round(sm["frac"], 4),
                               "achieved_gbs": round(sm["achieved_gbs"], 1), "sweep_ms": round(sm["sweep_ms"], 4),
