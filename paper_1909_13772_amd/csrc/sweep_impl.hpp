@@ -103,21 +103,149 @@ template <> struct Codec<bf16_t> {
     static __device__ __forceinline__ Raw enc(T v) { return __builtin_bit_cast(Raw, (__bf16)v); }
 };
 
-// Typed loads / stores through the codec.
-template <typename ST, bool NT = true>
-__device__ __forceinline__ typename Codec<ST>::T ldv(const ST *p)
+// FP16 deviations are stored multiplied by a power of two per weight class
+// (the same for slot i and its opposite, which the AA pattern exchanges):
+// the largest S with 16 w_i S <= 65504, so |d_i| up to 16 w_i stays finite
+// and deviations down to 2^-14 / S (about 5e-10 for the smallest weights)
+// stay normal instead of losing their low bits as subnormals.  Scaling by a
+// power of two is exact both ways.  Other storage types use no scale.
+template <int Q>
+__host__ __device__ constexpr float f16_scale(int i)
+{
+    const double lim = 65504.0 * (double)wden<Q>() / (16.0 * (double)wnum<Q>(i));
+    double s = 1.0;
+    while (s * 2.0 <= lim) s *= 2.0;
+    return (float)s;
+}
+
+// Decode / encode one population of slot class i (round to nearest even).
+template <int Q, typename ST>
+__device__ __forceinline__ typename Codec<ST>::T dec_slot(typename Codec<ST>::Raw r, int i)
+{
+    if constexpr (std::is_same_v<ST, _Float16>)
+        return Codec<ST>::dec(r) * (1.0f / f16_scale<Q>(i));
+    else
+        return Codec<ST>::dec(r);
+}
+template <int Q, typename ST>
+__device__ __forceinline__ typename Codec<ST>::Raw enc_slot(typename Codec<ST>::T v, int i)
+{
+    if constexpr (std::is_same_v<ST, _Float16>)
+        return Codec<ST>::enc(v * f16_scale<Q>(i));
+    else
+        return Codec<ST>::enc(v);
+}
+
+// Stochastic rounding of the 16-bit stores: the value goes to one of its
+// two neighbours in the storage format with probabilities that make the
+// stored value's expectation the value itself (rnd: 32 uniform bits).  A
+// population changes by a nearly constant amount per step while it stays in
+// one binade (a body force, a slowly growing flow), so rounding to nearest
+// would commit the same error every step and the state would drift by up to
+// half an ulp per step; the unbiased rounding turns that drift into a random
+// walk.  FP16: the dither is added to the 13 float bits below the half
+// precision's mantissa and cut off, which is exact in the normal range of
+// half precision (|v S| >= 2^-14); below it the conversion then rounds to
+// nearest.  BF16: the dither is added to the 16 bits that the conversion
+// drops.  Infinities and NaN stay what they are.  FP32 and FP64 round to
+// nearest.
+template <int Q, typename ST>
+__device__ __forceinline__ typename Codec<ST>::Raw enc_slot_sr(typename Codec<ST>::T v, int i, uint32_t rnd)
+{
+    if constexpr (std::is_same_v<ST, _Float16>) {
+        const uint32_t b = __float_as_uint(v * f16_scale<Q>(i));
+        const uint32_t t = ((b & 0x7fffffffu) + (rnd >> 19)) & ~0x1fffu;
+        return Codec<ST>::enc(__uint_as_float(t | (b & 0x80000000u)));
+    } else if constexpr (std::is_same_v<ST, bf16_t>) {
+        const uint32_t b = __float_as_uint(v);
+        if ((b & 0x7f800000u) == 0x7f800000u) return Codec<ST>::enc(v);
+        return (uint16_t)((b + (rnd >> 16)) >> 16);
+    } else {
+        return Codec<ST>::enc(v);
+    }
+}
+template <typename ST>
+constexpr bool kStochastic = std::is_same_v<ST, _Float16> || std::is_same_v<ST, bf16_t>;
+// Type in which a collision accumulates each new population before it is
+// rounded for storage: FP64 for FP32 storage (a final FP32 rounding of the
+// same sum would be the only rounding), the compute type otherwise.
+template <typename ST>
+using AccOf = std::conditional_t<std::is_same_v<ST, float>, double, typename Codec<ST>::T>;
+
+// Random bits of a cell for the stochastic rounding of its stores: a hash
+// of the cell's incoming populations (which change every step) and its
+// global index, so that the rounding is reproducible and the same whatever
+// the tiles, blocks, launch order or kernel variant.  Per population the
+// bits are mixed once more with the population's index.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+template <int Q, typename T>
+__device__ __forceinline__ uint32_t state_hash(const T (&f)[Q], uint32_t gcell)
+{
+    uint32_t h = gcell * 0x9e3779b1u;
+    if constexpr (sizeof(T) == 4) {
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            h += __builtin_rotateleft32(__float_as_uint((float)f[i]), (7 * i) & 31);
+        });
+    }
+    return mix32(h);
+}
+__device__ __forceinline__ uint32_t pop_bits(uint32_t h, int i)
+{
+    return (h ^ (0x9e3779b9u * (uint32_t)(i + 1))) * 0x85ebca6bu;
+}
+
+// Raw bits of a collision result for storage (stochastic rounding for
+// 16-bit storage).
+template <int Q, typename ST>
+__device__ __forceinline__ typename Codec<ST>::Raw enc_result(typename Codec<ST>::T v, int i, uint32_t h)
+{
+    if constexpr (kStochastic<ST>)
+        return enc_slot_sr<Q, ST>(v, i, pop_bits(h, i));
+    else
+        return enc_slot<Q, ST>(v, i);
+}
+// Global cell index (x fastest) that seeds the rounding hash.
+__device__ __forceinline__ uint32_t global_cell(const SweepArgs &a, const DevBlock &B, int x, int y, int z)
+{
+    return (uint32_t)(B.g[0] + x) + (uint32_t)a.dom[0] * ((uint32_t)(B.g[1] + y) + (uint32_t)a.dom[1] * (uint32_t)(B.g[2] + z));
+}
+
+// Typed loads / stores of one population of slot class i through the codec.
+template <int Q, typename ST, bool NT = true>
+__device__ __forceinline__ typename Codec<ST>::T ldv(const ST *p, int i)
 {
     using Raw = typename Codec<ST>::Raw;
-    return Codec<ST>::dec(mem_ld<NT>(reinterpret_cast<const Raw *>(p)));
+    return dec_slot<Q, ST>(mem_ld<NT>(reinterpret_cast<const Raw *>(p)), i);
 }
-template <typename ST, bool NT = true>
-__device__ __forceinline__ void stv(ST *p, typename Codec<ST>::T v)
+template <int Q, typename ST, bool NT = true>
+__device__ __forceinline__ void stv(ST *p, typename Codec<ST>::T v, int i)
 {
     using Raw = typename Codec<ST>::Raw;
     if constexpr (std::is_same_v<ST, cover_t>)
         atomicAdd(reinterpret_cast<uint32_t *>(p), 1u);
     else
-        mem_st<NT>(reinterpret_cast<Raw *>(p), Codec<ST>::enc(v));
+        mem_st<NT>(reinterpret_cast<Raw *>(p), enc_slot<Q, ST>(v, i));
+}
+// Store of a collision result (stochastic rounding for 16-bit storage).
+template <int Q, typename ST, bool NT = true>
+__device__ __forceinline__ void stv_sr(ST *p, typename Codec<ST>::T v, int i, uint32_t h)
+{
+    using Raw = typename Codec<ST>::Raw;
+    if constexpr (std::is_same_v<ST, cover_t>)
+        atomicAdd(reinterpret_cast<uint32_t *>(p), 1u);
+    else if constexpr (kStochastic<ST>)
+        mem_st<NT>(reinterpret_cast<Raw *>(p), enc_slot_sr<Q, ST>(v, i, pop_bits(h, i)));
+    else
+        mem_st<NT>(reinterpret_cast<Raw *>(p), enc_slot<Q, ST>(v, i));
 }
 template <typename ST, bool NT = true>
 __device__ __forceinline__ typename Codec<ST>::Raw ldraw(const ST *p)
@@ -140,6 +268,7 @@ __device__ __forceinline__ void straw(ST *p, typename Codec<ST>::Raw r)
 template <int Q, typename T>
 struct Macro {
     T drho, rho, u[3], uu;
+    T j[3];  // sum c d (without the force half-step)
 };
 
 // 1/x: exact division in FP64; the hardware reciprocal (1 ulp) in FP32,
@@ -162,6 +291,9 @@ __device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
         if constexpr (cz<Q>(i) == -1) jz -= d[i];
     });
     Macro<Q, T> m;
+    m.j[0] = jx;
+    m.j[1] = jy;
+    m.j[2] = jz;
     m.drho = drho;
     m.rho = T(1) + drho;
     const T inv = recip(m.rho);
@@ -335,7 +467,7 @@ __device__ __forceinline__ T source_moment(const MomentSources<T> &s)
 // the stationary point of the quadratic entropy of the post-collision state
 // (gamma = 2 when dh vanishes).  ds and dh are taken back to populations by
 // the inverse transform for the two entropic products.
-template <int Q, typename T, bool KBC = false>
+template <int Q, typename T, bool KBC = false, typename A = T>
 __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omb, T omh,
                                             int closure, T tau0, T smag_k)
 {
@@ -431,9 +563,11 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
     tvalues<2>(g);
     tvalues<1>(g);
     tvalues<0>(g);
+    // the change g contains the force, a nearly constant amount per step:
+    // subtracted in A (FP64 for FP32 storage) and rounded once
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        d[i] -= g[tpos<Q>(i)];
+        d[i] = T(A(d[i]) - A(g[tpos<Q>(i)]));
     });
 }
 
@@ -631,34 +765,113 @@ __device__ __forceinline__ void pi_pairs(const T (&d)[Q], const Macro<Q, T> &m, 
     });
 }
 
-// SRT / TRT relaxation evaluated pair by pair (i, opp(i)).  With the pair
-// parts d+- = (d_i +- d_opp) / 2 the update is
-//   d_i += r+ + r-,  d_opp += r+ - r-,  r+- = -omega+- (d+- - e+-) + (1 - omega+-/2) F+-,
-//   e+ = w (A + 9/2 rho cu^2),  e- = 3 w rho cu,  A = drho - 3/2 rho uu,
-//   F+ = w (9 cu cF - 3 u.F),   F- = 3 w cF.
-// The source parts are gathered into per-cell vectors so that a pair costs
-// three dot products with c (a few adds) and a handful of FMAs:
-//   omega+ e+ + (1 - omega+/2) F+ = w (K + cu c.V),  K = omega+ A - 3 (1 - omega+/2) u.F,
-//                                                    V = 9/2 omega+ rho u + 9 (1 - omega+/2) F,
-//   omega- e- + (1 - omega-/2) F- = w c.W,           W = 3 omega- rho u + 3 (1 - omega-/2) F,
-// and d_i' = alpha d_i + beta d_opp + z+ + z-, alpha = 1 - (omega+ + omega-)/2,
-// beta = (omega- - omega+)/2 (zero for SRT).  Only the populations stay live.
-template <int Q, typename T, bool SRT = false>
+// Antisymmetric pair constants t_i ~ 3 w_i of the SRT / TRT update, as
+// values of the compute type T whose lattice sum sum_i t_i c_ia c_ib = delta_ab
+// holds exactly (no rounding): with the textbook weights rounded to T that
+// sum misses 1 by about one ulp, and the collision then multiplies the
+// momentum by 1 + omega- eps every step (a drift of 1e-4 over 2000 steps in
+// FP32 for a flow that is only accelerated).  Every class but the faces is
+// rounded to a multiple of U = ulp(t_face) / 4 (twice that where its count
+// along an axis is not a multiple of 8, and never finer than its own ulp in
+// T), and t_face takes what the identity
+// leaves, 1 - sum, which is then a multiple of ulp(t_face): exact.  The
+// symmetric part keeps the plain weights (their rounding only perturbs the
+// mass, by omega+ eps A per step, A = drho - 3/2 rho u.u).
+template <int Q>
+__host__ __device__ constexpr int n_xclass(int c2v)
+{
+    int n = 0;
+    for (int i = 0; i < Q; ++i) n += (c2<Q>(i) == c2v && cx<Q>(i) != 0);
+    return n;
+}
+template <int Q>
+__host__ __device__ constexpr int first_of_class(int c2v)
+{
+    for (int i = 0; i < Q; ++i)
+        if (c2<Q>(i) == c2v) return i;
+    return 0;
+}
+template <int Q, typename T>
+__host__ __device__ constexpr T pair_t(int i)
+{
+    constexpr int P = sizeof(T) == 8 ? 53 : 24;
+    const double tf = 3.0 * (double)wnum<Q>(1) / (double)wden<Q>();
+    double g = 1.0;  // 2^floor(log2 tf)
+    while (g > tf) g *= 0.5;
+    while (g * 2.0 <= tf) g *= 2.0;
+    for (int k = 1; k < P; ++k) g *= 0.5;  // ulp(tf)
+    long long inv_u = 4;  // 1 / U in powers of two: U = g / 4
+    for (double x = g; x < 1.0; x *= 2.0) inv_u *= 2;
+    const double U = 1.0 / (double)inv_u;
+    long long rest = inv_u;  // 1 / U - sum over non-face classes of count * n
+    long long ni = 0;
+    for (int k = 2; k <= 3; ++k) {
+        const int cnt = n_xclass<Q>(k);
+        if (cnt == 0) continue;
+        const double tk = 3.0 * (double)wnum<Q>(first_of_class<Q>(k)) / (double)wden<Q>();
+        long long step = (cnt % 8 == 0) ? 1 : 2;
+        double uk = 1.0;  // ulp(tk): the multiple must also be a value of T
+        while (uk > tk) uk *= 0.5;
+        for (int b = 1; b < P; ++b) uk *= 0.5;
+        while ((double)step * U < uk) step *= 2;
+        const long long nk = (long long)(tk / U / (double)step + 0.5) * step;
+        rest -= (long long)cnt * nk;
+        if (c2<Q>(i) == k) ni = nk;
+    }
+    if (c2<Q>(i) == 1) ni = rest / 2;
+    if (c2<Q>(i) == 0) ni = 0;
+    return (T)((double)ni * U);
+}
+
+template <int Q, typename T>
+__host__ __device__ constexpr bool pair_t_exact()
+{
+    // summed in integer units of 2^-60 (every t_i is a multiple of 2^-58 or
+    // coarser), so the check itself does not round
+    long long s = 0;
+    double unit = 1.0;
+    for (int k = 0; k < 60; ++k) unit *= 2.0;
+    for (int i = 0; i < Q; ++i) s += (long long)((double)pair_t<Q, T>(i) * unit) * (cx<Q>(i) * cx<Q>(i));
+    return s == (long long)unit;
+}
+static_assert(pair_t_exact<19, float>() && pair_t_exact<27, float>() && pair_t_exact<15, float>() &&
+                  pair_t_exact<9, float>() && pair_t_exact<19, double>() && pair_t_exact<27, double>() &&
+                  pair_t_exact<15, double>() && pair_t_exact<9, double>(),
+              "pair constants must sum exactly to the identity");
+
+// SRT / TRT relaxation evaluated pair by pair (i, opp(i)) on the pair parts
+// s = d_i + d_opp and a = d_i - d_opp:
+//   s' = (1 - omega+) s + 2 z+,  a' = (1 - omega-) a + 2 z-,
+//   d_i' = (s' + a')/2,  d_opp' = (s' - a')/2,
+//   z+ = omega+ e+ + (1 - omega+/2) F+ = w (K + cu c.V),
+//        K = omega+ A - 3 (1 - omega+/2) u.F,  V = 9/2 omega+ rho u + 9 (1 - omega+/2) F,
+//        e+ = w (A + 9/2 rho cu^2),  A = drho - 3/2 rho u.u,  F+ = w (9 cu cF - 3 u.F),
+//   z- = omega- e- + (1 - omega-/2) F- = t (omega- c.j + c.F),
+//        e- = 3 w c.(rho u) = 3 w c.(j + F/2),  F- = 3 w c.F,  t = 3 w,
+// where j = sum c d is the momentum without the half force, so that the
+// constant force never enters a sum with the much larger momentum in the
+// compute type (rounding j + F/2 to FP32 would round the same way every step
+// while j grows by F).  Each new population is accumulated in A (FP64 for
+// FP32 storage, the storage's compute type otherwise) from the pair parts
+// and the force part t c.F and rounded once: with t_i summing exactly to the
+// identity (pair_t) the momentum then changes by exactly F per step up to
+// one rounding per population.
+template <int Q, typename T, bool SRT = false, typename A = T>
 __device__ __forceinline__ void relax_pairs(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omm)
 {
-    const T fop = T(1) - T(0.5) * om, fom = T(1) - T(0.5) * omm;
-    const T A = m.drho - T(1.5) * m.rho * m.uu;
+    const T fop = T(1) - T(0.5) * om;
+    const T A0 = m.drho - T(1.5) * m.rho * m.uu;
     const T uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
-    const T K = om * A - T(3) * fop * uF;
-    const T kv = T(4.5) * om * m.rho, kw = T(3) * omm * m.rho;
-    const T fv = T(9) * fop, fw = T(3) * fom;
-    T V[3], W[3];
+    const T K = om * A0 - T(3) * fop * uF;
+    const T kv = T(4.5) * om * m.rho, fv = T(9) * fop;
+    T V[3], J[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         V[k] = kv * m.u[k] + fv * F[k];
-        W[k] = kw * m.u[k] + fw * F[k];
+        J[k] = (SRT ? om : omm) * m.j[k];
     }
-    const T al = T(1) - T(0.5) * (om + omm), be = T(0.5) * (omm - om);
+    // (1 - omega)/2, exact for omega in [1/2, 2]
+    const A hp = A(T(0.5) - T(0.5) * om), hm = SRT ? hp : A(T(0.5) - T(0.5) * omm);
     {
         constexpr T w0 = weight<Q, T>(0);
         d[0] = (T(1) - om) * d[0] + w0 * K;
@@ -666,22 +879,19 @@ __device__ __forceinline__ void relax_pairs(T (&d)[Q], const Macro<Q, T> &m, con
     sfor<(Q - 1) / 2>([&](auto I) {
         constexpr int i = 2 * decltype(I)::value + 1, o = i + 1;
         constexpr T w = weight<Q, T>(i);
+        constexpr T t = pair_t<Q, T>(i);
         const T cu = cdot<Q, i>(m.u);
         const T zp = w * (K + cu * cdot<Q, i>(V));
-        const T zm = w * cdot<Q, i>(W);
-        const T di = d[i], dd = d[o];
-        if constexpr (SRT) {
-            d[i] = al * di + (zp + zm);
-            d[o] = al * dd + (zp - zm);
-        } else {
-            d[i] = al * di + be * dd + (zp + zm);
-            d[o] = al * dd + be * di + (zp - zm);
-        }
+        const T zj = t * cdot<Q, i>(J);
+        const A sh = hp * A(d[i] + d[o]) + A(zp);
+        const A ah = hm * A(d[i] - d[o]) + A(zj) + A(t) * A(cdot<Q, i>(F));
+        d[i] = T(sh + ah);
+        d[o] = T(sh - ah);
     });
 }
 
 // Collide one cell in place.  Returns the macroscopic state used.
-template <int Q, int COLL, typename T>
+template <int Q, int COLL, typename T, typename A = T>
 __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p)
 {
     const Macro<Q, T> m = moments_of<Q, T>(d, p.F);
@@ -694,7 +904,7 @@ __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p
         }
         cumulant_collide<Q, T>(d, m, p.F, om, p.omb);
     } else if constexpr (COLL == 2 || COLL == 3) {
-        mrt_collide<Q, T, COLL == 3>(d, m, p.F, om, p.omb, p.omh, p.closure, p.tau0, p.smag_k);
+        mrt_collide<Q, T, COLL == 3, A>(d, m, p.F, om, p.omb, p.omh, p.closure, p.tau0, p.smag_k);
     } else {
         if (p.closure == 1) {
             T P[6];
@@ -704,7 +914,7 @@ __device__ __forceinline__ Macro<Q, T> collide(T (&d)[Q], const CollParams<T> &p
             omm = recip(T(0.5) + p.magic * recip(tau - T(0.5)));
         }
         if constexpr (COLL == 0) omm = om;
-        relax_pairs<Q, T, COLL == 0>(d, m, p.F, om, omm);
+        relax_pairs<Q, T, COLL == 0, A>(d, m, p.F, om, omm);
     }
     return m;
 }
@@ -914,11 +1124,12 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (!SWAPPED) {
-            f[i] = ldv<ST, NT>(at<ST>(slot_base<ST>(a, B, i), o.at));
+            f[i] = ldv<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, i), o.at), i);
         } else {
             const Alt<ST> p = alt_in<Q, ST, i>(a, B);
-            f[i] = ldv<ST, NT>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
-                                                                      : xshift<-cx<Q>(i)>(o) + p.add_reg));
+            f[i] = ldv<Q, ST, NT>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
+                                                                         : xshift<-cx<Q>(i)>(o) + p.add_reg),
+                                  i);
         }
     });
     if constexpr (SWAPPED) {
@@ -931,8 +1142,9 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
                 constexpr int i = decltype(I)::value;
                 if constexpr (cx<Q>(i) == 1)
                     if (!((special >> opp(i)) & 1u))
-                        f[i] = ldv<ST, false>(at<ST>(slot_base<ST>(a, N, opp(i)),
-                                                     cell_off(N, N.n[0] - 1, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)));
+                        f[i] = ldv<Q, ST, false>(at<ST>(slot_base<ST>(a, N, opp(i)),
+                                                        cell_off(N, N.n[0] - 1, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)),
+                                                 i);
             });
         }
         if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
@@ -941,8 +1153,8 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
                 constexpr int i = decltype(I)::value;
                 if constexpr (cx<Q>(i) == -1)
                     if (!((special >> opp(i)) & 1u))
-                        f[i] = ldv<ST, false>(
-                            at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)));
+                        f[i] = ldv<Q, ST, false>(
+                            at<ST>(slot_base<ST>(a, N, opp(i)), cell_off(N, 0, y - cy<Q>(i), z - cz<Q>(i)) * (uint32_t)sizeof(ST)), i);
             });
         }
     }
@@ -953,16 +1165,17 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
 // bounce-back / anti-bounce-back links.
 template <int Q, typename ST, bool ODD, bool NT = true>
 __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, int y, int z,
-                                        uint32_t special, const typename Codec<ST>::T (&f)[Q])
+                                        uint32_t special, const typename Codec<ST>::T (&f)[Q], uint32_t h)
 {
     const XOff o = xoffsets<ST>(B, off, x);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if constexpr (!ODD) {
-            stv<ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i]);
+            stv_sr<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i], i, h);
         } else {
             const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-            stv<ST, NT>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg), f[i]);
+            stv_sr<Q, ST, NT>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg), f[i],
+                              i, h);
         }
     });
     if constexpr (ODD) {
@@ -975,8 +1188,9 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
                 constexpr int i = decltype(I)::value;
                 if constexpr (cx<Q>(i) == 1)
                     if (!((special >> i) & 1u))
-                        stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)),
-                                       f[i]);
+                        stv_sr<Q, ST, false>(
+                            at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)), f[i],
+                            i, h);
             });
         }
         if (x == 0 && B.nbx[0] >= 0) {
@@ -985,9 +1199,9 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
                 constexpr int i = decltype(I)::value;
                 if constexpr (cx<Q>(i) == -1)
                     if (!((special >> i) & 1u))
-                        stv<ST, false>(
+                        stv_sr<Q, ST, false>(
                             at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)),
-                            f[i]);
+                            f[i], i, h);
             });
         }
     }
@@ -1019,24 +1233,26 @@ __device__ __forceinline__ typename Codec<ST>::Raw load_regular_in(const SweepAr
 // sweep makes it.
 template <int Q, typename ST, int i>
 __device__ __forceinline__ void store_regular_out(const SweepArgs &a, const DevBlock &B, const XOff &o, int x, int y,
-                                                  int z, typename Codec<ST>::T v)
+                                                  int z, typename Codec<ST>::T v, uint32_t h)
 {
     if constexpr (cx<Q>(i) == 1) {
         if (x == B.n[0] - 1 && B.nbx[1] >= 0) {
             const DevBlock N = a.blocks[B.nbx[1]];
-            stv<ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)), v);
+            stv_sr<Q, ST, false>(at<ST>(slot_base<ST>(a, N, i), cell_off(N, 0, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)), v,
+                                 i, h);
             return;
         }
     } else {
         if (x == 0 && B.nbx[0] >= 0) {
             const DevBlock N = a.blocks[B.nbx[0]];
-            stv<ST, false>(
-                at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)), v);
+            stv_sr<Q, ST, false>(
+                at<ST>(slot_base<ST>(a, N, i), cell_off(N, N.n[0] - 1, y + cy<Q>(i), z + cz<Q>(i)) * (uint32_t)sizeof(ST)), v, i,
+                h);
             return;
         }
     }
     const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-    stv<ST, false>(at<ST>(p.base, xshift<cx<Q>(i)>(o) + p.add_reg), v);
+    stv_sr<Q, ST, false>(at<ST>(p.base, xshift<cx<Q>(i)>(o) + p.add_reg), v, i, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -1066,7 +1282,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         const uint32_t special = L.bb | L.alo | L.ahi;
         T f[Q];
         gather<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f);
-        const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
+        const uint32_t h = kStochastic<ST> ? state_hash<Q, T>(f, global_cell(a, B, c.x, c.y, c.z)) : 0u;
+        const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;
             sfor<Q>([&](auto I) {
@@ -1075,7 +1292,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
             });
         }
-        scatter<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f);
+        scatter<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f, h);
     }
 }
 
@@ -1172,10 +1389,10 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                         if (cx<Q>(i) == -1 && lx == ex - 1)
                             buf[k * stride + rb + 1] = load_regular_in<Q, ST, i>(a, B, o, x, y, z);
                     }
-                    if ((special >> opp(i)) & 1u) f[i] = ldv<ST, NT>(at<ST>(slot_base<ST>(a, B, i), boff));
+                    if ((special >> opp(i)) & 1u) f[i] = ldv<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, i), boff), i);
                 } else {
                     const Alt<ST> p = alt_in<Q, ST, i>(a, B);
-                    f[i] = ldv<ST, NT>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)));
+                    f[i] = ldv<Q, ST, NT>(at<ST>(p.base, boff + (((special >> opp(i)) & 1u) ? p.add_sp : p.add_reg)), i);
                 }
             });
         }
@@ -1185,13 +1402,14 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                 constexpr int i = decltype(I)::value;
                 if constexpr (cx<Q>(i) != 0) {
                     constexpr int k = xshift_index<Q>(i);
-                    if (!((special >> opp(i)) & 1u)) f[i] = Codec<ST>::dec(buf[k * stride + row + lane_at(-cx<Q>(i))]);
+                    if (!((special >> opp(i)) & 1u)) f[i] = dec_slot<Q, ST>(buf[k * stride + row + lane_at(-cx<Q>(i))], i);
                 }
             });
         }
         __syncthreads();  // the buffer now takes the outgoing populations
         if (active) {
-            const Macro<Q, T> m = collide<Q, COLL, T>(f, cp);
+            const uint32_t h = kStochastic<ST> ? state_hash<Q, T>(f, global_cell(a, B, x, y, z)) : 0u;
+            const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
             if (L.alo | L.ahi) {
                 const T rin = (T)a.rho_in, rout = (T)a.rho_out;
                 sfor<Q>([&](auto I) {
@@ -1205,15 +1423,15 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
                 const bool sp = (special >> i) & 1u;
                 if constexpr (cx<Q>(i) == 0) {
                     const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-                    stv<ST, NT>(at<ST>(p.base, boff + (sp ? p.add_sp : p.add_reg)), f[i]);
+                    stv_sr<Q, ST, NT>(at<ST>(p.base, boff + (sp ? p.add_sp : p.add_reg)), f[i], i, h);
                 } else {
                     constexpr int k = xshift_index<Q>(i);
                     if (sp) {
-                        stv<ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i]);
+                        stv_sr<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), boff), f[i], i, h);
                     } else if (!RING && !ring && ((cx<Q>(i) == 1 && lx == ex - 1) || (cx<Q>(i) == -1 && lx == 0))) {
-                        store_regular_out<Q, ST, i>(a, B, o, x, y, z, f[i]);  // target outside the segment
+                        store_regular_out<Q, ST, i>(a, B, o, x, y, z, f[i], h);  // target outside the segment
                     } else {
-                        buf[k * stride + row + lane_at(cx<Q>(i))] = Codec<ST>::enc(f[i]);
+                        buf[k * stride + row + lane_at(cx<Q>(i))] = enc_result<Q, ST>(f[i], i, h);
                     }
                 }
             });
@@ -1277,6 +1495,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         } else {
             for (int i = 0; i < Q; ++i) f[i] = T(0);
         }
+        const uint32_t h = kStochastic<ST> ? state_hash<Q, T>(f, global_cell(a, B, c.x, c.y, c.z)) : 0u;
         const Macro<Q, T> m0 = moments_of<Q, T>(f, cp.F);
         T P[6];
         pi_pairs<Q, T>(f, m0, P);
@@ -1313,7 +1532,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         }
         const T om = recip(tau);
         const T omm = COLL == 1 ? recip(T(0.5) + cp.magic * recip(tau - T(0.5))) : om;
-        relax_pairs<Q, T, COLL == 0>(f, m, cp.F, om, omm);
+        relax_pairs<Q, T, COLL == 0, AccOf<ST>>(f, m, cp.F, om, omm);
         if (!active) continue;
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;
@@ -1323,7 +1542,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
             });
         }
-        scatter<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f);
+        scatter<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f, h);
     }
 }
 
@@ -1486,7 +1705,10 @@ __global__ __launch_bounds__(kWG) void init_kernel(const SweepArgs a, const doub
         if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
         const uint32_t off = cell_off(B, c.x, c.y, c.z);
         if (mask & kSolidBit) {
-            sfor<Q>([&](auto I) { stv<ST>(at<ST>(slot_base<ST>(a, B, decltype(I)::value), off * sizeof(ST)), T(0)); });
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                stv<Q, ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), T(0), i);
+            });
             continue;
         }
         const int64_t S = (int64_t)(z1 - z0) * a.dom[1] * a.dom[0];
@@ -1499,7 +1721,7 @@ __global__ __launch_bounds__(kWG) void init_kernel(const SweepArgs a, const doub
             constexpr int i = decltype(I)::value;
             const double cu = cdot<Q, i>(u);
             const double v = weight<Q, double>(i) * ((rho - 1.0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-            stv<ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)v);
+            stv<Q, ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)v, i);
         });
     }
 }
@@ -1531,7 +1753,7 @@ __global__ __launch_bounds__(kWG) void pdfs_kernel(const SweepArgs a, double *bu
         if constexpr (TO_DEVICE) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                stv<ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)buf[i * S + k]);
+                stv<Q, ST>(at<ST>(slot_base<ST>(a, B, i), off * sizeof(ST)), (T)buf[i * S + k], i);
             });
         } else {
             const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
@@ -1605,7 +1827,7 @@ __global__ __launch_bounds__(kWG) void force_kernel(const SweepArgs a, double *p
                 sfor<Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     if ((L.bb >> i) & 1u) {
-                        const double f = weight<Q, double>(i) + (double)ldv<ST, false>(at<ST>(slot_base<ST>(a, B, opp(i)), off));
+                        const double f = weight<Q, double>(i) + (double)ldv<Q, ST, false>(at<ST>(slot_base<ST>(a, B, opp(i)), off), i);
                         const int k = ((to_solid >> i) & 1u) ? 0 : 3;
                         if constexpr (cx<Q>(i) != 0) acc[k + 0] += 2.0 * cx<Q>(i) * f;
                         if constexpr (cy<Q>(i) != 0) acc[k + 1] += 2.0 * cy<Q>(i) * f;

@@ -1,0 +1,156 @@
+"""The precision codec of the population storage (deviations d = f - w).
+
+1. Conversions that round to nearest even (set-up: wlb_pdfs_set, init):
+   every stored value is the nearest value of the storage format to the
+   input rounded to FP32 (ties to even), bit for bit the same as numpy's
+   conversions, so the one-store error is at most half an ulp of the format
+   (plus half an FP32 ulp).  FP16
+   stores d times a power of two per weight class (the largest S with
+   16 w S <= 65504, so |d| <= 16 w stays finite); BF16 and FP32 store d.
+2. Stores of collision results in FP16 / BF16 round stochastically: after
+   one step from a state that the format represents exactly, every stored
+   population is one of the two format neighbours of the FP64 oracle's
+   value (up to the FP32 collision's own rounding), i.e. the one-step error
+   is below one ulp of the format.
+3. The stochastic rounding is unbiased: a uniform flow is a fixed point of
+   the collision and of streaming; after one step every cell holds the same
+   exact value per population, rounded independently per cell, so the mean
+   over the cells must sit on the exact value within a few standard errors.
+   Rounding to nearest would put every cell on the same neighbour, up to
+   half an ulp away."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import inputs, say
+
+pytestmark = pytest.mark.gpu
+
+wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
+
+
+def f16_scale(q):
+    _, w, _ = O.stencil(q)
+    s = np.ones(q)
+    for i in range(q):
+        lim = 65504.0 / (16.0 * w[i])
+        while s[i] * 2.0 <= lim:
+            s[i] *= 2.0
+    return s
+
+
+def bf16_rne(x):
+    return np.array([O.bf16_round(float(v)) for v in np.asarray(x).ravel()]).reshape(np.shape(x))
+
+
+def rne(storage, d, q):
+    if storage == wlb.F64:
+        return d.copy()
+    if storage == wlb.F32:
+        return d.astype(np.float32).astype(np.float64)
+    if storage == wlb.F16DEV:
+        s = f16_scale(q)[:, None]
+        return (d.astype(np.float32) * s.astype(np.float32)).astype(np.float16).astype(np.float64) / s
+    return bf16_rne(d)
+
+
+def ulp(storage, y, q):
+    """Spacing of the storage format at |y| (per population)."""
+    a = np.abs(y)
+    if storage == wlb.F16DEV:
+        s = f16_scale(q)[:, None]
+        e = np.floor(np.log2(np.maximum(a * s, 2.0 ** -30)))
+        return 2.0 ** (np.maximum(e, -14) - 10) / s
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+@pytest.mark.parametrize("q", [19, 27, 15, 9])
+@pytest.mark.parametrize("storage", [wlb.F32, wlb.F16DEV, wlb.BF16DEV])
+def test_set_rounds_to_nearest_even_bitwise(q, storage):
+    say(f"case codec rne q{q} storage{storage}")
+    dom = (12, 10, 6)
+    n = int(np.prod(dom))
+    rng = np.random.default_rng(100 + q + storage)
+    _, w, _ = O.stencil(q)
+    # magnitudes from 1e-11 w to 8 w (half precision: subnormal to near the
+    # scaled limit), both signs, plus exact zeros
+    mag = w[:, None] * 10.0 ** rng.uniform(-11, np.log10(8.0), size=(q, n))
+    d = np.where(rng.random((q, n)) < 0.5, -mag, mag)
+    d[:, ::97] = 0.0
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 1, 1), stencil=q, storage=storage)
+    try:
+        rho, u = inputs.uniform_state(dom)
+        B.init(wlb.SRT, wlb.make_params(tau=0.8), rho, u)
+        B.pdfs_set(d)
+        got = B.pdfs_get()
+    finally:
+        B.close()
+    exp = rne(storage, d, q)
+    assert np.array_equal(got, exp), np.abs(got - exp).max()
+    sp32 = np.spacing(np.abs(d).astype(np.float32)).astype(np.float64)
+    half = 0.5 * (ulp(storage, d, q) + sp32 if storage != wlb.F32 else sp32)
+    assert np.all(np.abs(got - d) <= half)
+
+
+def _one_step(q, storage, coll, dom, rho, u, params, oparams):
+    B = wlb.Blocks(wlb.single_block(dom), dom, (1, 1, 1), stencil=q, storage=storage)
+    try:
+        B.init(coll, params, rho, u)
+        s0 = B.pdfs_get()
+        B.step(1)
+        g = B.pdfs_get()
+    finally:
+        B.close()
+    y = O.run(oparams, dom, s0.copy(), 1)
+    return s0, g, y
+
+
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (19, 0)])
+@pytest.mark.parametrize("storage", [wlb.F16DEV, wlb.BF16DEV])
+def test_one_step_error_below_one_ulp(q, coll, storage):
+    say(f"case codec one-step q{q} coll{coll} storage{storage}")
+    dom = (20, 12, 10)
+    rho, u = inputs.random_state(dom, seed=31, umag=0.04)
+    F = (1e-5, -2e-6, 3e-6)
+    p = wlb.make_params(tau=0.7, magic=3 / 16, force=F, omega_bulk=1.2, omega_higher=1.1)
+    op = O.Params(q=q, collision=coll, tau=0.7, magic=3 / 16, force=F, omega_bulk=1.2, omega_higher=1.1)
+    s0, g, y = _one_step(q, storage, coll, dom, rho, u, p, op)
+    u1 = ulp(storage, y, q)
+    err = np.abs(g - y)
+    # FP32 collision: its own rounding is a few 1e-9 on these magnitudes
+    ok = err < u1 + 2e-8
+    frac_half = float((err > 0.5 * u1 + 2e-8).mean())
+    say(f"one-step q{q} c{coll} {storage}: max err/ulp {(err / u1).max():.3f}, "
+        f"share beyond half an ulp {frac_half:.3f}")
+    assert ok.all(), float((err / u1).max())
+    # the rounding is not to nearest: a good share of the stores lands on
+    # the farther neighbour
+    assert frac_half > 0.05
+
+
+@pytest.mark.parametrize("storage", [wlb.F16DEV, wlb.BF16DEV])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
+def test_stochastic_rounding_is_unbiased(q, coll, storage):
+    say(f"case codec unbiased q{q} coll{coll} storage{storage}")
+    dom = (32, 32, 32)
+    n = int(np.prod(dom))
+    rho, u = inputs.uniform_state(dom, rho=1.002, u=(0.03, -0.02, 0.01))
+    p = wlb.make_params(tau=0.7, magic=3 / 16, omega_bulk=1.2, omega_higher=1.1)
+    op = O.Params(q=q, collision=coll, tau=0.7, magic=3 / 16, omega_bulk=1.2, omega_higher=1.1)
+    s0, g, _ = _one_step(q, storage, coll, dom, rho, u, p, op)
+    assert np.all(s0 == s0[:, :1])
+    # the exact one-step value of the uniform state (the same in every cell)
+    y = O.run(op, (2, 2, 2), np.repeat(s0[:, :1], 8, axis=1), 1)[:, 0]
+    u1 = ulp(storage, y[:, None], q)[:, 0]
+    lo, hi = g.min(axis=1), g.max(axis=1)
+    mean = g.mean(axis=1)
+    zscore = np.abs(mean - y) / (0.5 * u1 / np.sqrt(n))
+    say(f"unbiased q{q} c{coll} {storage}: max |mean - exact| / ulp {(np.abs(mean - y) / u1).max():.4f}, "
+        f"max z {zscore.max():.2f}")
+    # two neighbours at most, bracketing the exact value
+    assert np.all(hi - lo <= u1 * 1.0000001)
+    assert np.all((lo <= y + 2e-9) & (y - 2e-9 <= hi))
+    # mean within 6 standard errors (sd <= ulp/2) plus the FP32 collision's
+    # rounding (well below 1e-3 ulp here)
+    assert np.all(np.abs(mean - y) <= 6 * 0.5 * u1 / np.sqrt(n) + 1e-3 * u1)

@@ -1,8 +1,12 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
 the same seeded inputs.  FP64 storage must agree to 1e-12 (relative L2 of the
 velocity over fluid cells, and max population error relative to max |f|);
-FP32 storage to 1e-5, FP16 storage to 1e-3 (velocity); BF16 storage is
-reported against a looser 1e-2 bound (8 mantissa bits).  Block
+FP32 storage to 1e-5, FP16 storage to 1e-3 (velocity relative L2); BF16
+storage is reported against a looser 1e-2 bound (8 significand bits).  The
+velocity's max norm (max |u - u_ref| / max |u_ref|) is bounded too, for the
+16-bit forms by 3 times the L2 bound (their stochastic rounding makes the
+error a random field whose largest cell sits a few standard deviations out).
+Block
 decomposition, tile shape, persistent grid, graph replay and sweep/exchange
 splitting must not change a single bit."""
 import math
@@ -17,6 +21,7 @@ pytestmark = pytest.mark.gpu
 wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
 
 TOL = {wlb.F64: 1e-12, wlb.F32: 1e-5, wlb.F16DEV: 1e-3, wlb.BF16DEV: 1e-2}
+TOL_MAX = {wlb.F64: 1e-12, wlb.F32: 1e-5, wlb.F16DEV: 3e-3, wlb.BF16DEV: 3e-2}
 
 
 def _compare(case, storage, q, gpu, orc, solid, n, check_pops=True):
@@ -24,12 +29,15 @@ def _compare(case, storage, q, gpu, orc, solid, n, check_pops=True):
     do, ro, uo, to = orc
     B.close()
     m = fluid_mask(solid, n)
-    eu = rel_l2(u.reshape(3, -1), uo, m)
+    uu = u.reshape(3, -1)
+    eu = rel_l2(uu, uo, m)
+    emax = np.abs(uu[:, m] - uo[:, m]).max() / max(np.abs(uo[:, m]).max(), 1e-300)
     er = np.abs(r.reshape(-1)[m] - ro[m]).max()
     ep = pop_err(d[:, m], do[:, m], q)
-    say(f"{case}: u rel L2 {eu:.3e}, rho max {er:.3e}, pops {ep:.3e}")
+    say(f"{case}: u rel L2 {eu:.3e}, u max norm {emax:.3e}, rho max {er:.3e}, pops {ep:.3e}")
     tol = TOL[storage]
     assert eu <= tol, (case, eu)
+    assert emax <= TOL_MAX[storage], (case, emax)
     if check_pops and storage == wlb.F64:
         assert ep <= tol, (case, ep)
         assert er <= 1e-12
