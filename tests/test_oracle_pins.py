@@ -375,6 +375,35 @@ def test_uniform_flow_is_fixed_point(coll):
     assert np.abs(O.run(p, shape, d, 50) - d).max() <= 16 * ulp
 
 
+@pytest.mark.parametrize("coll", [O.SRT, O.TRT, O.MRT])
+def test_uniform_flow_through_density_faces_is_fixed_point(coll):
+    """Anti-bounce-back with the wall density equal to the flow's density is
+    exact for a uniform flow: at equilibrium f*_opp(i) = w rho (1 - 3 c.u +
+    9/2 (c.u)^2 - 3/2 u.u), so -f*_opp(i) + 2 w rho (1 + 9/2 (c.u)^2 - 3/2 u.u)
+    is f_eq_i itself.  The flow enters and leaves through both density faces
+    (u_x != 0) and has transverse components, so a dropped (c.u)^2 or u.u
+    term, a wrong sign of f*_opp or a wrong weight changes the incoming
+    populations at both faces by about w u^2 (1e-5 here), far above the
+    rounding noise."""
+    q = 27 if coll == O.MRT else 19
+    shape = (7, 5, 4)
+    rho0 = 1.01
+    rho, u = inputs.uniform_state(shape, rho=rho0, u=(0.03, -0.02, 0.01))
+    d = O.init(q, shape, rho, u)
+    p = O.Params(q=q, collision=coll, tau=0.7, omega_bulk=1.2, omega_higher=1.1, periodic=(0, 1, 1),
+                 pressure_axis=0, rho_in=rho0, rho_out=rho0)
+    # the boundary value is formed at the scale of 2 w rho (a face weight),
+    # so its rounding is a few ulp of that, not of the deviations
+    _, w, _ = O.stencil(q)
+    ulp = np.spacing(2.0 * w[1] * rho0)
+    assert np.abs(O.run(p, shape, d, 1) - d).max() <= 4 * ulp
+    # rounding does not accumulate
+    assert np.abs(O.run(p, shape, d, 40) - d).max() <= 8 * ulp
+    # and the same flow against a lower outlet density is not a fixed point
+    p.rho_out = rho0 - 1e-3
+    assert np.abs(O.run(p, shape, d, 1) - d).max() > 1e-6
+
+
 @pytest.mark.parametrize("q", [9, 15, 19, 27])
 def test_periodic_streaming_is_a_roll(q):
     c, w, _ = O.stencil(q)
