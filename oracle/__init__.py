@@ -141,6 +141,7 @@ def lib():
         L.orc_bf16_round.restype = C.c_double
         L.orc_mlp_forward.argtypes = [dp, C.c_int64, dp, dp, ip]
         L.orc_mlp_backward.argtypes = [dp, C.c_int64, dp, dp, C.c_double, dp, dp]
+        L.orc_mlp_undecided.argtypes = [dp, C.c_int64, dp, C.c_double, C.c_double, ip, dp]
         L.orc_mlp_nparam.restype = C.c_int
         L.orc_mlp_set_rounding.argtypes = [C.c_int]
         L.orc_gelu.argtypes = [C.c_double]
@@ -309,6 +310,21 @@ def mlp_forward(params, raw):
     flag = np.zeros(n, np.int32)
     _chk(lib().orc_mlp_forward(P, n, raw, o, flag), "mlp_forward")
     return o, flag
+
+
+def mlp_undecided(params, raw, rel0: float, rel2: float):
+    """Per sample: the number of bf16 rounding decisions that a
+    single-precision evaluation may take differently (operand within its
+    error bound of a rounding boundary; GELU(z) evaluated with relative error
+    at most rel0 + rel2 z^2), and the summed change of the output when each
+    of them alone goes the other way (see orc_mlp_undecided)."""
+    P = np.ascontiguousarray(params, np.float64)
+    raw = np.ascontiguousarray(raw, np.float64).reshape(-1, MLP_IN)
+    n = raw.shape[0]
+    cnt = np.zeros(n, np.int32)
+    flip = np.zeros(n)
+    _chk(lib().orc_mlp_undecided(P, n, raw, float(rel0), float(rel2), cnt, flip), "mlp_undecided")
+    return cnt, flip
 
 
 def mlp_backward(params, raw, target, inv_scale: float):

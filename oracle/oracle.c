@@ -383,6 +383,128 @@ int orc_mlp_forward(const double *P, int64_t n, const double *raw, double *o, in
     return 0;
 }
 
+/* Forward pass with the rounded operands of one rounding point replaced:
+ * layer 0 = input x_k, 1 = first hidden h1_k, 2 = second hidden h2_k (the
+ * values fed to the GEMMs); layer -1 replaces nothing. */
+static double mlp_forward_replace(const double *P, const double *x, int layer, int idx, double val)
+{
+    double xb[ORC_MLP_IN], g1[ORC_MLP_H], g2[ORC_MLP_H];
+    for (int k = 0; k < ORC_MLP_IN; ++k) xb[k] = to_bf16(x[k]);
+    if (layer == 0) xb[idx] = val;
+    for (int j = 0; j < ORC_MLP_H; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < ORC_MLP_IN; ++k) s += to_bf16(P[ORC_MLP_OFF_W1 + j * ORC_MLP_IN + k]) * xb[k];
+        g1[j] = to_bf16(gelu(s + P[ORC_MLP_OFF_B1 + j]));
+    }
+    if (layer == 1) g1[idx] = val;
+    for (int j = 0; j < ORC_MLP_H; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < ORC_MLP_H; ++k) s += to_bf16(P[ORC_MLP_OFF_W2 + j * ORC_MLP_H + k]) * g1[k];
+        g2[j] = to_bf16(gelu(s + P[ORC_MLP_OFF_B2 + j]));
+    }
+    if (layer == 2) g2[idx] = val;
+    double o = 0.0;
+    for (int k = 0; k < ORC_MLP_H; ++k) o += to_bf16(P[ORC_MLP_OFF_W3 + k]) * g2[k];
+    return o + P[ORC_MLP_OFF_B3];
+}
+
+/* Distance of v from the nearest bf16 rounding boundary (a midpoint between
+ * two adjacent bf16 values), and the bf16 value on the other side of it. */
+static double bf16_boundary(double v, double *other)
+{
+    const double a = fabs(v);
+    float fa = (float)a;
+    uint32_t u;
+    memcpy(&u, &fa, 4);
+    const uint32_t lo = u & 0xffff0000u;
+    double best = INFINITY, mid_best = 0.0;
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && lo < 0x10000u) break;
+        const uint32_t mb = (k == 0 ? lo : lo - 0x10000u) | 0x8000u;
+        float fm;
+        memcpy(&fm, &mb, 4);
+        const double dist = fabs(a - (double)fm);
+        if (dist < best) {
+            best = dist;
+            mid_best = (double)fm;
+        }
+    }
+    /* reflect the rounded value across the midpoint */
+    const double r = fabs(to_bf16(a));
+    const double o = 2.0 * mid_best - r;
+    *other = v < 0 ? -o : o;
+    return best;
+}
+
+/* Rounding decisions of the network evaluated in single precision (the
+ * GPU's matrix-core forward: standardisation in FP32, exact bf16 products
+ * summed in FP32 in any order, GELU(z) with relative error at most
+ * rel0 + rel2 z^2).  Such an
+ * evaluation takes every bf16 rounding decision of this oracle the same way
+ * unless the operand lies within the evaluation's error bound of a rounding
+ * boundary.  Error bounds per operand (u = 2^-24; n-term sums bounded by
+ * gamma_n = n u / (1 - n u) times the sum of magnitudes):
+ *   x_k:  2u |x_k| (a subtraction and a product);
+ *   h1_j: |GELU'(z)| gamma_8 (sum |W1 x| + |b1|) + (rel0 + rel2 z^2 + 2u) |h1|
+ *         + 2^-126 (z the pre-activation);
+ *   h2_j: the same with gamma_33 (sum |W2 h1| + |b2|);
+ * each computed from this oracle's own (rounded) operands.  For every sample:
+ * count[s] = number of undecided operands, flip[s] = sum over them of |o'-o|
+ * with o' the output when that operand alone takes its other bf16 neighbour
+ * (the layers after it recomputed). */
+int orc_mlp_undecided(const double *P, int64_t n, const double *raw, double rel0, double rel2, int32_t *count,
+                      double *flip)
+{
+    const double u = ldexp(1.0, -24);
+    const double g8 = 8 * u / (1 - 8 * u), g33 = 33 * u / (1 - 33 * u);
+    for (int64_t s = 0; s < n; ++s) {
+        double x[ORC_MLP_IN], xb[ORC_MLP_IN], g1b[ORC_MLP_H];
+        mlp_features(P, raw + ORC_MLP_IN * s, x);
+        const double o = mlp_forward_replace(P, x, -1, 0, 0.0);
+        int cnt = 0;
+        double eff = 0.0, other;
+        for (int k = 0; k < ORC_MLP_IN; ++k) {
+            xb[k] = to_bf16(x[k]);
+            if (bf16_boundary(x[k], &other) <= 2 * u * fabs(x[k])) {
+                ++cnt;
+                eff += fabs(mlp_forward_replace(P, x, 0, k, other) - o);
+            }
+        }
+        for (int j = 0; j < ORC_MLP_H; ++j) {
+            double sum = 0.0, mag = fabs(P[ORC_MLP_OFF_B1 + j]);
+            for (int k = 0; k < ORC_MLP_IN; ++k) {
+                const double t = to_bf16(P[ORC_MLP_OFF_W1 + j * ORC_MLP_IN + k]) * xb[k];
+                sum += t;
+                mag += fabs(t);
+            }
+            const double z = sum + P[ORC_MLP_OFF_B1 + j], h = gelu(z);
+            g1b[j] = to_bf16(h);
+            const double e = fabs(gelu_grad(z)) * g8 * mag + (rel0 + rel2 * z * z + 2 * u) * fabs(h) + ldexp(1.0, -126);
+            if (bf16_boundary(h, &other) <= e) {
+                ++cnt;
+                eff += fabs(mlp_forward_replace(P, x, 1, j, other) - o);
+            }
+        }
+        for (int j = 0; j < ORC_MLP_H; ++j) {
+            double sum = 0.0, mag = fabs(P[ORC_MLP_OFF_B2 + j]);
+            for (int k = 0; k < ORC_MLP_H; ++k) {
+                const double t = to_bf16(P[ORC_MLP_OFF_W2 + j * ORC_MLP_H + k]) * g1b[k];
+                sum += t;
+                mag += fabs(t);
+            }
+            const double z = sum + P[ORC_MLP_OFF_B2 + j], h = gelu(z);
+            const double e = fabs(gelu_grad(z)) * g33 * mag + (rel0 + rel2 * z * z + 2 * u) * fabs(h) + ldexp(1.0, -126);
+            if (bf16_boundary(h, &other) <= e) {
+                ++cnt;
+                eff += fabs(mlp_forward_replace(P, x, 2, j, other) - o);
+            }
+        }
+        count[s] = cnt;
+        flip[s] = eff;
+    }
+    return 0;
+}
+
 /* Backward pass of the training loss
  *   L = (1/n) sum_s ((softplus(o_s) - t_s) * inv_scale)^2
  * with respect to all parameters (mean/inv_std excluded: fixed).  The bf16

@@ -2,7 +2,9 @@
 
 Every .hip source under csrc/ is compiled to an object in _build/ (in
 parallel), then linked into paper_1909_13772_amd/libwlb.so.  Packed FP32
-instructions are disabled for all device code.
+instructions are disabled for all device code, and floating-point
+contraction is off (fused multiply-adds are written out where wanted), so
+that every kernel variant rounds the same way.
 """
 from __future__ import annotations
 
@@ -20,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]

@@ -109,13 +109,30 @@ template <> struct Codec<bf16_t> {
 // and deviations down to 2^-14 / S (about 5e-10 for the smallest weights)
 // stay normal instead of losing their low bits as subnormals.  Scaling by a
 // power of two is exact both ways.  Other storage types use no scale.
+// The scale of weight class c (|c|^2 = c) is evaluated at compile time only
+// (its loop must never reach the device code), and a slot picks the value of
+// its class.
 template <int Q>
-__host__ __device__ constexpr float f16_scale(int i)
+__host__ __device__ constexpr float f16_class_scale(int c)
 {
-    const double lim = 65504.0 * (double)wden<Q>() / (16.0 * (double)wnum<Q>(i));
+    int num = 0;
+    for (int i = 0; i < Q && num == 0; ++i)
+        if (c2<Q>(i) == c) num = wnum<Q>(i);
+    if (num == 0) return 1.0f;
+    const double lim = 65504.0 * (double)wden<Q>() / (16.0 * (double)num);
     double s = 1.0;
     while (s * 2.0 <= lim) s *= 2.0;
     return (float)s;
+}
+template <int Q, bool INV = false>
+__host__ __device__ __forceinline__ float f16_scale(int i)
+{
+    constexpr float s0 = INV ? 1.0f / f16_class_scale<Q>(0) : f16_class_scale<Q>(0);
+    constexpr float s1 = INV ? 1.0f / f16_class_scale<Q>(1) : f16_class_scale<Q>(1);
+    constexpr float s2 = INV ? 1.0f / f16_class_scale<Q>(2) : f16_class_scale<Q>(2);
+    constexpr float s3 = INV ? 1.0f / f16_class_scale<Q>(3) : f16_class_scale<Q>(3);
+    const int k = c2<Q>(i);
+    return k == 0 ? s0 : (k == 1 ? s1 : (k == 2 ? s2 : s3));
 }
 
 // Decode / encode one population of slot class i (round to nearest even).
@@ -123,7 +140,7 @@ template <int Q, typename ST>
 __device__ __forceinline__ typename Codec<ST>::T dec_slot(typename Codec<ST>::Raw r, int i)
 {
     if constexpr (std::is_same_v<ST, _Float16>)
-        return Codec<ST>::dec(r) * (1.0f / f16_scale<Q>(i));
+        return Codec<ST>::dec(r) * f16_scale<Q, true>(i);
     else
         return Codec<ST>::dec(r);
 }
@@ -276,6 +293,14 @@ struct Macro {
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// a * b + c with one rounding.  The library is compiled without
+// floating-point contraction, so that every kernel variant (direct or
+// LDS-staged sweep, any tile mode) evaluates the collision with the same
+// roundings and results stay bitwise independent of the launch choice; the
+// fused operations of the hot path are written out here.
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <int Q, typename T>
 __device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
 {
@@ -297,10 +322,10 @@ __device__ __forceinline__ Macro<Q, T> moments_of(const T (&d)[Q], const T F[3])
     m.drho = drho;
     m.rho = T(1) + drho;
     const T inv = recip(m.rho);
-    m.u[0] = (jx + T(0.5) * F[0]) * inv;
-    m.u[1] = (jy + T(0.5) * F[1]) * inv;
-    m.u[2] = (jz + T(0.5) * F[2]) * inv;
-    m.uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+    m.u[0] = fmadd(T(0.5), F[0], jx) * inv;
+    m.u[1] = fmadd(T(0.5), F[1], jy) * inv;
+    m.u[2] = fmadd(T(0.5), F[2], jz) * inv;
+    m.uu = fmadd(m.u[0], m.u[0], fmadd(m.u[1], m.u[1], m.u[2] * m.u[2]));
     return m;
 }
 
@@ -392,7 +417,7 @@ template <int Q, typename T>
 __device__ __forceinline__ MomentSources<T> moment_sources(const Macro<Q, T> &m, const T F[3])
 {
     MomentSources<T> s;
-    s.A = m.drho - T(1.5) * m.rho * m.uu;
+    s.A = fmadd(T(-1.5) * m.rho, m.uu, m.drho);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         s.ru[k] = m.rho * m.u[k];
@@ -404,13 +429,13 @@ __device__ __forceinline__ MomentSources<T> moment_sources(const Macro<Q, T> &m,
     s.ruu[3] = s.ru[0] * m.u[1];
     s.ruu[4] = s.ru[0] * m.u[2];
     s.ruu[5] = s.ru[1] * m.u[2];
-    s.uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
+    s.uF = fmadd(m.u[0], F[0], fmadd(m.u[1], F[1], m.u[2] * F[2]));
     s.uFs[0] = m.u[0] * F[0];
     s.uFs[1] = m.u[1] * F[1];
     s.uFs[2] = m.u[2] * F[2];
-    s.uFs[3] = m.u[0] * F[1] + m.u[1] * F[0];
-    s.uFs[4] = m.u[0] * F[2] + m.u[2] * F[0];
-    s.uFs[5] = m.u[1] * F[2] + m.u[2] * F[1];
+    s.uFs[3] = fmadd(m.u[0], F[1], m.u[1] * F[0]);
+    s.uFs[4] = fmadd(m.u[0], F[2], m.u[2] * F[0]);
+    s.uFs[5] = fmadd(m.u[1], F[2], m.u[2] * F[1]);
     return s;
 }
 
@@ -430,20 +455,20 @@ __device__ __forceinline__ T source_moment(const MomentSources<T> &s)
     T r = T(0);
     if constexpr (L0 != 0) {
         if constexpr (EQ)
-            r += T(L0 / D) * s.A;
+            r = T(L0 / D) * s.A;
         else
-            r -= T(3.0 * L0 / D) * s.uF;
+            r = T(-3.0 * L0 / D) * s.uF;
     }
     sfor<3>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        if constexpr (L1[j] != 0) r += T(3.0 * L1[j] / D) * (EQ ? s.ru[j] : s.F[j]);
+        if constexpr (L1[j] != 0) r = fmadd(T(3.0 * L1[j] / D), EQ ? s.ru[j] : s.F[j], r);
     });
     sfor<6>([&](auto J) {
         constexpr int j = decltype(J)::value;
         // (c.u)^2 counts each off-diagonal product twice; (c.u)(c.F) is
         // already summed over both orders in uFs
         constexpr double k = EQ ? (j < 3 ? 4.5 : 9.0) : 9.0;
-        if constexpr (L2[j] != 0) r += T(k * L2[j] / D) * (EQ ? s.ruu[j] : s.uFs[j]);
+        if constexpr (L2[j] != 0) r = fmadd(T(k * L2[j] / D), EQ ? s.ruu[j] : s.uFs[j], r);
     });
     return r;
 }
@@ -542,9 +567,9 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
         } else if constexpr (ord == 2 && (a == 2 || b == 2 || c == 2)) {
             g[k] = T(0);  // diagonal: below
         } else if constexpr (ord == 2) {
-            g[k] = om * mn[k] - (T(1) - T(0.5) * om) * source_moment<Q, false, a, b, c>(src);
+            g[k] = fmadd(om, mn[k], -(T(1) - T(0.5) * om) * source_moment<Q, false, a, b, c>(src));
         } else {
-            g[k] = omh * mn[k] - (T(1) - T(0.5) * omh) * source_moment<Q, false, a, b, c>(src);
+            g[k] = fmadd(omh, mn[k], -(T(1) - T(0.5) * omh) * source_moment<Q, false, a, b, c>(src));
         }
     });
     {
@@ -552,9 +577,9 @@ __device__ __forceinline__ void mrt_collide(T (&d)[Q], const Macro<Q, T> &m, con
                 fzz = source_moment<Q, false, 0, 0, 2>(src);
         const T An = mn[XX] - mn[YY], Bn = mn[XX] - mn[ZZ], Tn = mn[XX] + mn[YY] + mn[ZZ];
         const T Af = fxx - fyy, Bf = fxx - fzz, Tf = fxx + fyy + fzz;
-        const T gA = om * An - (T(1) - T(0.5) * om) * Af;
-        const T gB = om * Bn - (T(1) - T(0.5) * om) * Bf;
-        const T gT = omb * Tn - (T(1) - T(0.5) * omb) * Tf;
+        const T gA = fmadd(om, An, -(T(1) - T(0.5) * om) * Af);
+        const T gB = fmadd(om, Bn, -(T(1) - T(0.5) * om) * Bf);
+        const T gT = fmadd(omb, Tn, -(T(1) - T(0.5) * omb) * Tf);
         const T third = T(1) / T(3);
         g[XX] = (gA + gB + gT) * third;
         g[YY] = (gT - T(2) * gA + gB) * third;
@@ -859,32 +884,32 @@ static_assert(pair_t_exact<19, float>() && pair_t_exact<27, float>() && pair_t_e
 template <int Q, typename T, bool SRT = false, typename A = T>
 __device__ __forceinline__ void relax_pairs(T (&d)[Q], const Macro<Q, T> &m, const T F[3], T om, T omm)
 {
-    const T fop = T(1) - T(0.5) * om;
-    const T A0 = m.drho - T(1.5) * m.rho * m.uu;
-    const T uF = m.u[0] * F[0] + m.u[1] * F[1] + m.u[2] * F[2];
-    const T K = om * A0 - T(3) * fop * uF;
+    const T fop = fmadd(T(-0.5), om, T(1));
+    const T A0 = fmadd(T(-1.5) * m.rho, m.uu, m.drho);
+    const T uF = fmadd(m.u[0], F[0], fmadd(m.u[1], F[1], m.u[2] * F[2]));
+    const T K = fmadd(om, A0, T(-3) * fop * uF);
     const T kv = T(4.5) * om * m.rho, fv = T(9) * fop;
     T V[3], J[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        V[k] = kv * m.u[k] + fv * F[k];
+        V[k] = fmadd(kv, m.u[k], fv * F[k]);
         J[k] = (SRT ? om : omm) * m.j[k];
     }
     // (1 - omega)/2, exact for omega in [1/2, 2]
-    const A hp = A(T(0.5) - T(0.5) * om), hm = SRT ? hp : A(T(0.5) - T(0.5) * omm);
+    const A hp = A(fmadd(T(-0.5), om, T(0.5))), hm = SRT ? hp : A(fmadd(T(-0.5), omm, T(0.5)));
     {
         constexpr T w0 = weight<Q, T>(0);
-        d[0] = (T(1) - om) * d[0] + w0 * K;
+        d[0] = fmadd(T(1) - om, d[0], w0 * K);
     }
     sfor<(Q - 1) / 2>([&](auto I) {
         constexpr int i = 2 * decltype(I)::value + 1, o = i + 1;
         constexpr T w = weight<Q, T>(i);
         constexpr T t = pair_t<Q, T>(i);
         const T cu = cdot<Q, i>(m.u);
-        const T zp = w * (K + cu * cdot<Q, i>(V));
+        const T zp = w * fmadd(cu, cdot<Q, i>(V), K);
         const T zj = t * cdot<Q, i>(J);
-        const A sh = hp * A(d[i] + d[o]) + A(zp);
-        const A ah = hm * A(d[i] - d[o]) + A(zj) + A(t) * A(cdot<Q, i>(F));
+        const A sh = fmadd(hp, A(d[i] + d[o]), A(zp));
+        const A ah = fmadd(hm, A(d[i] - d[o]), A(zj) + A(t) * A(cdot<Q, i>(F)));
         d[i] = T(sh + ah);
         d[o] = T(sh - ah);
     });

@@ -151,6 +151,10 @@ def test_stochastic_rounding_is_unbiased(q, coll, storage):
     # two neighbours at most, bracketing the exact value
     assert np.all(hi - lo <= u1 * 1.0000001)
     assert np.all((lo <= y + 2e-9) & (y - 2e-9 <= hi))
-    # mean within 6 standard errors (sd <= ulp/2) plus the FP32 collision's
-    # rounding (well below 1e-3 ulp here)
-    assert np.all(np.abs(mean - y) <= 6 * 0.5 * u1 / np.sqrt(n) + 1e-3 * u1)
+    # mean within 6 standard errors (sd <= ulp/2) of the value the FP32
+    # collision rounds; that value differs from the exact one by the
+    # collision's own rounding, the same in every cell: about 2^-24 times
+    # the deviations' scale (1e-2), 2e-9 absolute.  This is far below the
+    # format's ulp for every population but the few near zero (a D3Q27
+    # corner pair of the MRT state sits at 5e-7 with an FP16 ulp of 5e-10).
+    assert np.all(np.abs(mean - y) <= 6 * 0.5 * u1 / np.sqrt(n) + 2e-9)

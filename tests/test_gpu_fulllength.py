@@ -8,10 +8,14 @@ exact solution is the same.  A 1 x 256 x 1 run of the oracle (periodic x/z,
 walls in y) is therefore the exact answer for every cell of the 256^3 run,
 which makes element-wise parity at full size and full length tractable on
 the CPU (2000 x 256 cell updates).  Checked per storage:
-  - every x-z column of the GPU result is bitwise the same (this covers the
-    periodic wrap along x, the z exchange and every tile of the full grid);
-  - the column against the oracle: velocity relative L2 and max norm
-    (relative to max |u|), populations max |d - d_ref| / max |f_ref|.
+  - FP64 and FP32 (rounding to nearest): every x-z column of the GPU result
+    is bitwise the same (this covers the periodic wrap along x, the z
+    exchange and every tile of the full grid);
+  - every cell against the oracle column: velocity relative L2 and max norm
+    (relative to max |u|), populations max |d - d_ref| / max |f_ref|.  The
+    16-bit forms round stochastically with bits drawn per cell, so their
+    columns differ from each other by rounding noise; every one of them is
+    held to the bounds.
 Bounds: FP64 1e-12 (velocity and populations), FP32 1e-5, FP16 1e-3 on the
 velocity's relative L2 (the accuracy targets of the method's precision
 forms).  BF16 (8 significand bits) cannot reach 1e-3 on this flow: a
@@ -67,21 +71,23 @@ def test_channel_256_full_length_vs_oracle_column(storage, column):
         B.close()
     u = u.reshape(3, N, N, N)
     d = d.reshape(19, N, N, N)
-    # every x-z column bitwise equal to column (x = 0, z = 0)
-    assert np.array_equal(u, np.broadcast_to(u[:, :1, :, :1], u.shape)), "velocity differs between x-z columns"
-    assert np.array_equal(d, np.broadcast_to(d[:, :1, :, :1], d.shape)), "populations differ between x-z columns"
-    ug = u[:, 0, :, 0]
-    dg = d[:, 0, :, 0]
-    del u, d
+    same_columns = bool(np.array_equal(u, np.broadcast_to(u[:, :1, :, :1], u.shape))
+                        and np.array_equal(d, np.broadcast_to(d[:, :1, :, :1], d.shape)))
     do, uo = column
-    ux, uxo = ug[0], uo[0]
-    e_l2 = np.linalg.norm(ux - uxo) / np.linalg.norm(uxo)
-    e_max = np.abs(ux - uxo).max() / np.abs(uxo).max()
-    e_cross = np.abs(ug[1:] - uo[1:]).max() / np.abs(uxo).max()
     _, w, _ = O.stencil(19)
-    e_pop = np.abs(dg - do).max() / np.abs(do + w[:, None]).max()
+    umax = np.abs(uo[0]).max()
+    # every cell against the oracle column (y is the second array axis)
+    dux = u[0] - uo[0][None, :, None]
+    e_l2 = np.sqrt((dux ** 2).sum() / (N * N * (uo[0] ** 2).sum()))
+    e_max = np.abs(dux).max() / umax
+    del dux
+    e_cross = max(np.abs(u[k] - uo[k][None, :, None]).max() for k in (1, 2)) / umax
+    e_pop = max(np.abs(d[k] - do[k][None, :, None]).max() for k in range(19)) / np.abs(do + w[:, None]).max()
+    del u, d
     say(f"channel256 {name}: u rel L2 {e_l2:.3e}, max {e_max:.3e}, cross {e_cross:.3e}, pops {e_pop:.3e}, "
-        f"u_max {np.abs(uxo).max():.6e}, mass {tot[0]:.15g}")
+        f"u_max {umax:.6e}, mass {tot[0]:.15g}, columns bitwise equal {same_columns}")
+    if storage in (wlb.F64, wlb.F32):
+        assert same_columns, "populations or velocity differ between x-z columns"
     bl2, bmax, bpop = BOUNDS[storage]
     assert e_l2 <= bl2, (name, e_l2)
     assert e_max <= bmax, (name, e_max)

@@ -92,3 +92,28 @@ def test_trained_closure_keeps_the_coarse_les_stable():
         assert not r["diverged"] and len(r["energy"]) == 21
         e = np.asarray(r["energy"])
         assert np.all(np.isfinite(e)) and e[-1] < 0.5 * e[0]
+
+
+def test_solver_in_the_loop_training_small():
+    """Solver-in-the-loop training of the output layer at toy size: a 32^3
+    fine run per seed filtered to 8^3, two SPSA iterations whose every loss
+    is a coarse LES run of the library against the filtered fine run.  The
+    losses are finite, the point returned is the best one evaluated (its
+    loss is recomputed and matches, runs being deterministic), and only the
+    33 output-layer parameters move."""
+    from paper_1909_13772_amd import les
+    say("case les solver-in-the-loop small")
+    n, f = 32, 4
+    P0 = inputs.mlp_params(5, mean=np.zeros(7), inv_std=np.array([400.0] * 6 + [150.0]), out_bias=-2.0)
+    P, best, hist = les.train_a_posteriori(wlb, torch, P0, [0], n, f, 40, 20, iters=2)
+    assert len(hist) == 3
+    losses = [hist[0][1]] + [v for h in hist[1:] for v in h[1:]]
+    assert all(np.isfinite(losses)), losses
+    assert best == min(losses)
+    lo, hi = les.B3 - 32, les.B3 + 1
+    assert np.array_equal(P[:lo], P0[:lo]) and np.array_equal(P[hi:], P0[hi:])
+    # the returned parameters reproduce the best loss
+    tau0 = les.coarse_tau(f)
+    rc, uc, ref = les.reference(wlb, torch, 0, n, f, 40, 20)
+    run = les.les_run(wlb, torch, rc, uc, wlb.CLOSURE_MLP, P, 40 // f, 20 // f, tau0)
+    assert abs(les.energy_error(run, ref) - best) <= 1e-12 * max(1.0, best)

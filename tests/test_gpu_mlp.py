@@ -3,9 +3,14 @@ training gradient and Adam kernels, and the sweep with the MLP closure,
 against the FP64 CPU oracle (same bf16 rounding points).
 
 Where FP32 decides a bf16 rounding (x, h1, h2) the two sides may round a
-value that sits on a rounding boundary differently; such flips are rare and
-bounded, so the forward check requires 1e-5 relative agreement on at least
-99.5 % of the samples and 1e-2 absolute on all of them."""
+value that sits on a rounding boundary differently.  The oracle marks, per
+sample, every operand that lies within the GPU's FP32 error bound of a bf16
+rounding boundary (orc_mlp_undecided: worst-case summation bounds, GELU
+evaluated to a relative error of 1e-6 + 1e-7 z^2, the bound of the GPU's
+erfc-based GELU found by evaluating its FP32 formula against the exact
+function over |z| <= 11).  Samples with no such operand take every decision
+the same way on both sides and must agree to 1e-5 relative; the others must
+agree to 1e-5 plus the summed effect of turning each undecided decision."""
 import math
 
 import numpy as np
@@ -56,11 +61,16 @@ def test_forward_matches_oracle():
     # the oracle sees exactly the FP32 values the GPU read
     o_orc, f_orc = O.mlp_forward(P.astype(np.float64), raw.astype(np.float32).astype(np.float64))
     err = np.abs(o_gpu - o_orc)
-    rel = err / np.maximum(1.0, np.abs(o_orc))
-    frac = float((rel > 1e-5).mean())
-    say(f"mlp forward: max abs {err.max():.3e}, frac beyond 1e-5 {frac:.4f}")
-    assert frac < 5e-3
-    assert err.max() < 1e-2
+    tol = 1e-5 * np.maximum(1.0, np.abs(o_orc))
+    cnt, flip = O.mlp_undecided(P.astype(np.float64), raw.astype(np.float32).astype(np.float64), 1e-6, 1e-7)
+    dec = cnt == 0
+    beyond = err > tol
+    say(f"mlp forward: decided samples {dec.mean():.3f}, max rel err decided "
+        f"{(err[dec] / tol[dec]).max() * 1e-5:.3e}; beyond 1e-5: {int(beyond.sum())} samples "
+        f"({beyond.mean():.4f}), all undecided; max abs {err.max():.3e}")
+    assert dec.mean() > 0.3
+    assert np.all(err[dec] <= tol[dec]), "a sample without an undecided rounding differs"
+    assert np.all(err[~dec] <= tol[~dec] + flip[~dec]), "an undecided sample differs by more than its flips"
     assert (f_gpu != f_orc).mean() < 1e-3
 
 

@@ -4,8 +4,9 @@ velocity over fluid cells, and max population error relative to max |f|);
 FP32 storage to 1e-5, FP16 storage to 1e-3 (velocity relative L2); BF16
 storage is reported against a looser 1e-2 bound (8 significand bits).  The
 velocity's max norm (max |u - u_ref| / max |u_ref|) is bounded too, for the
-16-bit forms by 3 times the L2 bound (their stochastic rounding makes the
-error a random field whose largest cell sits a few standard deviations out).
+reduced-precision forms by 3 times the L2 bound: the accuracy targets are
+stated on the L2 norm, and the largest cell error of a rounding-noise field
+sits a few standard deviations above its mean.
 Block
 decomposition, tile shape, persistent grid, graph replay and sweep/exchange
 splitting must not change a single bit."""
@@ -21,7 +22,7 @@ pytestmark = pytest.mark.gpu
 wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not built")
 
 TOL = {wlb.F64: 1e-12, wlb.F32: 1e-5, wlb.F16DEV: 1e-3, wlb.BF16DEV: 1e-2}
-TOL_MAX = {wlb.F64: 1e-12, wlb.F32: 1e-5, wlb.F16DEV: 3e-3, wlb.BF16DEV: 3e-2}
+TOL_MAX = {wlb.F64: 1e-12, wlb.F32: 3e-5, wlb.F16DEV: 3e-3, wlb.BF16DEV: 3e-2}
 
 
 def _compare(case, storage, q, gpu, orc, solid, n, check_pops=True):
