@@ -341,6 +341,24 @@ size_t wlb_mlp_grad_workspace(int64_t n);
 int wlb_mlp_grad(const float *params, const float *raw, const float *target, int64_t n, double inv_scale, float *grad,
                  float *loss, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* Largest minibatch of wlb_mlp_grad_noalloc. */
+#define WLB_MLP_NOALLOC_MAX_SAMPLES 262144
+
+/* wlb_mlp_grad without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * results (bit for bit) as wlb_mlp_grad; the per-workgroup partial sums go to
+ * a fixed library-owned device array of WLB_MLP_NOALLOC_MAX_SAMPLES / 256 x
+ * (WLB_MLP_NPARAM + 1) floats (5.6 MB), one per GPU, held until the process
+ * ends.  The call allocates nothing.  Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other threads, other
+ * streams) race and must be serialised by the caller.  Asynchronous on
+ * `hip_stream` (the device current at the call must be the stream's).
+ * Errors: WLB_ERR_ARG (null argument, n <= 0, n > WLB_MLP_NOALLOC_MAX_SAMPLES),
+ * WLB_ERR_HIP. */
+int wlb_mlp_grad_noalloc(const float *params, const float *raw, const float *target, int64_t n, double inv_scale,
+                         float *grad, float *loss, void *hip_stream);
+
 /* One Adam update of the FP32 master parameters in place (mean / inv_std
  * untouched); m, v: device moment buffers (WLB_MLP_NPARAM floats, zero at
  * step 1); step counts from 1.  Asynchronous on `hip_stream`. */

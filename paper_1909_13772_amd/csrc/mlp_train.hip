@@ -11,6 +11,7 @@
 // (deterministic).  Adam keeps FP32 master weights; mean / inv_std are not
 // trained.
 #include <cstring>
+#include <mutex>
 
 #include "mlp.hpp"
 #include "wlb_internal.hpp"
@@ -217,6 +218,39 @@ hipError_t launch_mlp_grad(const float *P, const float *raw, const float *target
     hipLaunchKernelGGL(mlp_grad_reduce_kernel, dim3((kNParam + 1 + kWG - 1) / kWG), dim3(kWG), 0, st, work, (int)nwg, n,
                        grad, loss);
     return hipGetLastError();
+}
+
+// Gradient pass without a caller workspace: the per-workgroup partials live in
+// a library-owned device array of fixed size, one copy per GPU (each device
+// gets its own instance of a __device__ variable).  Every workgroup writes its
+// whole partial row before the reduction reads it, so nothing needs clearing
+// between calls; calls that overlap on one GPU share the array and race.
+constexpr int64_t kNoAllocMaxWG = kMlpNoAllocMaxSamples / kWG;
+static_assert(kMlpNoAllocMaxSamples % kWG == 0, "whole workgroups");
+static __device__ __align__(256) float scratch[kNoAllocMaxWG * (kNParam + 1)];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        // the array's name is a host-side stand-in: the device address of
+        // this GPU's copy comes from the runtime, with this device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, int64_t step, float lr, float b1, float b2,

@@ -1523,6 +1523,21 @@ int wlb_mlp_grad(const float *params, const float *raw, const float *target, int
     return WLB_OK;
 }
 
+int wlb_mlp_grad_noalloc(const float *params, const float *raw, const float *target, int64_t n, double inv_scale,
+                         float *grad, float *loss, void *stream)
+{
+    if (!params || !raw || !target || !grad || !loss) return fail(WLB_ERR_ARG, "null argument");
+    if (n <= 0) return fail(WLB_ERR_ARG, "empty minibatch");
+    if (n > WLB_MLP_NOALLOC_MAX_SAMPLES)
+        return fail(WLB_ERR_ARG, "minibatch of %lld samples exceeds the %d that the library's fixed scratch holds",
+                    (long long)n, WLB_MLP_NOALLOC_MAX_SAMPLES);
+    void *scr = nullptr;
+    HIPCHK(mlp_scratch_address(&scr));
+    HIPCHK(launch_mlp_grad(params, raw, target, n, (float)inv_scale, grad, loss, static_cast<float *>(scr),
+                           static_cast<hipStream_t>(stream)));
+    return WLB_OK;
+}
+
 int wlb_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr, double beta1,
                  double beta2, double eps, void *stream)
 {

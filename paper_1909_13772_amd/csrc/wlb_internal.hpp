@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wlb.h"
+
 namespace wlb {
 
 constexpr int kMaxQ = 27;
@@ -121,6 +123,11 @@ WLB_DECLARE_LAUNCHERS(cover)  // write-coverage check (4-byte counters in the FP
 // Learned closure (mlp_train.hip).
 hipError_t launch_mlp_forward(const void *net, const float *raw, int64_t n, float *out, int32_t *flag, hipStream_t st);
 size_t mlp_grad_workspace_bytes(int64_t n);
+// largest minibatch of the gradient pass without a caller workspace, and the
+// device address of this GPU's copy of its partial-sum array
+constexpr int64_t kMlpNoAllocMaxSamples = WLB_MLP_NOALLOC_MAX_SAMPLES;
+constexpr int kMaxDevices = 64;
+hipError_t mlp_scratch_address(void **out);
 hipError_t launch_mlp_grad(const float *P, const float *raw, const float *target, int64_t n, float inv_scale,
                            float *grad, float *loss, float *work, hipStream_t st);
 hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, int64_t step, float lr, float b1, float b2,

@@ -30,6 +30,7 @@ SRT, TRT, MRT, KBC, CUMULANT = 0, 1, 2, 3, 4
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 CLOSURE_NONE, CLOSURE_SMAG, CLOSURE_MLP = 0, 1, 2
 MLP_NPARAM = 1359
+MLP_NOALLOC_MAX_SAMPLES = 262144
 ELEM_BYTES = {F64: 8, F32: 4, F16DEV: 2, BF16DEV: 2}
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16DEV: "f16dev", BF16DEV: "bf16dev"}
 
@@ -127,6 +128,7 @@ _sig = {
     "wlb_mlp_forward": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "wlb_mlp_grad_workspace": (C.c_size_t, [C.c_int64]),
     "wlb_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "wlb_mlp_grad_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
     "wlb_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, _vp]),
 }
 for _n, (_r, _a) in _sig.items():
@@ -275,6 +277,11 @@ def wlb_mlp_grad_workspace(n):
 def wlb_mlp_grad(params_ptr, raw_ptr, target_ptr, n, inv_scale, grad_ptr, loss_ptr, ws_ptr, ws_bytes, stream_ptr):
     _check(_lib.wlb_mlp_grad(_vp(params_ptr), _vp(raw_ptr), _vp(target_ptr), int(n), float(inv_scale), _vp(grad_ptr),
                              _vp(loss_ptr), _vp(ws_ptr), int(ws_bytes), _vp(stream_ptr)))
+
+
+def wlb_mlp_grad_noalloc(params_ptr, raw_ptr, target_ptr, n, inv_scale, grad_ptr, loss_ptr, stream_ptr):
+    _check(_lib.wlb_mlp_grad_noalloc(_vp(params_ptr), _vp(raw_ptr), _vp(target_ptr), int(n), float(inv_scale),
+                                     _vp(grad_ptr), _vp(loss_ptr), _vp(stream_ptr)))
 
 
 def wlb_mlp_adam(params_ptr, grad_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, stream_ptr):
