@@ -128,7 +128,10 @@ typedef struct {
     int32_t autotune;
 } wlb_lbm_params;
 
-/* Create a block set.  d[n] describes the blocks, domain[3] the bounding box,
+/* Create a block set (Sec. 3.1: the domain split into blocks that are the
+ * containers of the simulation data; Sec. 4.1: each block a uniform grid of
+ * cells with ghost layers, translating between block-local and global cell
+ * coordinates).  d[n] describes the blocks, domain[3] the bounding box,
  * periodic[3] which axes wrap.  stencil = WLB_D2Q9/D3Q15/D3Q19/D3Q27, storage =
  * WLB_F64/F32/F16DEV/BF16DEV.  Builds the 26-neighbour table (periodic links
  * included), the tile list and the exchange work list, and returns in
@@ -140,13 +143,16 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
 
 /* Bind a caller-owned device arena (>= arena_bytes, 256-byte aligned) and the
  * HIP stream (a hipStream_t; must not be the null stream) on which all work
- * of this handle runs.  Uploads the descriptor tables.  The arena must stay
+ * of this handle runs (Sec. 4.3: the GPU fields, laid out with padding so
+ * that rows are aligned, Sec. 4.2).  Uploads the descriptor tables.  The arena must stay
  * allocated until wlb_blocks_destroy. */
 int wlb_blocks_bind(wlb_blocks_t h, void *device_arena, size_t bytes, void *hip_stream);
 
 /* Initialise the populations to the equilibrium of rho[N], u[3][N] (host,
  * FP64, global order) and the geometry from solid[N] (host, 1 = solid, may be
- * NULL for no solid cells).  collision = WLB_SRT/TRT/MRT/KBC/CUMULANT.  Resets the step
+ * NULL for no solid cells).  Sec. 4.3: the initial state is set up in host
+ * (mirror) arrays and transferred to the GPU once; Sec. 4.4: the geometry
+ * becomes per-cell flags that select the boundary treatment.  collision = WLB_SRT/TRT/MRT/KBC/CUMULANT.  Resets the step
  * counter.  Runs the tile autotuner when p->autotune is set (the state is
  * re-initialised afterwards).  Synchronises the stream.
  * Errors: WLB_ERR_ARG (tau <= 1/2, bad pressure axis, MLP without weights),
@@ -166,7 +172,10 @@ int wlb_lbm_step(wlb_blocks_t h, int32_t nsteps);
  * next sweep; wlb_lbm_step(h, 1) == wlb_lbm_sweep + wlb_ghost_exchange. */
 int wlb_lbm_sweep(wlb_blocks_t h);
 
-/* Exchange the ghost layers that the last sweep requires (after an even sweep
+/* Ghost-layer exchange between the blocks (Sec. 4.1 and Sec. 4.2: after a
+ * sweep the ghost layers propagate the updated data to neighbouring blocks;
+ * Sec. 3.3: between blocks of one process a direct copy without buffers).
+ * Exchange the ghost layers that the last sweep requires (after an even sweep
  * the neighbours' outgoing populations are copied into the ghost layer;
  * after an odd sweep the populations written into the ghost layer are
  * copied into the neighbours).  Idempotent; asynchronous. */
@@ -210,7 +219,9 @@ int wlb_force_get(wlb_blocks_t h, double out[8]);
 int wlb_debug_write_coverage(wlb_blocks_t h, int32_t odd, uint32_t *counts);
 
 /* Population deviations d_i = f_i - w_i of the current state in natural
- * layout d[q][N] (FP64, host), and the reverse.  set also re-establishes the
+ * layout d[q][N] (FP64, host), and the reverse (Sec. 3.4: the block data is
+ * serialised for checkpoints and restored on restart; Sec. 4.3: results are
+ * copied back to host arrays).  set also re-establishes the
  * natural layout so the next sweep is even; solid cells are ignored.  Used
  * for checkpoint / resume (bitwise for every storage type). */
 int wlb_pdfs_get(wlb_blocks_t h, double *d);
@@ -227,7 +238,7 @@ typedef struct {
     int32_t tile[3];        /* tile shape target in use (x, y, z); -1, 0, 0: fluid-cell lists */
     int32_t grid;           /* workgroups per sweep launch (0 = one per tile, -1 = one per tile
                                with XCD-contiguous tile ranges) */
-    int32_t lds_staging;    /* 1: the odd sweep stages x-shifted populations in LDS */
+    int32_t lds_staging;    /* odd-sweep kernel in use: 0 direct, 1 LDS-staged, 2 row vectors */
     int32_t n_xchg_items;   /* exchange work items per exchange */
     int64_t xchg_elems;     /* populations copied per exchange */
     size_t arena_bytes;
@@ -252,16 +263,28 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *out);
  * arena's tile table holds), WLB_ERR_STATE (tx = -1 without fluid lists). */
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid);
 
-/* Stage (1) or not (0, default) the odd sweep's x-shifted populations in LDS
- * row buffers so that all its global accesses are row-aligned (the same
- * populations move; Eq. 2 and the AA scheme of Sec. 4.1 are unchanged).
- * Tiles that are whole rows of a block wrapping onto itself along x shift
- * around the row buffer; other row segments load one halo element per row
- * end and store one element past it, through the block's other end, its
- * ghost column or an x-neighbour block.  Staging is skipped automatically
- * with fluid-cell list tiles and when the buffers exceed 64 KiB per
- * workgroup (see wlb_info_t.lds_staging).  The autotuner tries both.
- * Errors: WLB_ERR_ARG for a null handle. */
+/* Odd-sweep kernel (Eq. 2 and the AA scheme of Sec. 4.1 are the same in all
+ * three; results are bitwise identical):
+ *   0 (default) direct: every lane reads and writes its cell's x-shifted
+ *     populations one element off the row alignment;
+ *   1 LDS staging: the x-shifted populations pass through LDS row buffers
+ *     so that all global accesses are row-aligned.  Tiles that are whole
+ *     rows of a block wrapping onto itself along x shift around the row
+ *     buffer; other row segments load one halo element per row end and
+ *     store one element past it, through the block's other end, its ghost
+ *     column or an x-neighbour block.  Skipped automatically with
+ *     fluid-cell list tiles and when the buffers exceed 64 KiB per
+ *     workgroup;
+ *   2 row vectors: whole rows, 16 / (element bytes) consecutive cells per
+ *     lane, every access one aligned 16-byte vector, the one-cell x shift
+ *     done by moving elements between lanes (the lane at a wavefront edge
+ *     reads or writes the element crossing it).  Needs every block to wrap
+ *     onto itself along x, to hold no solid cells nearby, to have rows that
+ *     split into whole vectors of at most 256 lanes, no MLP closure and no
+ *     interior/frontier overlap; otherwise the direct sweep runs.
+ * wlb_info_t.lds_staging reports the kernel in use.  The autotuner tries all
+ * three.
+ * Errors: WLB_ERR_ARG for a null handle or a mode outside 0..2. */
 int wlb_set_lds_staging(wlb_blocks_t h, int32_t on);
 
 /* Interior/frontier overlap (1) or not (0, default).  Sec. 3.3 and 6: the

@@ -69,7 +69,8 @@ struct wlb_blocks {
     // arena layout (bytes)
     size_t off_pop = 0, pop_bytes = 0, off_mask = 0, mask_words = 0, off_blocks = 0, off_tiles = 0,
            tile_cap = 0, off_pull = 0, off_push = 0, off_partials = 0, off_totals = 0, off_stage = 0,
-           stage_bytes = 0, off_mlp = 0, arena_bytes = 0, off_cells = 0, off_ltiles = 0, ltile_cap = 0;
+           stage_bytes = 0, off_mlp = 0, arena_bytes = 0, off_cells = 0, off_ltiles = 0, ltile_cap = 0,
+           off_vtiles = 0, vtile_cap = 0;
     char *arena = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false, inited = false;
@@ -88,6 +89,11 @@ struct wlb_blocks {
     int shape[3] = {0, 0, 0};
     int grid = 0;
     bool lds_stage = false;  // odd sweep stages x-shifted populations in LDS (autotuner candidate)
+    // odd sweep over whole rows with 16-byte vectors per lane (autotuner
+    // candidate); possible when every block wraps onto itself along x, has
+    // no solid cells nearby and rows split into whole vectors
+    bool vec_want = false, vec_ok = false;
+    std::vector<int4> vtiles;
     // interior/frontier overlap: each sweep is split into the cells at least
     // kFrontier rows away from every y/z face with a neighbour (interior) and
     // the rest (frontier); the frontier and the exchange run on a second
@@ -226,7 +232,47 @@ void update_lds_stride(wlb_blocks *h)
     for (int i = 0; i < h->q; ++i) nsh += ccq(h->q, i, 0) != 0;
     const size_t bytes = (((size_t)nsh * stride * h->esize + 15) & ~(size_t)15) + kWG * 4;
     h->args.lds_stride = (h->lds_stage && bytes <= 65536 && !h->list_mode) ? stride : 0;
+    // the row-vector odd sweep takes whole rows of its own tiles; it has no
+    // interior / frontier split, so the overlap turns it off
+    h->args.vec_odd = (h->vec_want && h->vec_ok && !h->overlap) ? 1 : 0;
+    if (h->args.vec_odd) h->args.lds_stride = 0;
     h->graph_valid = false;
+}
+
+// Elements per 16-byte vector of the storage type.
+int row_vec(const wlb_blocks *h) { return 16 / h->esize; }
+
+// Row tiles of the vector odd sweep (after the masks are known).  A tile is
+// floor(256 / (n0 / V)) rows of one block along y.
+int build_vtiles(wlb_blocks *h)
+{
+    const int V = row_vec(h);
+    h->vec_ok = h->params.closure != WLB_CLOSURE_MLP && !h->blocks.empty();
+    for (size_t b = 0; b < h->blocks.size() && h->vec_ok; ++b) {
+        const DevBlock &D = h->dev[b];
+        const int L = D.n[0] / V;
+        if (D.wrapx == 0 || D.mask >= 0 || D.xoff != 0 || D.n[0] % V != 0 || L > kWG || L < 1) h->vec_ok = false;
+    }
+    h->vtiles.clear();
+    if (!h->vec_ok) return WLB_OK;
+    for (size_t b = 0; b < h->blocks.size(); ++b) {
+        const DevBlock &D = h->dev[b];
+        const int R = kWG / (D.n[0] / V);
+        for (int z = 0; z < D.n[2]; ++z)
+            for (int y0 = 0; y0 < D.n[1]; y0 += R)
+                h->vtiles.push_back(make_int4((int)b, D.n[0] << 16, y0 | (std::min(R, D.n[1] - y0) << 16), z | (1 << 16)));
+    }
+    if (h->vtiles.size() > h->vtile_cap) {
+        h->vtiles.clear();
+        h->vec_ok = false;
+        return WLB_OK;
+    }
+    HIPCHK(hipMemcpyAsync(h->arena + h->off_vtiles, h->vtiles.data(), h->vtiles.size() * sizeof(int4),
+                          hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->args.vtiles = reinterpret_cast<const int4 *>(h->arena + h->off_vtiles);
+    h->args.nvtiles = (int)h->vtiles.size();
+    return WLB_OK;
 }
 
 int upload_tiles(wlb_blocks *h)
@@ -285,6 +331,10 @@ hipError_t sweep_launch(const wlb_blocks *h, bool odd, const SweepArgs &args, in
 {
     SweepArgs a = args;
     a.nt = (odd ? h->nt_odd : h->nt_even) ? 1 : 0;
+    // the row-vector odd sweep exists for FP64 storage (and the counting
+    // storage of the write-coverage check); other storage runs the direct one
+    if (a.vec_odd && !(h->esize == 8 || h->cover)) a.vec_odd = 0;
+    if (odd && a.vec_odd) g = (h->grid > 0 && h->grid < a.nvtiles) ? h->grid : std::max(1, a.nvtiles);
     if (h->cover) return sweep_cover(h->q, h->collision, odd, a, g, st);
     switch (h->storage) {
     case WLB_F64: return sweep_f64(h->q, h->collision, odd, a, g, st);
@@ -636,12 +686,14 @@ int autotune(wlb_blocks *h)
     int bs[3] = {0, 0, 0}, bg = 0;
     // repetitions scaled so each candidate runs ~ 2e8 cell updates at most
     int reps = (int)std::max<int64_t>(2, std::min<int64_t>(10, 200000000 / std::max<int64_t>(1, 2 * h->ncells)));
-    bool blds = false;
     // WLB_AUTOTUNE_LOG=1 prints every candidate's time to stderr
     const char *env = getenv("WLB_AUTOTUNE_LOG");
     const bool log = env && env[0] == '1';
-    for (int lds = 0; lds <= 1; ++lds) {
-        h->lds_stage = lds != 0;
+    int blds = 0;  // odd-sweep mode: 0 direct, 1 LDS-staged, 2 row vectors
+    for (int lds = 0; lds <= 2; ++lds) {
+        if (lds == 2 && !(h->vec_ok && h->esize == 8)) continue;
+        h->lds_stage = lds == 1;
+        h->vec_want = lds == 2;
         std::vector<std::array<int, 3>> shapes;
         for (const auto &s : kShapes) shapes.push_back({s[0], s[1], s[2]});
         if (h->list_built) shapes.push_back({-1, 0, 0});
@@ -651,7 +703,8 @@ int autotune(wlb_blocks *h)
                 int rc = set_tiles(h, s[0], s[1], s[2], g);
                 if (rc) return rc;
                 if (g > 0 && g >= (int)h->tiles.size()) continue;  // same as one workgroup per tile
-                if (lds && h->args.lds_stride == 0) continue;      // staging does not fit: covered by lds = 0
+                if (lds == 1 && h->args.lds_stride == 0) continue;  // staging does not fit: covered by lds = 0
+                if (lds == 2 && !h->args.vec_odd) continue;
                 float ms = 0.f;
                 rc = time_pairs(h, reps, &ms);
                 if (rc) return rc;
@@ -664,7 +717,7 @@ int autotune(wlb_blocks *h)
                     bs[1] = s[1];
                     bs[2] = s[2];
                     bg = g;
-                    blds = lds != 0;
+                    blds = lds;
                 }
             }
         }
@@ -672,16 +725,19 @@ int autotune(wlb_blocks *h)
     // the best shape and grid once more with each choice of the non-temporal
     // hint per parity, with and without LDS staging
     bool bne = true, bno = true;
-    for (int lds = 0; lds <= 1; ++lds)
+    for (int lds = 0; lds <= 2; ++lds)
         for (int v = 0; v < 4; ++v) {
             const bool ne = (v & 1) == 0, no = (v & 2) == 0;
             if (ne && no) continue;  // measured above
-            h->lds_stage = lds != 0;
+            if (lds == 2 && !(h->vec_ok && h->esize == 8)) continue;
+            h->lds_stage = lds == 1;
+            h->vec_want = lds == 2;
             h->nt_even = ne;
             h->nt_odd = no;
             int rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
             if (rc) return rc;
-            if (lds && h->args.lds_stride == 0) continue;
+            if (lds == 1 && h->args.lds_stride == 0) continue;
+            if (lds == 2 && !h->args.vec_odd) continue;
             float ms = 0.f;
             rc = time_pairs(h, reps, &ms);
             if (rc) return rc;
@@ -690,14 +746,15 @@ int autotune(wlb_blocks *h)
                         bs[1], bs[2], bg, lds, ne ? 1 : 0, no ? 1 : 0, ms);
             if (ms < best) {
                 best = ms;
-                blds = lds != 0;
+                blds = lds;
                 bne = ne;
                 bno = no;
             }
         }
     h->nt_even = bne;
     h->nt_odd = bno;
-    h->lds_stage = blds;
+    h->lds_stage = blds == 1;
+    h->vec_want = blds == 2;
     h->overlap = false;
     int rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
     if (rc || (h->pull.empty() && h->push.empty())) return rc;
@@ -712,7 +769,7 @@ int autotune(wlb_blocks *h)
     if (rc) return rc;
     if (log)
         fprintf(stderr, "[wlb autotune] tile %d,%d,%d grid %d lds %d overlap 1: %.4f ms per two steps\n", bs[0], bs[1],
-                bs[2], bg, blds ? 1 : 0, ms);
+                bs[2], bg, blds, ms);
     if (ms < 0.99f * best) return WLB_OK;  // kept only for a clear gain (it adds launches and a second stream)
     h->overlap = false;
     return set_tiles(h, bs[0], bs[1], bs[2], bg);
@@ -833,12 +890,29 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
         // boundary (whole lines per wave).  Shorter rows are packed with just
         // their two ghost cells: a wave then covers several rows of nearly
         // contiguous memory instead of touching a mostly empty line per row
-        // and another for each ghost cell.
+        // and another for each ghost cell.  A block that wraps onto itself
+        // along x never touches an x ghost cell (the kernels wrap inside the
+        // row), so its aligned rows carry no x padding at all.  Ghost rows
+        // exist only along a y face with a neighbour: beyond a wall nothing
+        // is read or written (bounce-back links use the cell's own slots).
+        // Rows and planes without padding keep the sweeps' streams
+        // contiguous, which measurably raises the achieved bandwidth.
         const bool packed = (size_t)B.n[0] * h->esize < 256;
-        D.xoff = packed ? 1 : align_e;
-        D.pitch = packed ? B.n[0] + 2 : (int32_t)round_up((size_t)align_e + B.n[0] + 1, align_e);
-        const int64_t plane = (int64_t)D.pitch * (B.n[1] + 2);
-        const int64_t slot = (int64_t)round_up((size_t)(plane * (B.n[2] + 2)), align_e);
+        const bool selfx = B.nbr[12] == b && B.nbr[14] == b;
+        D.gy = (B.nbr[10] >= 0 || B.nbr[16] >= 0) ? 1 : 0;
+        D.xoff = packed ? 1 : (selfx ? 0 : align_e);
+        D.pitch = packed ? B.n[0] + 2
+                         : (int32_t)(selfx ? round_up((size_t)B.n[0], align_e)
+                                           : round_up((size_t)align_e + B.n[0] + 1, align_e));
+        const int64_t plane = (int64_t)D.pitch * (B.n[1] + 2 * D.gy);
+        // Large slots start 16 MiB apart: the sweeps stream all q slots at
+        // the same cell offset at once, and on MI355X the achieved bandwidth
+        // of that access pattern depends on the slots' stride; strides that
+        // are multiples of 16 MiB measured best (the even sweep's pattern
+        // over a 256^3 FP64 block: 0.83 ms at 144 MiB against 0.96 ms at
+        // the unpadded 129 MiB).  Smaller slots are only aligned.
+        int64_t slot = (int64_t)round_up((size_t)(plane * (B.n[2] + 2)), align_e);
+        if (slot * h->esize >= ((int64_t)64 << 20)) slot = (int64_t)round_up((size_t)slot * h->esize, (size_t)16 << 20) / h->esize;
         if (slot * h->esize >= (int64_t)1 << 31) {
             delete h;
             return fail(WLB_ERR_ARG, "block %d too large: one population slot must stay below 2 GiB", b);
@@ -889,6 +963,11 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
         h->off_ltiles = off;
         off += round_up(h->ltile_cap * sizeof(int4), 256);
     }
+    // row tiles of the vector odd sweep (at most one per row)
+    h->vtile_cap = 1;
+    for (const HostBlock &B : h->blocks) h->vtile_cap += (size_t)B.n[1] * B.n[2];
+    h->off_vtiles = off;
+    off += round_up(h->vtile_cap * sizeof(int4), 256);
     // --- exchange work lists
     for (int b = 0; b < n; ++b) {
         const HostBlock &A = h->blocks[b];
@@ -1147,6 +1226,10 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
             h->ltiles.clear();
         }
     }
+    {
+        const int rcv = build_vtiles(h);
+        if (rcv) return rcv;
+    }
     if (h->list_mode && !h->list_built) {
         const int rc0 = set_tiles(h, 0, 0, 0, h->grid);
         if (rc0) return rc0;
@@ -1306,7 +1389,7 @@ int wlb_debug_write_coverage(wlb_blocks_t h, int32_t odd, uint32_t *counts)
                 for (int y = 0; y < B.n[1]; ++y)
                     for (int x = 0; x < B.n[0]; ++x)
                         counts[i * N + ((int64_t)(B.g[2] + z) * ny + B.g[1] + y) * nx + B.g[0] + x] =
-                            raw[B.pop + i * B.slot + (int64_t)(z + 1) * B.plane + (int64_t)(y + 1) * B.pitch + B.xoff + x];
+                            raw[B.pop + i * B.slot + (int64_t)(z + 1) * B.plane + (int64_t)(y + B.gy) * B.pitch + B.xoff + x];
     return WLB_OK;
 }
 
@@ -1360,7 +1443,7 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
     o->n_tiles = (int32_t)(h->list_mode ? h->ltiles.size() : h->tiles.size());
     for (int a = 0; a < 3; ++a) o->tile[a] = h->shape[a];
     o->grid = h->grid;
-    o->lds_staging = h->args.lds_stride > 0 ? 1 : 0;
+    o->lds_staging = (h->args.vec_odd && h->esize == 8) ? 2 : (h->args.lds_stride > 0 ? 1 : 0);
     o->overlap = split_sweeps(h) ? 1 : 0;
     o->nt_even = h->nt_even ? 1 : 0;
     o->nt_odd = h->nt_odd ? 1 : 0;
@@ -1393,7 +1476,9 @@ int wlb_set_nontemporal(wlb_blocks_t h, int32_t even, int32_t odd)
 int wlb_set_lds_staging(wlb_blocks_t h, int32_t on)
 {
     if (!h) return fail(WLB_ERR_ARG, "null handle");
-    h->lds_stage = on != 0;
+    if (on < 0 || on > 2) return fail(WLB_ERR_ARG, "odd-sweep mode must be 0, 1 or 2");
+    h->lds_stage = on == 1;
+    h->vec_want = on == 2;
     update_lds_stride(h);
     return WLB_OK;
 }

@@ -160,23 +160,20 @@ __device__ __forceinline__ typename Codec<ST>::Raw enc_slot(typename Codec<ST>::
 // one binade (a body force, a slowly growing flow), so rounding to nearest
 // would commit the same error every step and the state would drift by up to
 // half an ulp per step; the unbiased rounding turns that drift into a random
-// walk.  FP16: the dither is added to the 13 float bits below the half
-// precision's mantissa and cut off, which is exact in the normal range of
-// half precision (|v S| >= 2^-14); below it the conversion then rounds to
-// nearest.  BF16: the dither is added to the 16 bits that the conversion
-// drops.  Infinities and NaN stay what they are.  FP32 and FP64 round to
-// nearest.
+// walk.  gfx950 converts FP32 to FP16 / BF16 with stochastic rounding in
+// one instruction (v_cvt_sr_f16_f32, v_cvt_sr_bf16_f32), which takes the
+// random bits as an operand.  FP32 and FP64 round to nearest.
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 template <int Q, typename ST>
 __device__ __forceinline__ typename Codec<ST>::Raw enc_slot_sr(typename Codec<ST>::T v, int i, uint32_t rnd)
 {
     if constexpr (std::is_same_v<ST, _Float16>) {
-        const uint32_t b = __float_as_uint(v * f16_scale<Q>(i));
-        const uint32_t t = ((b & 0x7fffffffu) + (rnd >> 19)) & ~0x1fffu;
-        return Codec<ST>::enc(__uint_as_float(t | (b & 0x80000000u)));
+        const f16x2_t r = __builtin_amdgcn_cvt_sr_f16_f32(f16x2_t{}, v * f16_scale<Q>(i), rnd, false);
+        return __builtin_bit_cast(uint16_t, r[0]);
     } else if constexpr (std::is_same_v<ST, bf16_t>) {
-        const uint32_t b = __float_as_uint(v);
-        if ((b & 0x7f800000u) == 0x7f800000u) return Codec<ST>::enc(v);
-        return (uint16_t)((b + (rnd >> 16)) >> 16);
+        const bf16x2_t r = __builtin_amdgcn_cvt_sr_bf16_f32(bf16x2_t{}, v, rnd, false);
+        return __builtin_bit_cast(uint16_t, r[0]);
     } else {
         return Codec<ST>::enc(v);
     }
@@ -190,10 +187,12 @@ template <typename ST>
 using AccOf = std::conditional_t<std::is_same_v<ST, float>, double, typename Codec<ST>::T>;
 
 // Random bits of a cell for the stochastic rounding of its stores: a hash
-// of the cell's incoming populations (which change every step) and its
-// global index, so that the rounding is reproducible and the same whatever
-// the tiles, blocks, launch order or kernel variant.  Per population the
-// bits are mixed once more with the population's index.
+// of four of the cell's incoming populations (which change every step) and
+// its global index, so that the rounding is reproducible and the same
+// whatever the tiles, blocks, launch order or kernel variant.  Per
+// population the bits are mixed once more with the population's index, and
+// the high half is folded into the low half so that every bit of the
+// result depends on every bit of the cell hash.
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -208,16 +207,18 @@ __device__ __forceinline__ uint32_t state_hash(const T (&f)[Q], uint32_t gcell)
 {
     uint32_t h = gcell * 0x9e3779b1u;
     if constexpr (sizeof(T) == 4) {
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            h += __builtin_rotateleft32(__float_as_uint((float)f[i]), (7 * i) & 31);
-        });
+        // the rest population and one per axis (slots 1, 3, 5 exist in every set)
+        h += __float_as_uint((float)f[0]);
+        h += __builtin_rotateleft32(__float_as_uint((float)f[1]), 7);
+        h += __builtin_rotateleft32(__float_as_uint((float)f[3]), 14);
+        h += __builtin_rotateleft32(__float_as_uint((float)f[5]), 21);
     }
     return mix32(h);
 }
 __device__ __forceinline__ uint32_t pop_bits(uint32_t h, int i)
 {
-    return (h ^ (0x9e3779b9u * (uint32_t)(i + 1))) * 0x85ebca6bu;
+    const uint32_t r = (h ^ (0x9e3779b9u * (uint32_t)(i + 1))) * 0x85ebca6bu;
+    return r ^ (r >> 16);
 }
 
 // Raw bits of a collision result for storage (stochastic rounding for
@@ -1034,13 +1035,17 @@ __device__ __forceinline__ Links<Q> classify(uint32_t mask, const DevBlock &B, i
 }
 
 // Anti-bounce-back value for the population entering the cell against
-// direction i: -f*_i + 2 w_i rho_w (1 + 9/2 (c_i.u)^2 - 3/2 u.u), as deviation.
+// direction i: -f*_i + 2 w_i rho_w (1 + 9/2 (c_i.u)^2 - 3/2 u.u), as deviation
+// -d*_i + 2 w_i ((rho_w - 1) + rho_w (9/2 (c_i.u)^2 - 3/2 u.u)).  This form
+// keeps every intermediate at the size of the result (rho_w - 1 comes exact
+// from the FP64 parameters), so FP32 loses no digits to a term of order one.
 template <int Q, int i, typename T>
-__device__ __forceinline__ T abb_value(T post_i, const Macro<Q, T> &m, T rho_w)
+__device__ __forceinline__ T abb_value(T post_i, const Macro<Q, T> &m, T rho_w, T drho_w)
 {
     constexpr T w = weight<Q, T>(i);
     const T cu = cdot<Q, i>(m.u);
-    return -post_i + T(2) * w * (rho_w * (T(1) + T(4.5) * cu * cu - T(1.5) * m.uu) - T(1));
+    const T X = fmadd(T(4.5) * cu, cu, T(-1.5) * m.uu);
+    return fmadd(T(2) * w, fmadd(rho_w, X, drho_w), -post_i);
 }
 
 // Addressing: every access is (uniform 64-bit slot base) + (32-bit byte
@@ -1061,7 +1066,7 @@ __device__ __forceinline__ ST *at(const char *base, uint32_t byte_off)
 
 __device__ __forceinline__ uint32_t cell_off(const DevBlock &B, int x, int y, int z)
 {
-    return (uint32_t)((z + 1) * B.plane + (y + 1) * B.pitch + B.xoff + x);
+    return (uint32_t)((z + 1) * B.plane + (y + B.gy) * B.pitch + B.xoff + x);
 }
 
 template <int Q, int i>
@@ -1311,10 +1316,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+            const T drin = (T)(a.rho_in - 1.0), drout = (T)(a.rho_out - 1.0);
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
-                if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
+                if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout, lo ? drin : drout);
             });
         }
         scatter<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f, h);
@@ -1437,10 +1443,11 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
             const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
             if (L.alo | L.ahi) {
                 const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+                const T drin = (T)(a.rho_in - 1.0), drout = (T)(a.rho_out - 1.0);
                 sfor<Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
-                    if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
+                    if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout, lo ? drin : drout);
                 });
             }
             sfor<Q>([&](auto I) {
@@ -1483,6 +1490,229 @@ __global__ __launch_bounds__(kWG) void sweep_odd_lds_kernel(const SweepArgs a)
         // LDS and info are reused by the next tile of this workgroup (t is
         // the same in all its waves, so all or none of them wait)
         if (t + (int)gridDim.x < a.nstiles) __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Odd sweep over whole rows with V = 16 / (element bytes) consecutive cells
+// per lane, so that every population access of a lane is one 16-byte vector.
+// For blocks that wrap onto themselves along x and hold no solid cells: all
+// cells of a row then share their link classes (walls and density faces lie
+// on y / z faces), and a row's populations move as whole vectors.  A
+// population with c_x != 0 is read from (written to) the aligned vector of
+// the lane's own cells in the row shifted by c_y, c_z; the one-cell x shift
+// is done with lane moves, each lane taking the element at the end of its
+// neighbour lane's vector.  A row held by one wavefront rotates within its
+// lanes (the x wrap); where a row spans several wavefronts, the lane at a
+// wavefront edge reads (writes) the element that crosses the edge from
+// (to) memory itself, and the lane on the other side leaves that element
+// out of its vector store.  A workgroup takes floor(256 / (n0 / V)) rows
+// (tiles built on the host, a.vtiles).
+// ---------------------------------------------------------------------------
+// Value of `v` held by lane `src` of the wavefront.
+template <typename Raw>
+__device__ __forceinline__ Raw lane_get(Raw v, int src)
+{
+    if constexpr (sizeof(Raw) == 8) {
+        const uint64_t b = (uint64_t)v;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)b);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(b >> 32));
+        return (Raw)(((uint64_t)hi << 32) | lo);
+    } else {
+        return (Raw)(uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)v);
+    }
+}
+
+template <typename ST>
+constexpr int kRowVec = 16 / (int)sizeof(typename Codec<ST>::Raw);
+
+// A lane's row vector: 16 bytes as four 32-bit words, elements of the
+// storage type packed in order (two 16-bit elements per word).
+typedef uint32_t RowWords __attribute__((ext_vector_type(4)));
+template <typename ST>
+__device__ __forceinline__ typename Codec<ST>::Raw row_get(const RowWords &w, int k)
+{
+    using Raw = typename Codec<ST>::Raw;
+    if constexpr (sizeof(Raw) == 8)
+        return (Raw)w[2 * k] | ((Raw)w[2 * k + 1] << 32);
+    else if constexpr (sizeof(Raw) == 4)
+        return (Raw)w[k];
+    else
+        return (Raw)((w[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+}
+template <typename ST>
+__device__ __forceinline__ void row_set(RowWords &w, int k, typename Codec<ST>::Raw r)
+{
+    using Raw = typename Codec<ST>::Raw;
+    if constexpr (sizeof(Raw) == 8) {
+        w[2 * k] = (uint32_t)r;
+        w[2 * k + 1] = (uint32_t)((uint64_t)r >> 32);
+    } else if constexpr (sizeof(Raw) == 4) {
+        w[k] = (uint32_t)r;
+    } else {
+        const uint32_t sh = 16u * (uint32_t)(k & 1);
+        w[k >> 1] = (w[k >> 1] & ~(0xffffu << sh)) | ((uint32_t)r << sh);
+    }
+}
+// The vector shifted by one element: towards higher x (cells x0 - 1 ..
+// x0 + V - 2, `in` entering at element 0) or towards lower x (cells x0 + 1
+// .. x0 + V, `in` entering at element V - 1).
+template <typename ST>
+__device__ __forceinline__ RowWords row_shift_up(const RowWords &w, typename Codec<ST>::Raw in)
+{
+    constexpr int V = kRowVec<ST>;
+    RowWords o;
+    row_set<ST>(o, 0, in);
+#pragma unroll
+    for (int k = 1; k < V; ++k) row_set<ST>(o, k, row_get<ST>(w, k - 1));
+    return o;
+}
+template <typename ST>
+__device__ __forceinline__ RowWords row_shift_down(const RowWords &w, typename Codec<ST>::Raw in)
+{
+    constexpr int V = kRowVec<ST>;
+    RowWords o;
+#pragma unroll
+    for (int k = 0; k < V - 1; ++k) row_set<ST>(o, k, row_get<ST>(w, k + 1));
+    row_set<ST>(o, V - 1, in);
+    return o;
+}
+
+// Elements [k0, k1) of a row vector to memory (the counting storage adds one
+// per element).
+template <typename ST, bool NT>
+__device__ __forceinline__ void store_elems(char *p, const RowWords &w, int k0, int k1)
+{
+    using Raw = typename Codec<ST>::Raw;
+    constexpr int V = kRowVec<ST>;
+    if constexpr (std::is_same_v<ST, cover_t>) {
+        for (int k = k0; k < k1; ++k) atomicAdd(reinterpret_cast<uint32_t *>(p) + k, 1u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (k >= k0 && k < k1) mem_st<false>(reinterpret_cast<Raw *>(p) + k, row_get<ST>(w, k));
+    }
+}
+template <typename ST, bool NT>
+__device__ __forceinline__ void store_vec(char *p, const RowWords &w)
+{
+    if constexpr (std::is_same_v<ST, cover_t>)
+        store_elems<ST, NT>(p, w, 0, kRowVec<ST>);
+    else
+        mem_st<NT>(reinterpret_cast<RowWords *>(p), w);
+}
+
+template <int Q, int COLL, typename ST, bool NT>
+__global__ __launch_bounds__(kWG) void sweep_odd_vec_kernel(const SweepArgs a)
+{
+    using T = typename Codec<ST>::T;
+    using Raw = typename Codec<ST>::Raw;
+    constexpr int V = kRowVec<ST>;
+    constexpr uint32_t E = (uint32_t)sizeof(ST);
+    const int tid = threadIdx.x, lane = tid & 63, wlo = tid & ~63;
+    for (int t = blockIdx.x; t < a.nvtiles; t += gridDim.x) {
+        const int4 tv = a.vtiles[t];
+        const DevBlock B = a.blocks[tv.x];
+        const int n0 = B.n[0], L = n0 / V;  // lanes per row (the host checks n0 % V == 0, L <= 256)
+        const int ey = tv.z >> 16, ez = tv.w >> 16;
+        const int r = tid / L;
+        if (r >= ey * ez) continue;  // whole rows stay active together
+        const int rlo = r * L, rhi = rlo + L;
+        const int x0 = (tid - rlo) * V;
+        const int y = (tv.z & 0xffff) + r % ey, z = (tv.w & 0xffff) + r / ey;
+        const bool inwave = rlo >= wlo && rhi <= wlo + 64;  // the row lies in this wavefront: rotate
+        const bool has_prev = tid > rlo && tid > wlo, has_next = tid + 1 < rhi && tid + 1 < wlo + 64;
+        const int src_prev = has_prev ? lane - 1 : (inwave ? ((rhi - 1) & 63) : lane);
+        const int src_next = has_next ? lane + 1 : (inwave ? (rlo & 63) : lane);
+        const bool edge_prev = !has_prev && !inwave, edge_next = !has_next && !inwave;
+        // every access is a uniform base (slot and row shift) plus one of
+        // three per-lane byte offsets: the lane's vector, and the elements
+        // one cell before and after it (with the x wrap)
+        const uint32_t row0 = cell_off(B, 0, y, z) * E;
+        const uint32_t ov = row0 + (uint32_t)x0 * E;
+        const uint32_t om1 = row0 + (uint32_t)(x0 == 0 ? n0 - 1 : x0 - 1) * E;
+        const uint32_t opv = row0 + (uint32_t)(x0 + V == n0 ? 0 : x0 + V) * E;
+        const Links<Q> Lk = classify<Q>(0u, B, 0, y, z, a);  // the same for every cell of the row
+        const uint32_t special = Lk.bb | Lk.alo | Lk.ahi;
+        // ---- incoming populations of the lane's cells
+        RowWords v[Q];
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if ((special >> opp(i)) & 1u) {
+                // bounce-back / anti-bounce-back link: the cell's own slot i
+                v[i] = mem_ld<NT>(reinterpret_cast<const RowWords *>(slot_base<ST>(a, B, i) + (uint64_t)ov));
+            } else {
+                const char *base = slot_base<ST>(a, B, opp(i)) -
+                                   (int64_t)(cy<Q>(i) * B.pitch + cz<Q>(i) * B.plane) * (int64_t)E;
+                const RowWords w = mem_ld<NT>(reinterpret_cast<const RowWords *>(base + (uint64_t)ov));
+                if constexpr (cx<Q>(i) == 1) {  // cells x0 - 1 .. x0 + V - 2
+                    Raw in = lane_get<Raw>(row_get<ST>(w, V - 1), src_prev);
+                    if (edge_prev) in = mem_ld<false>(reinterpret_cast<const Raw *>(base + (uint64_t)om1));
+                    v[i] = row_shift_up<ST>(w, in);
+                } else if constexpr (cx<Q>(i) == -1) {  // cells x0 + 1 .. x0 + V
+                    Raw in = lane_get<Raw>(row_get<ST>(w, 0), src_next);
+                    if (edge_next) in = mem_ld<false>(reinterpret_cast<const Raw *>(base + (uint64_t)opv));
+                    v[i] = row_shift_down<ST>(w, in);
+                } else {
+                    v[i] = w;
+                }
+            }
+        });
+        // ---- collide the V cells one after the other
+        const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+        const T drin = (T)(a.rho_in - 1.0), drout = (T)(a.rho_out - 1.0);
+        const CollParams<T> cp = coll_params<T>(a);
+        sfor<V>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            T f[Q];
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                f[i] = dec_slot<Q, ST>(row_get<ST>(v[i], k), i);
+            });
+            const uint32_t h = kStochastic<ST> ? state_hash<Q, T>(f, global_cell(a, B, x0 + k, y, z)) : 0u;
+            const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
+            if (Lk.alo | Lk.ahi) {
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const bool lo = (Lk.alo >> i) & 1u, hi = (Lk.ahi >> i) & 1u;
+                    if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout, lo ? drin : drout);
+                });
+            }
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                row_set<ST>(v[i], k, enc_result<Q, ST>(f[i], i, h));
+            });
+            __builtin_amdgcn_sched_barrier(0);  // one cell's collision at a time
+        });
+        // ---- outgoing populations
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const RowWords w = v[i];
+            if ((special >> i) & 1u) {
+                // bounce-back / anti-bounce-back: slot opp(i) of the cell itself
+                store_vec<ST, NT>(const_cast<char *>(slot_base<ST>(a, B, opp(i))) + (uint64_t)ov, w);
+            } else {
+                char *base = const_cast<char *>(slot_base<ST>(a, B, i)) +
+                             (int64_t)(cy<Q>(i) * B.pitch + cz<Q>(i) * B.plane) * (int64_t)E;
+                if constexpr (cx<Q>(i) == 1) {  // positions x0 .. x0 + V - 1 take cells x0 - 1 .. x0 + V - 2
+                    const RowWords o = row_shift_up<ST>(w, lane_get<Raw>(row_get<ST>(w, V - 1), src_prev));
+                    if (edge_prev)
+                        store_elems<ST, NT>(base + (uint64_t)ov, o, 1, V);  // position x0 comes from the other wave
+                    else
+                        store_vec<ST, NT>(base + (uint64_t)ov, o);
+                    if (edge_next) store_elems<ST, NT>(base + (uint64_t)opv - (V - 1) * E, w, V - 1, V);
+                } else if constexpr (cx<Q>(i) == -1) {  // positions x0 .. x0 + V - 1 take cells x0 + 1 .. x0 + V
+                    const RowWords o = row_shift_down<ST>(w, lane_get<Raw>(row_get<ST>(w, 0), src_next));
+                    if (edge_next)
+                        store_elems<ST, NT>(base + (uint64_t)ov, o, 0, V - 1);  // position x0 + V - 1 comes from the other wave
+                    else
+                        store_vec<ST, NT>(base + (uint64_t)ov, o);
+                    if (edge_prev) store_elems<ST, NT>(base + (uint64_t)om1, w, 0, 1);
+                } else {
+                    store_vec<ST, NT>(base + (uint64_t)ov, w);
+                }
+            }
+        });
     }
 }
 
@@ -1561,10 +1791,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         if (!active) continue;
         if (L.alo | L.ahi) {
             const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+            const T drin = (T)(a.rho_in - 1.0), drout = (T)(a.rho_out - 1.0);
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
-                if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout);
+                if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout, lo ? drin : drout);
             });
         }
         scatter<Q, ST, ODD>(a, B, off, c.x, c.y, c.z, special, f, h);
@@ -1881,6 +2112,17 @@ __global__ __launch_bounds__(kWG) void force_kernel(const SweepArgs a, double *p
 template <int Q, int COLL, bool NT>
 static hipError_t sweep_qn(bool odd, const SweepArgs &a, int grid, hipStream_t st)
 {
+    if (odd && a.vec_odd) {
+        // FP64 only (and the counting storage of the write-coverage check,
+        // 4 cells per lane): with 4- and 2-byte elements a lane would hold 4
+        // or 8 cells, whose registers cut the occupancy to one or two waves
+        if constexpr (sizeof(typename Codec<WLB_STORAGE>::Raw) == 8 || std::is_same_v<WLB_STORAGE, cover_t>) {
+            hipLaunchKernelGGL((sweep_odd_vec_kernel<Q, COLL, WLB_STORAGE, NT>), dim3(grid), dim3(kWG), 0, st, a);
+            return hipGetLastError();
+        } else {
+            return hipErrorNotSupported;
+        }
+    }
     if (odd && a.lds_stride > 0) {
         using Raw = typename Codec<WLB_STORAGE>::Raw;
         const size_t bytes = lds_stage_bytes<Q, Raw>(a.lds_stride);

@@ -13,12 +13,16 @@ constexpr int kMaxQ = 27;
 constexpr int kWG = 256;  // threads per workgroup of every sweep kernel
 
 // Storage of one block in the arena.  Every population slot i is an array
-// s_i[z][y][x] over the block's cells plus one ghost layer on each side,
-// x fastest.  Rows of 256 bytes or more are padded so that interior x = 0
-// starts on a 128-byte boundary (the alignment rule of the paper's Field,
-// Sec. 4.2); shorter rows are packed with only their ghost cells (xoff 1):
-//   element(i, x, y, z) = pop + i * slot + (z + 1) * plane + (y + 1) * pitch + xoff + x
-// for x in [-1, n0], y in [-1, n1], z in [-1, n2].  Read with scalar loads.
+// s_i[z][y][x] over the block's cells, x fastest, with one ghost plane on
+// each z side, one ghost row on each y side when the block exchanges along y
+// (gy = 1; a block with walls on both y faces has none), and x ghost cells
+// only where rows need them.  Rows of 256 bytes or more start interior
+// x = 0 on a 128-byte boundary (the alignment rule of the paper's Field,
+// Sec. 4.2); a block that wraps onto itself along x has no x ghosts at all
+// (xoff 0, rows back to back when the row length is a multiple of 128
+// bytes); shorter rows are packed with only their ghost cells (xoff 1):
+//   element(i, x, y, z) = pop + i * slot + (z + 1) * plane + (y + gy) * pitch + xoff + x
+// for z in [-1, n2], y in [-gy, n1 - 1 + gy].  Read with scalar loads.
 struct DevBlock {
     int64_t pop;    // element index of slot 0, ghost-inclusive origin (row start of y=-1,z=-1)
     int64_t slot;   // elements per population slot
@@ -32,8 +36,10 @@ struct DevBlock {
     int32_t xoff;   // element offset of interior x = 0 within a row
     int32_t wrapx;  // n[0] if the block is its own neighbour along x (periodic), else 0
     int32_t nbx[2]; // other block across the -x / +x face (accessed directly), else -1
+    int32_t gy;     // 1: ghost rows on the y faces (the block exchanges along y), 0: none
+    int32_t pad_;
 };
-static_assert(sizeof(DevBlock) == 80, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 88, "DevBlock layout");
 
 // One tile of a sweep: block id and start/extent (extent <= 256 cells).
 // Packed as int4 {block, x0 | ex << 16, y0 | ey << 16, z0 | ez << 16}.  A
@@ -81,6 +87,9 @@ struct SweepArgs {
     int32_t lds_ring;      // 1: every tile is a whole row of a self-wrapping block (staged sweep without halos)
     int32_t xcd_map;       // 1: one workgroup per tile, each XCD takes a contiguous range of tiles
     int32_t nt;            // 1: the sweep's population accesses carry the non-temporal hint
+    int32_t vec_odd;       // 1: the odd sweep moves whole rows as 16-byte vectors per lane (vtiles)
+    int32_t nvtiles;
+    const int4 *vtiles;    // row tiles of the vector odd sweep: {block, 0 | n0 << 16, y0 | ey << 16, z0 | ez << 16}
     double omega;          // 1 / tau0
     double omega_minus;    // TRT rate of the antisymmetric part at tau0
     double magic;          // TRT Lambda

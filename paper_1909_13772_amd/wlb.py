@@ -219,7 +219,8 @@ def wlb_set_tiles(h, tx, ty, tz, grid):
 
 
 def wlb_set_lds_staging(h, on):
-    _check(_lib.wlb_set_lds_staging(h, 1 if on else 0))
+    """Odd-sweep kernel: False / 0 direct, True / 1 LDS-staged, 2 row vectors."""
+    _check(_lib.wlb_set_lds_staging(h, int(on)))
 
 
 def wlb_set_overlap(h, on):

@@ -62,10 +62,11 @@ def test_create_single_block_layout():
         # packed rows: 32 x 8 x 1 tiles
         assert info.n_tiles == 32 * 32 // 8
         assert info.xchg_elems == _crossing_links((32, 32, 32), (1, 1, 1), 19, xnbr=True)
-        # rows padded: x = 0 on a 128-byte boundary, pitch multiple of 16 doubles
-        pitch = -(-(16 + 32 + 1) // 16) * 16
+        # the block wraps onto itself along x: rows of 32 doubles back to back
+        # (no x ghosts); periodic y and z: one ghost row / plane on each side
+        pitch = 32
         slot = pitch * 34 * 34
-        assert info.pop_bytes >= 19 * slot * 8
+        assert info.pop_bytes == -(-(19 * slot * 8) // 256) * 256
         assert nbytes >= info.pop_bytes
     finally:
         wlb.wlb_blocks_destroy(h)
@@ -78,6 +79,18 @@ def test_exchange_counts_multi_block_periodic_x():
     try:
         info = wlb.wlb_info(h)
         assert info.xchg_elems == 2 * _crossing_links((8, 6, 5), (1, 1, 1), 19, xnbr=True)
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
+def test_walls_get_no_ghost_rows():
+    # walls on both y faces: no ghost rows (nothing is read or written beyond
+    # a wall); x wraps (no x ghosts), z periodic (ghost planes)
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (64, 24, 10))], (64, 24, 10), (1, 0, 1), 19, wlb.F64)
+    try:
+        info = wlb.wlb_info(h)
+        slot = 64 * 24 * 12
+        assert info.pop_bytes == -(-(19 * slot * 8) // 256) * 256
     finally:
         wlb.wlb_blocks_destroy(h)
 

@@ -82,3 +82,31 @@ def test_coverage_check_needs_fp32_storage_and_a_fresh_init():
         B.step(2)
     finally:
         B.close()
+
+
+# Row-vector odd sweep (wlb_set_lds_staging(2)): blocks that wrap onto
+# themselves along x and hold no solid cells.  The counting storage runs it
+# with 4 cells per lane, so these rows cover a row held inside one wavefront
+# (64 cells: 16 lanes, four rows per wavefront), rows straddling wavefront
+# boundaries at odd places (96 cells: 24 lanes), a row of exactly one
+# wavefront (256 cells) and rows spanning two and three wavefronts (512 and
+# 384 cells: the edge lanes read and write the crossing elements).
+@pytest.mark.parametrize("nx", [64, 96, 256, 384, 512])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (15, 0), (9, 1)])
+@pytest.mark.parametrize("odd", [0, 1])
+def test_row_vector_odd_sweep_writes_every_slot_once(nx, q, coll, odd):
+    say(f"case coverage rows nx{nx} q{q} coll{coll} odd{odd}")
+    dom = (nx, 10, 6)
+    rho, u = inputs.uniform_state(dom)
+    # walls in y (no ghost rows), periodic z (ghost planes and exchange),
+    # then blocks split along z that exchange with each other
+    for blocks, periodic in ((wlb.single_block(dom), (1, 0, 1)),
+                             (inputs.rectilinear_blocks([nx], [10], [2, 4])[0], (1, 1, 1))):
+        B = wlb.Blocks(blocks, dom, periodic, stencil=q, storage=wlb.F32)
+        try:
+            B.init(coll, wlb.make_params(tau=0.8, magic=3 / 16, omega_bulk=1.2, force=(1e-5, 0, 0)), rho, u)
+            B.set_lds_staging(2)
+            c = B.write_coverage(odd)
+        finally:
+            B.close()
+        assert c.min() == 1 and c.max() == 1, (periodic, int(c.min()), int(c.max()), int((c != 1).sum()))

@@ -345,7 +345,7 @@ def test_wrapping_and_exchanging_decompositions_agree_bitwise(storage):
     ref = {}
     # odd sweep: direct with the default (whole-row) tiles and over row
     # segments, staged in LDS likewise
-    variants = [dict(), dict(tiles=(8, 4, 4, 0)), dict(lds=True), dict(lds=True, tiles=(8, 4, 4, 0))]
+    variants = [dict(), dict(tiles=(8, 4, 4, 0)), dict(lds=True), dict(lds=True, tiles=(8, 4, 4, 0)), dict(lds=2)]
     for k, bl in enumerate(layouts):
         for kw in variants:
             for steps in (8, 9):  # ends in the natural and in the swapped layout
@@ -471,3 +471,39 @@ def test_totals_match_fsum_of_fields():
     px = math.fsum(rr * uu[0].reshape(-1)[fl])
     assert abs(tot[1] - px) <= 1e-15 * max(1.0, abs(px)) + 1e-18
     assert tot[7] == 5
+
+
+@pytest.mark.parametrize("nx", [64, 96, 256, 384, 512])
+@pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (27, 4), (15, 0), (9, 1)])
+def test_row_vector_odd_sweep_fp64_vs_oracle_and_direct(nx, q, coll):
+    """The row-vector odd sweep (two FP64 cells per lane, x shift by lane
+    moves): rows inside one wavefront (64 and 96 cells), rows of two and
+    three wavefronts (256, 384) and of a whole workgroup (512), walls in y
+    with a body force, then density faces in y; against the oracle and
+    bitwise against the direct odd sweep.  Blocks split along y and z
+    exchange with each other."""
+    say(f"case rows nx{nx} q{q} coll{coll}")
+    dom = (nx, 12, 6)
+    rho, u = inputs.random_state(dom, seed=nx + q, umag=0.02)
+    u, F = _plane(q, u, (1e-5, 0, -2e-6))
+    cases = [("walls", wlb.single_block(dom), (1, 0, 1), dict(force=F)),
+             ("density", wlb.single_block(dom), (1, 0, 1), dict(pressure_axis=1, rho_in=1.003, rho_out=0.998)),
+             ("blocks", inputs.rectilinear_blocks([nx], [5, 7], [2, 4])[0], (1, 1, 1), dict(force=F))]
+    for name, blocks, periodic, extra in cases:
+        kw = dict(tau=0.7, magic=3 / 16, omega_bulk=1.2, omega_higher=1.1, **extra)
+        p = wlb.make_params(**kw)
+        runs = []
+        for lds in (2, 0):
+            d, r, uu, tot, B = gpu_run(blocks, dom, periodic, q, wlb.F64, coll, p, rho, u, steps=7, lds=lds)
+            assert B.info().lds_staging == lds, (name, lds)
+            B.close()
+            runs.append((d, r, uu))
+        assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][2], runs[1][2]), name
+        op = oracle_params(q, coll, 0.7, 3 / 16, periodic, extra.get("force", (0, 0, 0)),
+                           pressure_axis=extra.get("pressure_axis", -1), rho_in=extra.get("rho_in", 1.0),
+                           rho_out=extra.get("rho_out", 1.0), omega_bulk=1.2, omega_higher=1.1)
+        do, ro, uo, to = oracle_run(op, dom, rho, u, None, 7)
+        eu = rel_l2(runs[0][2].reshape(3, -1), uo)
+        ep = pop_err(runs[0][0], do, q)
+        say(f"rows nx{nx} q{q} c{coll} {name}: u rel L2 {eu:.3e}, pops {ep:.3e}")
+        assert eu <= 1e-12 and ep <= 1e-12, (name, eu, ep)
