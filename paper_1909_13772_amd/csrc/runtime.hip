@@ -878,64 +878,106 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
         }
     }
     // --- arena layout
+    // Blocks that follow each other along x with the same y-z extent (an
+    // x-row of a rectilinear block grid) share their population rows: row
+    // (y, z) of each slot holds the cells of all blocks of the run side by
+    // side, so a row of the domain is one contiguous stretch of memory.  The
+    // blocks stay separate containers (own descriptor, tiles, masks, y/z
+    // exchange); a population crossing an x face between two blocks of a
+    // run is simply the next element of the row.  A run that spans a
+    // periodic x axis wraps inside its row (no x ghost cells).
     const int align_e = 128 / h->esize;
     size_t elems = 0;
     size_t mwords = 0;
     h->dev.resize(n);
+    std::vector<int> run_of(n, -1);
+    std::vector<std::vector<int>> runs;
     for (int b = 0; b < n; ++b) {
-        const HostBlock &B = h->blocks[b];
-        DevBlock &D = h->dev[b];
-        std::memset(&D, 0, sizeof D);
+        if (run_of[b] >= 0) continue;
+        // first block of the run: walk -x while the neighbour is adjacent
+        // without wrapping (the face check above gives it the same y-z extent)
+        int s0 = b;
+        for (int guard = 0; guard < n; ++guard) {
+            const int m = h->blocks[s0].nbr[12];
+            if (m < 0 || m == s0 || h->blocks[m].org[0] + h->blocks[m].n[0] != h->blocks[s0].org[0]) break;
+            s0 = m;
+        }
+        std::vector<int> r{s0};
+        for (int guard = 0; guard < n; ++guard) {
+            const int c = r.back(), m = h->blocks[c].nbr[14];
+            if (m < 0 || m == c || h->blocks[m].org[0] != h->blocks[c].org[0] + h->blocks[c].n[0]) break;
+            r.push_back(m);
+        }
+        for (int m : r) run_of[m] = (int)runs.size();
+        runs.push_back(r);
+    }
+    for (const std::vector<int> &r : runs) {
+        const HostBlock &F = h->blocks[r.front()], &Lb = h->blocks[r.back()];
+        int W = 0, gy = 0;
+        for (int m : r) {
+            W += h->blocks[m].n[0];
+            if (h->blocks[m].nbr[10] >= 0 || h->blocks[m].nbr[16] >= 0) gy = 1;
+        }
+        // the run wraps onto itself across a periodic x axis
+        const bool wraps = F.nbr[12] == r.back() && Lb.nbr[14] == r.front() && F.org[0] == 0 && W == domain[0];
         // Rows of at least 256 bytes start interior x = 0 on a 128-byte
         // boundary (whole lines per wave).  Shorter rows are packed with just
         // their two ghost cells: a wave then covers several rows of nearly
         // contiguous memory instead of touching a mostly empty line per row
-        // and another for each ghost cell.  A block that wraps onto itself
-        // along x never touches an x ghost cell (the kernels wrap inside the
-        // row), so its aligned rows carry no x padding at all.  Ghost rows
-        // exist only along a y face with a neighbour: beyond a wall nothing
-        // is read or written (bounce-back links use the cell's own slots).
-        // Rows and planes without padding keep the sweeps' streams
+        // and another for each ghost cell.  A run that wraps never touches an
+        // x ghost cell, so its aligned rows carry no x padding at all.  Ghost
+        // rows exist only along a y face with a neighbour: beyond a wall
+        // nothing is read or written (bounce-back links use the cell's own
+        // slots).  Rows and planes without padding keep the sweeps' streams
         // contiguous, which measurably raises the achieved bandwidth.
-        const bool packed = (size_t)B.n[0] * h->esize < 256;
-        const bool selfx = B.nbr[12] == b && B.nbr[14] == b;
-        D.gy = (B.nbr[10] >= 0 || B.nbr[16] >= 0) ? 1 : 0;
-        D.xoff = packed ? 1 : (selfx ? 0 : align_e);
-        D.pitch = packed ? B.n[0] + 2
-                         : (int32_t)(selfx ? round_up((size_t)B.n[0], align_e)
-                                           : round_up((size_t)align_e + B.n[0] + 1, align_e));
-        const int64_t plane = (int64_t)D.pitch * (B.n[1] + 2 * D.gy);
+        const bool packed = (size_t)W * h->esize < 256;
+        const int xoff = packed ? 1 : (wraps ? 0 : align_e);
+        const int pitch = packed ? W + 2
+                                 : (int32_t)(wraps ? round_up((size_t)W, align_e) : round_up((size_t)align_e + W + 1, align_e));
+        const int64_t plane = (int64_t)pitch * (F.n[1] + 2 * gy);
         // Large slots start 16 MiB apart: the sweeps stream all q slots at
         // the same cell offset at once, and on MI355X the achieved bandwidth
         // of that access pattern depends on the slots' stride; strides that
         // are multiples of 16 MiB measured best (the even sweep's pattern
         // over a 256^3 FP64 block: 0.83 ms at 144 MiB against 0.96 ms at
         // the unpadded 129 MiB).  Smaller slots are only aligned.
-        int64_t slot = (int64_t)round_up((size_t)(plane * (B.n[2] + 2)), align_e);
+        int64_t slot = (int64_t)round_up((size_t)(plane * (F.n[2] + 2)), align_e);
         if (slot * h->esize >= ((int64_t)64 << 20)) slot = (int64_t)round_up((size_t)slot * h->esize, (size_t)16 << 20) / h->esize;
         if (slot * h->esize >= (int64_t)1 << 31) {
             delete h;
-            return fail(WLB_ERR_ARG, "block %d too large: one population slot must stay below 2 GiB", b);
+            return fail(WLB_ERR_ARG, "block %d too large: one population slot must stay below 2 GiB", r.front());
         }
-        D.plane = (int32_t)plane;
-        D.slot = slot;
-        D.pop = (int64_t)elems;
+        const int64_t pop = (int64_t)elems;
         elems += (size_t)slot * stencil;
-        for (int a = 0; a < 3; ++a) {
-            D.n[a] = B.n[a];
-            D.g[a] = B.org[a];
+        for (size_t k = 0; k < r.size(); ++k) {
+            const int b = r[k];
+            const HostBlock &B = h->blocks[b];
+            DevBlock &D = h->dev[b];
+            std::memset(&D, 0, sizeof D);
+            D.gy = gy;
+            D.xoff = xoff + (B.org[0] - F.org[0]);
+            D.pitch = pitch;
+            D.plane = (int32_t)plane;
+            D.slot = slot;
+            D.pop = pop;
+            for (int a = 0; a < 3; ++a) {
+                D.n[a] = B.n[a];
+                D.g[a] = B.org[a];
+            }
+            // x accesses of the run's end cells wrap by the run's length
+            D.wraplo = (wraps && k == 0) ? W : 0;
+            D.wraphi = (wraps && k + 1 == r.size()) ? W : 0;
+            // a block that is its own neighbour on both x faces (a run of one)
+            D.wrapx = (wraps && r.size() == 1) ? B.n[0] : 0;
+            // blocks across an x face outside the run (none for a valid
+            // rectilinear grid): read and written through their own descriptor
+            D.nbx[0] = (B.nbr[12] >= 0 && run_of[B.nbr[12]] != run_of[b]) ? B.nbr[12] : -1;
+            D.nbx[1] = (B.nbr[14] >= 0 && run_of[B.nbr[14]] != run_of[b]) ? B.nbr[14] : -1;
+            D.mpitch = (int32_t)round_up(B.n[0], 32);
+            D.mplane = D.mpitch * B.n[1];
+            D.mask = (int64_t)mwords;  // provisional; -1 if the block has no solid nearby (set at init)
+            mwords += (size_t)D.mplane * B.n[2];
         }
-        // a block that is its own neighbour on both x faces wraps its x
-        // accesses in the kernels and takes no part in x exchanges
-        D.wrapx = (B.nbr[12] == b && B.nbr[14] == b) ? B.n[0] : 0;
-        // other blocks across the x faces: read and written directly by the
-        // kernels, so x crossings never go through ghost columns
-        D.nbx[0] = (B.nbr[12] >= 0 && B.nbr[12] != b) ? B.nbr[12] : -1;
-        D.nbx[1] = (B.nbr[14] >= 0 && B.nbr[14] != b) ? B.nbr[14] : -1;
-        D.mpitch = (int32_t)round_up(B.n[0], 32);
-        D.mplane = D.mpitch * B.n[1];
-        D.mask = (int64_t)mwords;  // provisional; -1 if the block has no solid nearby (set at init)
-        mwords += (size_t)D.mplane * B.n[2];
     }
     size_t off = 0;
     h->off_pop = off;

@@ -1118,21 +1118,21 @@ __device__ __forceinline__ Alt<ST> alt_out(const SweepArgs &a, const DevBlock &B
 }
 
 // Byte offsets of a cell for regular accesses shifted by 0, -1 and +1 cells
-// along x.  A block that is its own neighbour along x (one block spanning a
-// periodic axis) has no x exchange: the odd sweep and every reader of the
-// swapped layout wrap the shifted accesses around the block instead, so that
-// the sweep writes whole cache lines at both row ends.
+// along x.  Blocks of one x-run share their rows, so a shifted access across
+// an x face inside the run is the next element of the row.  A run that spans
+// a periodic axis has no x exchange: the odd sweep and every reader of the
+// swapped layout wrap the shifted accesses of its end cells around the row
+// instead, so that the sweep writes whole cache lines at both row ends.
 struct XOff {
     uint32_t at, left, right;
 };
 template <typename ST>
 __device__ __forceinline__ XOff xoffsets(const DevBlock &B, uint32_t off, int x)
 {
-    const uint32_t w = (uint32_t)B.wrapx * (uint32_t)sizeof(ST);
     XOff o;
     o.at = off * (uint32_t)sizeof(ST);
-    o.left = o.at + (x == 0 ? w : 0u);
-    o.right = o.at - (x == B.n[0] - 1 ? w : 0u);
+    o.left = o.at + (x == 0 ? (uint32_t)B.wraplo * (uint32_t)sizeof(ST) : 0u);
+    o.right = o.at - (x == B.n[0] - 1 ? (uint32_t)B.wraphi * (uint32_t)sizeof(ST) : 0u);
     return o;
 }
 // Offset of the regular access shifted by dx in {-1, 0, 1} cells along x.

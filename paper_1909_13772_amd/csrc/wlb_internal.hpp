@@ -12,7 +12,10 @@ namespace wlb {
 constexpr int kMaxQ = 27;
 constexpr int kWG = 256;  // threads per workgroup of every sweep kernel
 
-// Storage of one block in the arena.  Every population slot i is an array
+// Storage of one block in the arena.  Blocks that follow each other along x
+// with the same y-z extent (an x-run) share their rows: row (y, z) holds the
+// run's blocks side by side, and each block's xoff is its place in the row.
+// Every population slot i is an array
 // s_i[z][y][x] over the block's cells, x fastest, with one ghost plane on
 // each z side, one ghost row on each y side when the block exchanges along y
 // (gy = 1; a block with walls on both y faces has none), and x ghost cells
@@ -35,11 +38,13 @@ struct DevBlock {
     int32_t mplane; // mask elements per plane
     int32_t xoff;   // element offset of interior x = 0 within a row
     int32_t wrapx;  // n[0] if the block is its own neighbour along x (periodic), else 0
-    int32_t nbx[2]; // other block across the -x / +x face (accessed directly), else -1
+    int32_t nbx[2]; // other block across the -x / +x face outside the block's x-run, else -1
     int32_t gy;     // 1: ghost rows on the y faces (the block exchanges along y), 0: none
+    int32_t wraplo; // elements added to an access one cell below x = 0 (the run wraps), else 0
+    int32_t wraphi; // elements subtracted from an access one cell above x = n0 - 1, else 0
     int32_t pad_;
 };
-static_assert(sizeof(DevBlock) == 88, "DevBlock layout");
+static_assert(sizeof(DevBlock) == 96, "DevBlock layout");
 
 // One tile of a sweep: block id and start/extent (extent <= 256 cells).
 // Packed as int4 {block, x0 | ex << 16, y0 | ey << 16, z0 | ez << 16}.  A

@@ -95,6 +95,28 @@ def test_walls_get_no_ghost_rows():
         wlb.wlb_blocks_destroy(h)
 
 
+def test_blocks_of_an_x_run_share_their_rows():
+    # two blocks side by side along a periodic x axis: one run of 64 cells,
+    # rows back to back (the run wraps, no x ghosts), one set of slots
+    blocks = [((0, 0, 0), (24, 8, 6)), ((24, 0, 0), (40, 8, 6))]
+    h, _ = wlb.wlb_blocks_create(blocks, (64, 8, 6), (1, 1, 1), 19, wlb.F64)
+    try:
+        info = wlb.wlb_info(h)
+        slot = 64 * 10 * 8
+        assert info.pop_bytes == -(-(19 * slot * 8) // 256) * 256
+    finally:
+        wlb.wlb_blocks_destroy(h)
+    # not periodic in x: the run keeps one aligned ghost margin on each side
+    h, _ = wlb.wlb_blocks_create(blocks, (64, 8, 6), (0, 1, 1), 19, wlb.F64)
+    try:
+        info = wlb.wlb_info(h)
+        pitch = -(-(16 + 64 + 1) // 16) * 16
+        slot = pitch * 10 * 8
+        assert info.pop_bytes == -(-(19 * slot * 8) // 256) * 256
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
 def test_short_rows_are_packed():
     # 16 FP32 cells = 64-byte rows: pitch n + 2, no alignment padding
     h, _ = wlb.wlb_blocks_create([((0, 0, 0), (16, 16, 16))], (16, 16, 16), (1, 1, 1), 19, wlb.F32)
