@@ -37,8 +37,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 N = 256
 TAU, MAGIC, FX = 0.8, 3.0 / 16.0, 1e-6
+# the sweep kernels and the arena layout (runtime.hip) decide the HBM traffic
 SWEEP_SOURCES = ["paper_1909_13772_amd/csrc/sweep_impl.hpp", "paper_1909_13772_amd/csrc/lattice.hpp",
-                 "paper_1909_13772_amd/csrc/wlb_internal.hpp"]
+                 "paper_1909_13772_amd/csrc/wlb_internal.hpp", "paper_1909_13772_amd/csrc/runtime.hip"]
 
 
 def sweep_source_hash() -> str:
@@ -75,6 +76,16 @@ def closure_weights(inputs):
     return inputs.mlp_params(0, inv_std=[300.0] * 6 + [100.0], out_bias=-4.0)
 
 
+def VARIANTS(wlb):
+    """(name, storage, element bytes, closure, velocity set, collision) of the
+    variants timed on the headline channel."""
+    return (("f32", wlb.F32, 4, 0, 19, None), ("f16dev", wlb.F16DEV, 2, 0, 19, None),
+            ("bf16dev", wlb.BF16DEV, 2, 0, 19, None), ("f32_smagorinsky", wlb.F32, 4, 1, 19, None),
+            ("f32_mlp_closure", wlb.F32, 4, 2, 19, None), ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT),
+            ("f32_d3q27_kbc", wlb.F32, 4, 0, 27, wlb.KBC), ("f32_d3q27_cumulant", wlb.F32, 4, 0, 27, wlb.CUMULANT),
+            ("f32_d3q15", wlb.F32, 4, 0, 15, None), ("f32_d2q9_planes", wlb.F32, 4, 0, 9, None))
+
+
 def poiseuille_series(H, nu, g, T, s):
     u = g * s * (H - s) / (2 * nu)
     for n in range(1, 4000, 2):
@@ -99,7 +110,7 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
     try:
         B.init(wlb.TRT if coll is None else coll, p, rho, u)
         if lds is not None:  # fixed odd-sweep choice (profiler runs without the autotuner)
-            B.set_lds_staging(bool(lds))
+            B.set_lds_staging(int(lds))
         if nt is not None:  # fixed non-temporal choice per parity (profiler runs)
             B.set_nontemporal(*nt)
         B.step(warmup)
@@ -255,14 +266,20 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
-    ap.add_argument("--lds-staging", type=int, choices=[0, 1], default=None,
-                    help="with --no-autotune: odd sweep staged in LDS (1) or direct (0) for the headline run")
+    ap.add_argument("--lds-staging", type=int, choices=[0, 1, 2], default=None,
+                    help="with --no-autotune: odd sweep direct (0), staged in LDS (1) or over row vectors (2)")
     ap.add_argument("--nontemporal", type=str, default=None,
                     help="with --no-autotune: 'E,O' non-temporal accesses (1) or cached (0) in the even / odd sweep "
                          "(headline and variant runs)")
-    ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic", "matrix"],
+    ap.add_argument("--tiles", type=str, default=None,
+                    help="with --no-autotune: 'tx,ty,tz,grid' launch configuration of the porous workload")
+    ap.add_argument("--variant", type=str, default="f32_mlp_closure",
+                    help="with --workload variant: the variant configuration to run alone")
+    ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic", "matrix",
+                                           "variant"],
                     default="channel",
-                    help="channel = the headline configuration; the others print their own JSON line")
+                    help="channel = the headline configuration; variant = one of its variants alone (for "
+                         "profiler runs); the others print their own JSON line")
     ap.add_argument("--tau", type=float, default=0.5005, help="relaxation time of the turbulence workload")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -275,10 +292,28 @@ def main():
 
     torch.cuda.set_device(0)
     print(f"[bench] device {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    if args.workload == "variant":
+        cfg = {v[0]: v[1:] for v in VARIANTS(wlb)}
+        if args.variant not in cfg:
+            print(f"unknown variant {args.variant}; one of {sorted(cfg)}", file=sys.stderr)
+            sys.exit(2)
+        st, eb, cl, q, coll = cfg[args.variant]
+        nt = None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")]
+        r = run_config(wlb, inputs, st, args.steps, args.warmup, closure=cl, autotune=not args.no_autotune, q=q,
+                       coll=coll, lds=args.lds_staging, nt=nt if args.no_autotune else None)
+        sm = summarize(r, st, args.steps, eb, q=q)
+        print(json.dumps({"workload": f"channel 256^3 variant {args.variant}", "steps": args.steps,
+                          "mlups": sm["mlups"], "even_ms": sm["even_ms"], "odd_ms": sm["odd_ms"],
+                          "achieved_gbs": sm["achieved_gbs"], "roofline_frac": sm["frac"], "tile": r["tile"],
+                          "grid": r["grid"], "nt": r["nt"], "odd_sweep": r["lds_staging"]}))
+        return
     if args.workload != "channel":
         from paper_1909_13772_amd import workloads
         if args.workload == "porous":
-            r = workloads.porous(wlb, steps=args.steps, warmup=args.warmup, autotune=not args.no_autotune)
+            tiles = None if args.tiles is None else [int(v) for v in args.tiles.split(",")]
+            nt = None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")]
+            r = workloads.porous(wlb, steps=args.steps, warmup=args.warmup, autotune=not args.no_autotune,
+                                 tiles=tiles if args.no_autotune else None, nt=nt if args.no_autotune else None)
         elif args.workload == "turbulence":
             r = workloads.turbulence_precision(wlb, steps=args.steps, tau=args.tau)
         elif args.workload == "entropic":
@@ -302,15 +337,7 @@ def main():
         import numpy as np
         r64 = run_config(wlb, inputs, wlb.F64, args.variant_steps, args.warmup, check=True, autotune=False)
         p64 = r64["profile"]
-        for name, st, eb, cl, q, coll in (("f32", wlb.F32, 4, 0, 19, None), ("f16dev", wlb.F16DEV, 2, 0, 19, None),
-                                          ("bf16dev", wlb.BF16DEV, 2, 0, 19, None),
-                                          ("f32_smagorinsky", wlb.F32, 4, 1, 19, None),
-                                          ("f32_mlp_closure", wlb.F32, 4, 2, 19, None),
-                                          ("f32_d3q27_mrt", wlb.F32, 4, 0, 27, wlb.MRT),
-                                          ("f32_d3q27_kbc", wlb.F32, 4, 0, 27, wlb.KBC),
-                                          ("f32_d3q27_cumulant", wlb.F32, 4, 0, 27, wlb.CUMULANT),
-                                          ("f32_d3q15", wlb.F32, 4, 0, 15, None),
-                                          ("f32_d2q9_planes", wlb.F32, 4, 0, 9, None)):
+        for name, st, eb, cl, q, coll in VARIANTS(wlb):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
                            q=q, coll=coll, check=True, nt=head_nt if args.no_autotune else None)
             sm = summarize(r, st, args.variant_steps, eb, q=q)

@@ -43,7 +43,8 @@ def _timed_steps(B, steps, warmup, kernel_steps=None):
     return t1 - t0, ms, cnt
 
 
-def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0, seed_spheres=1, overlap=None):
+def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0, seed_spheres=1, overlap=None,
+           tiles=None, nt=None):
     """512 uneven blocks (rectilinear 8x8x8, edges from {16,24,32,48,64}),
     random spheres (radius 3-8, solid fraction >= 0.3), D3Q27 MRT, tau 0.8,
     density faces on x (1.0005 / 0.9995), periodic y/z, FP32 storage."""
@@ -60,6 +61,10 @@ def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0
         B.init(wlb.MRT, p, rho, u, solid)
         if overlap is not None:  # override the autotuner's choice
             B.set_overlap(overlap)
+        if tiles is not None:  # fixed launch configuration (profiler runs without the autotuner)
+            B.set_tiles(*tiles)
+        if nt is not None:
+            B.set_nontemporal(*nt)
         # per-kernel events over the timed steps, as for the channel, unless
         # the sweep parts run concurrently (then timed in a separate run)
         secs, ms, cnt = _timed_steps(B, steps, warmup, kernel_steps=50 if B.info().overlap else None)
