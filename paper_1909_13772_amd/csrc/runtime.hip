@@ -62,7 +62,15 @@ struct wlb_blocks {
     int q = 19, storage = 0, esize = 8;
     int dom[3] = {0, 0, 0}, periodic[3] = {0, 0, 0};
     std::vector<HostBlock> blocks;
+    // Blocks that follow each other along x with the same y-z extent form an
+    // x-run and share their population rows.  dev[0, n) describes the
+    // blocks (exchange, coverage), dev[n + r] run r as one block: every
+    // tile-based kernel works on runs, so a tile's rows are whole stretches
+    // of a domain row instead of the pieces that fall into one block.
     std::vector<DevBlock> dev;
+    int nblk = 0;
+    std::vector<std::vector<int>> runs;
+    std::vector<HostBlock> rhost;  // extent and y/z neighbour flags of each run
     std::vector<TileHost> tiles;
     std::vector<XItem> pull, push;
     int64_t ncells = 0, nfluid = 0, xchg_elems = 0;
@@ -184,8 +192,9 @@ void build_tiles(const wlb_blocks *h, int tx, int ty, int tz, std::vector<TileHo
 {
     out.clear();
     std::vector<TileHost> outer;
-    for (int b = 0; b < (int)h->blocks.size(); ++b) {
-        const HostBlock &B = h->blocks[b];
+    for (int r = 0; r < (int)h->rhost.size(); ++r) {
+        const HostBlock &B = h->rhost[r];
+        const int b = h->nblk + r;
         if (!split) {
             tile_region(B, b, tx, ty, tz, 0, B.n[1], 0, B.n[2], out);
             continue;
@@ -225,7 +234,7 @@ void update_lds_stride(wlb_blocks *h)
     bool ring = true;
     for (const TileHost &t : h->tiles) {
         stride = std::max(stride, t.ey * t.ez * (t.ex + 2));
-        ring = ring && t.ex == h->blocks[t.b].n[0] && h->dev[t.b].wrapx != 0;
+        ring = ring && t.ex == h->dev[t.b].n[0] && h->dev[t.b].wrapx != 0;
     }
     h->args.lds_ring = ring ? 1 : 0;
     int nsh = 0;  // populations with c_x != 0 (the staged ones)
@@ -243,19 +252,19 @@ void update_lds_stride(wlb_blocks *h)
 int row_vec(const wlb_blocks *h) { return 16 / h->esize; }
 
 // Row tiles of the vector odd sweep (after the masks are known).  A tile is
-// floor(256 / (n0 / V)) rows of one block along y.
+// floor(256 / (W / V)) rows of one x-run (row length W) along y.
 int build_vtiles(wlb_blocks *h)
 {
     const int V = row_vec(h);
-    h->vec_ok = h->params.closure != WLB_CLOSURE_MLP && !h->blocks.empty();
-    for (size_t b = 0; b < h->blocks.size() && h->vec_ok; ++b) {
+    h->vec_ok = h->params.closure != WLB_CLOSURE_MLP && !h->rhost.empty();
+    for (size_t b = h->nblk; b < h->dev.size() && h->vec_ok; ++b) {
         const DevBlock &D = h->dev[b];
         const int L = D.n[0] / V;
         if (D.wrapx == 0 || D.mask >= 0 || D.xoff != 0 || D.n[0] % V != 0 || L > kWG || L < 1) h->vec_ok = false;
     }
     h->vtiles.clear();
     if (!h->vec_ok) return WLB_OK;
-    for (size_t b = 0; b < h->blocks.size(); ++b) {
+    for (size_t b = h->nblk; b < h->dev.size(); ++b) {
         const DevBlock &D = h->dev[b];
         const int R = kWG / (D.n[0] / V);
         for (int z = 0; z < D.n[2]; ++z)
@@ -890,8 +899,10 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     size_t elems = 0;
     size_t mwords = 0;
     h->dev.resize(n);
+    h->nblk = n;
     std::vector<int> run_of(n, -1);
-    std::vector<std::vector<int>> runs;
+    std::vector<std::vector<int>> &runs = h->runs;
+    std::vector<DevBlock> rdev;
     for (int b = 0; b < n; ++b) {
         if (run_of[b] >= 0) continue;
         // first block of the run: walk -x while the neighbour is adjacent
@@ -973,12 +984,38 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
             // rectilinear grid): read and written through their own descriptor
             D.nbx[0] = (B.nbr[12] >= 0 && run_of[B.nbr[12]] != run_of[b]) ? B.nbr[12] : -1;
             D.nbx[1] = (B.nbr[14] >= 0 && run_of[B.nbr[14]] != run_of[b]) ? B.nbr[14] : -1;
-            D.mpitch = (int32_t)round_up(B.n[0], 32);
-            D.mplane = D.mpitch * B.n[1];
-            D.mask = (int64_t)mwords;  // provisional; -1 if the block has no solid nearby (set at init)
-            mwords += (size_t)D.mplane * B.n[2];
         }
+        // the run as one block: the first member's rows with the run's length,
+        // its x ends and the run's mask, of which every member sees its part
+        DevBlock R = h->dev[r.front()];
+        R.n[0] = W;
+        R.xoff = xoff;
+        R.wrapx = wraps ? W : 0;
+        R.wraplo = R.wraphi = wraps ? W : 0;
+        R.nbx[0] = h->dev[r.front()].nbx[0];
+        R.nbx[1] = h->dev[r.back()].nbx[1];
+        R.mpitch = (int32_t)round_up(W, 32);
+        R.mplane = R.mpitch * F.n[1];
+        R.mask = (int64_t)mwords;  // provisional; -1 if the run has no solid nearby (set at init)
+        mwords += (size_t)R.mplane * F.n[2];
+        for (int m : r) {
+            DevBlock &D = h->dev[m];
+            D.mpitch = R.mpitch;
+            D.mplane = R.mplane;
+            D.mask = R.mask + (h->blocks[m].org[0] - F.org[0]);
+        }
+        rdev.push_back(R);
+        HostBlock RH = F;
+        RH.n[0] = W;
+        for (int k = 0; k < 27; ++k) RH.nbr[k] = -1;
+        RH.nbr[12] = F.nbr[12];
+        RH.nbr[14] = Lb.nbr[14];
+        for (int m : r)
+            for (int k : {4, 10, 16, 22})
+                if (h->blocks[m].nbr[k] >= 0) RH.nbr[k] = h->blocks[m].nbr[k];
+        h->rhost.push_back(RH);
     }
+    h->dev.insert(h->dev.end(), rdev.begin(), rdev.end());
     size_t off = 0;
     h->off_pop = off;
     h->pop_bytes = round_up(elems * h->esize, 256);
@@ -987,7 +1024,7 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     h->mask_words = mwords;
     off += round_up(mwords * 4, 256);
     h->off_blocks = off;
-    off += round_up(n * sizeof(DevBlock), 256);
+    off += round_up(h->dev.size() * sizeof(DevBlock), 256);
     size_t cap = 0;
     for (const auto &s : kShapes)
         cap = std::max(cap, std::max(count_tiles(h, s[0], s[1], s[2]), count_tiles(h, s[0], s[1], s[2], true)));
@@ -996,18 +1033,18 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     off += round_up(cap * sizeof(int4), 256);
     // fluid-cell lists (every interior cell at most once) and their tiles
     h->list_ok = true;
-    for (const HostBlock &B : h->blocks)
+    for (const HostBlock &B : h->rhost)
         if (B.n[0] > 1024 || B.n[1] > 1024 || B.n[2] > 4096) h->list_ok = false;
     if (h->list_ok) {
         h->off_cells = off;
         off += round_up((size_t)h->ncells * 4, 256);
-        h->ltile_cap = (size_t)h->ncells / kWG + 2 * (size_t)n + 1;  // interior and frontier lists per block
+        h->ltile_cap = (size_t)h->ncells / kWG + 2 * h->rhost.size() + 1;  // interior and frontier lists per run
         h->off_ltiles = off;
         off += round_up(h->ltile_cap * sizeof(int4), 256);
     }
     // row tiles of the vector odd sweep (at most one per row)
     h->vtile_cap = 1;
-    for (const HostBlock &B : h->blocks) h->vtile_cap += (size_t)B.n[1] * B.n[2];
+    for (const HostBlock &B : h->rhost) h->vtile_cap += (size_t)B.n[1] * B.n[2];
     h->off_vtiles = off;
     off += round_up(h->vtile_cap * sizeof(int4), 256);
     // --- exchange work lists
@@ -1195,9 +1232,9 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
         for (int64_t k = 0; k < N; ++k) nsolid += solid[k] ? 1 : 0;
     h->nfluid = N - nsolid;
     int64_t mwords = 0;
-    for (size_t b = 0; b < h->blocks.size(); ++b) {
-        const HostBlock &B = h->blocks[b];
-        DevBlock &D = h->dev[b];
+    for (size_t r = 0; r < h->rhost.size(); ++r) {
+        const HostBlock &B = h->rhost[r];
+        DevBlock &D = h->dev[h->nblk + r];
         bool need = false;
         if (solid && nsolid > 0) {
             for (int z = -1; z <= B.n[2] && !need; ++z)
@@ -1217,6 +1254,8 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
         }
         D.mask = need ? mwords : -1;
         mwords += (int64_t)D.mplane * B.n[2];
+        for (int m : h->runs[r])
+            h->dev[m].mask = need ? D.mask + (h->blocks[m].org[0] - B.org[0]) : -1;
     }
     HIPCHK(hipMemcpyAsync(h->arena + h->off_blocks, h->dev.data(), h->dev.size() * sizeof(DevBlock),
                           hipMemcpyHostToDevice, h->stream));
@@ -1237,8 +1276,9 @@ int wlb_lbm_init(wlb_blocks_t h, int32_t collision, const wlb_lbm_params *p, con
         std::vector<uint32_t> cells;
         cells.reserve((size_t)h->nfluid);
         for (int pass = 0; pass < 2; ++pass) {
-            for (size_t b = 0; b < h->blocks.size(); ++b) {
-                const HostBlock &B = h->blocks[b];
+            for (size_t r = 0; r < h->rhost.size(); ++r) {
+                const HostBlock &B = h->rhost[r];
+                const int b = h->nblk + (int)r;
                 int y0, y1, z0, z1;
                 interior_rows(B, y0, y1, z0, z1);
                 const size_t first = cells.size();
@@ -1425,13 +1465,15 @@ int wlb_debug_write_coverage(wlb_blocks_t h, int32_t odd, uint32_t *counts)
     HIPCHK(hipStreamSynchronize(h->stream));
     const int64_t nx = h->dom[0], ny = h->dom[1], N = nx * ny * h->dom[2];
     std::fill(counts, counts + (int64_t)h->q * N, 0u);
-    for (const DevBlock &B : h->dev)
+    for (int b = 0; b < h->nblk; ++b) {
+        const DevBlock &B = h->dev[b];
         for (int i = 0; i < h->q; ++i)
             for (int z = 0; z < B.n[2]; ++z)
                 for (int y = 0; y < B.n[1]; ++y)
                     for (int x = 0; x < B.n[0]; ++x)
                         counts[i * N + ((int64_t)(B.g[2] + z) * ny + B.g[1] + y) * nx + B.g[0] + x] =
                             raw[B.pop + i * B.slot + (int64_t)(z + 1) * B.plane + (int64_t)(y + B.gy) * B.pitch + B.xoff + x];
+    }
     return WLB_OK;
 }
 

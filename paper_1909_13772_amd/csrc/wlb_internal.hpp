@@ -25,7 +25,12 @@ constexpr int kWG = 256;  // threads per workgroup of every sweep kernel
 // (xoff 0, rows back to back when the row length is a multiple of 128
 // bytes); shorter rows are packed with only their ghost cells (xoff 1):
 //   element(i, x, y, z) = pop + i * slot + (z + 1) * plane + (y + gy) * pitch + xoff + x
-// for z in [-1, n2], y in [-gy, n1 - 1 + gy].  Read with scalar loads.
+// for z in [-1, n2], y in [-gy, n1 - 1 + gy].  Besides one descriptor per
+// block (used by the ghost exchange), each x-run has a descriptor of its own
+// that describes the run as one block (row length W = sum of its blocks' n0,
+// the run's x ends and mask); the sweeps and every other tile-based kernel
+// work on those, so a tile covers whole stretches of domain rows.  A block's
+// mask is its part of the run's mask.  Read with scalar loads.
 struct DevBlock {
     int64_t pop;    // element index of slot 0, ghost-inclusive origin (row start of y=-1,z=-1)
     int64_t slot;   // elements per population slot
