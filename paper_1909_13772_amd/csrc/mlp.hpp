@@ -61,15 +61,18 @@ __host__ __device__ constexpr int mlp_unit(int j, int h) { return 8 * (j / 4) + 
 __device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 __device__ __forceinline__ float bf16_round(float v) { return __uint_as_float((uint32_t)bf16_bits(v) << 16); }
 
-// Standard normal CDF Phi(z) = erfc(-z / sqrt 2) / 2 without branches:
-// erfc(u) for u >= 0 from the Chebyshev-fitted form t exp(-u^2 + P(t)),
-// t = 1 / (1 + u / 2), of Numerical Recipes (2nd ed., Sec. 6.2), whose
-// fractional error is below 1.2e-7 for every u >= 0; Phi(z) = 1 - erfc/2 for
-// z >= 0.  The exponential is the hardware base-2 one: P's coefficients
-// below are NR's times log2(e), with the factor 1/2 folded into the constant
-// term (-1), and u^2 log2(e) = (|z| sqrt(log2(e) / 2))^2.  One reciprocal, one
-// exp2 and a degree-9 polynomial, the same for every lane.
-__device__ __forceinline__ float norm_cdf(float z)
+// Phi(-|z|) = erfc(|z| / sqrt 2) / 2 without branches, as t * e: erfc(u)
+// for u >= 0 from the Chebyshev-fitted form t exp(-u^2 + P(t)), t = 1 / (1 +
+// u / 2), of Numerical Recipes (2nd ed., Sec. 6.2), whose fractional error is
+// below 1.2e-7 for every u >= 0.  The exponential is the hardware base-2 one:
+// P's coefficients below are NR's times log2(e), with the factor 1/2 folded
+// into the constant term (-1), and u^2 log2(e) = (|z| sqrt(log2(e) / 2))^2.
+// One reciprocal, one exp2 and a degree-9 polynomial, the same for every
+// lane.  t and e are returned apart so that GELU can fold |z| into t.
+struct HalfErfc {
+    float t, e;
+};
+__device__ __forceinline__ HalfErfc half_erfc_parts(float z)
 {
     const float az = fabsf(z);
     const float t = __builtin_amdgcn_rcpf(fmaf(0.35355339059327376f, az, 1.0f));  // 1 / (1 + u/2), u = |z|/sqrt2
@@ -84,12 +87,24 @@ __device__ __forceinline__ float norm_cdf(float z)
     p = fmaf(p, t, 5.397006155e-01f);
     p = fmaf(p, t, 1.442729204e+00f);
     p = fmaf(p, t, -2.825748218e+00f);
-    const float half_erfc = t * __builtin_amdgcn_exp2f(fmaf(-v, v, p));
+    return HalfErfc{t, __builtin_amdgcn_exp2f(fmaf(-v, v, p))};
+}
+
+// Standard normal CDF: Phi(z) = 1 - Phi(-z) for z >= 0.
+__device__ __forceinline__ float norm_cdf(float z)
+{
+    const HalfErfc h = half_erfc_parts(z);
+    const float half_erfc = h.t * h.e;
     return z >= 0.f ? 1.0f - half_erfc : half_erfc;
 }
 
-// GELU with the exact Gaussian CDF: z Phi(z).
-__device__ __forceinline__ float gelu_erf(float z) { return z * norm_cdf(z); }
+// GELU with the exact Gaussian CDF, z Phi(z) = max(z, 0) - |z| Phi(-|z|):
+// one multiply, one max and one fused multiply-add after the CDF's parts.
+__device__ __forceinline__ float gelu_erf(float z)
+{
+    const HalfErfc h = half_erfc_parts(z);
+    return fmaf(-(fabsf(z) * h.t), h.e, fmaxf(z, 0.f));
+}
 
 __device__ __forceinline__ bf16x8_t load_bf16x8(const uint16_t *p)
 {
@@ -161,7 +176,7 @@ __device__ __forceinline__ float mlp_tile(const MlpDev *__restrict__ P, int lane
     float part = 0.f;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        part += w3[j] * bf16_round(gelu_erf(d[j]));
+        part = fmaf(w3[j], bf16_round(gelu_erf(d[j])), part);
         if (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     }
     return part;

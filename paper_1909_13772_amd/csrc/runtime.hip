@@ -1094,13 +1094,13 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
                     }
                 }
                 const int cells = ext[0] * ext[1] * ext[2];
-                for (int s0 = 0; s0 < cells; s0 += kWG) {
+                for (int s0 = 0; s0 < cells; s0 += kXChunk) {
                     XItem it;
                     it.slot = j;
                     it.ex = ext[0];
                     it.ey = ext[1];
                     it.start = s0;
-                    it.count = std::min(kWG, cells - s0);
+                    it.count = std::min(kXChunk, cells - s0);
                     // after the even sweep: neighbour interior -> own ghost layer
                     it.sb = nb;
                     it.db = b;

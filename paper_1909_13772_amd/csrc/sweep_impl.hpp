@@ -191,8 +191,7 @@ using AccOf = std::conditional_t<std::is_same_v<ST, float>, double, typename Cod
 // its global index, so that the rounding is reproducible and the same
 // whatever the tiles, blocks, launch order or kernel variant.  Per
 // population the bits are mixed once more with the population's index, and
-// the high half is folded into the low half so that every bit of the
-// result depends on every bit of the cell hash.
+// the high half is folded into the low half, which the conversion uses.
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -217,7 +216,10 @@ __device__ __forceinline__ uint32_t state_hash(const T (&f)[Q], uint32_t gcell)
 }
 __device__ __forceinline__ uint32_t pop_bits(uint32_t h, int i)
 {
-    const uint32_t r = (h ^ (0x9e3779b9u * (uint32_t)(i + 1))) * 0x85ebca6bu;
+    // 24-bit multiply: full rate, where a 32-bit integer multiply issues at
+    // a quarter of the rate; the cell hash is uniform in every bit, so its
+    // low 24 bits carry the mix
+    const uint32_t r = __umul24(h ^ (0x9e3779b9u * (uint32_t)(i + 1)), 0xebca6bu);
     return r ^ (r >> 16);
 }
 
@@ -1069,6 +1071,24 @@ __device__ __forceinline__ uint32_t cell_off(const DevBlock &B, int x, int y, in
     return (uint32_t)((z + 1) * B.plane + (y + B.gy) * B.pitch + B.xoff + x);
 }
 
+// A copy of the descriptor whose addressing fields the compiler cannot
+// relate to the original: the stores of a sweep then compute their slot
+// bases after the collision instead of sharing the loads' bases, which
+// would keep some 40-60 uniform registers live through the collision and
+// spill them into vector lanes (a VALU instruction per spill and reload).
+__device__ __forceinline__ DevBlock fresh_bases(const DevBlock &B)
+{
+    DevBlock C = B;
+    int64_t z = 0;
+    int32_t zi = 0;
+    asm volatile("" : "+s"(z), "+s"(zi));
+    C.pop += z;
+    C.slot += z;
+    C.pitch += zi;
+    C.plane += zi;
+    return C;
+}
+
 template <int Q, int i>
 __device__ __forceinline__ int link_delta(const DevBlock &B)
 {
@@ -1151,17 +1171,30 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
                                        uint32_t special, typename Codec<ST>::T (&f)[Q])
 {
     const XOff o = xoffsets<ST>(B, off, x);
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (!SWAPPED) {
-            f[i] = ldv<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, i), o.at), i);
+    if constexpr (SWAPPED) {
+        if (!__any(special != 0u)) {
+            // no lane of the wave has a bounce-back link: every access is the
+            // regular one, a uniform base and the lane's shifted offset
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const Alt<ST> p = alt_in<Q, ST, i>(a, B);
+                f[i] = ldv<Q, ST, NT>(at<ST>(p.base + p.add_reg, xshift<-cx<Q>(i)>(o)), i);
+            });
         } else {
-            const Alt<ST> p = alt_in<Q, ST, i>(a, B);
-            f[i] = ldv<Q, ST, NT>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
-                                                                         : xshift<-cx<Q>(i)>(o) + p.add_reg),
-                                  i);
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const Alt<ST> p = alt_in<Q, ST, i>(a, B);
+                f[i] = ldv<Q, ST, NT>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
+                                                                             : xshift<-cx<Q>(i)>(o) + p.add_reg),
+                                      i);
+            });
         }
-    });
+    } else {
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            f[i] = ldv<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, i), o.at), i);
+        });
+    }
     if constexpr (SWAPPED) {
         // x faces shared with another block: populations entering through
         // the face come straight from the neighbour's cells (no x exchange;
@@ -1198,16 +1231,27 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
                                         uint32_t special, const typename Codec<ST>::T (&f)[Q], uint32_t h)
 {
     const XOff o = xoffsets<ST>(B, off, x);
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if constexpr (!ODD) {
-            stv_sr<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i], i, h);
+    if constexpr (ODD) {
+        if (!__any(special != 0u)) {  // regular stores only (see gather)
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const Alt<ST> p = alt_out<Q, ST, i>(a, B);
+                stv_sr<Q, ST, NT>(at<ST>(p.base + p.add_reg, xshift<cx<Q>(i)>(o)), f[i], i, h);
+            });
         } else {
-            const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-            stv_sr<Q, ST, NT>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg), f[i],
-                              i, h);
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const Alt<ST> p = alt_out<Q, ST, i>(a, B);
+                stv_sr<Q, ST, NT>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg),
+                                  f[i], i, h);
+            });
         }
-    });
+    } else {
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            stv_sr<Q, ST, NT>(at<ST>(slot_base<ST>(a, B, opp(i)), o.at), f[i], i, h);
+        });
+    }
     if constexpr (ODD) {
         // populations leaving through an x face shared with another block go
         // straight into the neighbour's cells (the regular stores above
@@ -1323,7 +1367,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
                 if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout, lo ? drin : drout);
             });
         }
-        scatter<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f, h);
+        scatter<Q, ST, ODD, NT>(a, fresh_bases(B), off, c.x, c.y, c.z, special, f, h);
     }
 }
 
@@ -2031,24 +2075,38 @@ __global__ __launch_bounds__(kWG) void exchange_kernel(Raw *arena, const DevBloc
                                                        const XItem *items, int xcd_map)
 {
     const XItem &it = items[xcd_map ? xcd_item(blockIdx.x, gridDim.x) : (int)blockIdx.x];
-    const int l = threadIdx.x;
-    if (l >= it.count) return;
-    const int r = it.start + l;
-    const int rx = r % it.ex, rq = r / it.ex;
-    const int ry = rq % it.ey, rz = rq / it.ey;
     const DevBlock &S = blocks[it.sb];
     const DevBlock &D = blocks[it.db];
-    const int dx = it.d0[0] + rx, dy = it.d0[1] + ry, dz = it.d0[2] + rz;
-    if (it.chk >= 0 && D.mask >= 0) {
-        const uint32_t m = masks[D.mask + (int64_t)dz * D.mplane + dy * D.mpitch + dx];
-        if (m & (kSolidBit | (1u << it.chk))) return;
+    // up to kXChunk / kWG cells per thread: every load is issued before the
+    // first store, so one workgroup keeps several independent copies in flight
+    constexpr int K = kXChunk / kWG;
+    Raw v[K];
+    Raw *dst[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int l = (int)threadIdx.x + k * kWG;
+        dst[k] = nullptr;
+        if (l >= it.count) continue;
+        const int r = it.start + l;
+        const int rx = r % it.ex, rq = r / it.ex;
+        const int ry = rq % it.ey, rz = rq / it.ey;
+        const int dx = it.d0[0] + rx, dy = it.d0[1] + ry, dz = it.d0[2] + rz;
+        if (it.chk >= 0 && D.mask >= 0) {
+            const uint32_t m = masks[D.mask + (int64_t)dz * D.mplane + dy * D.mpitch + dx];
+            if (m & (kSolidBit | (1u << it.chk))) continue;
+        }
+        const Raw *src = arena + S.pop + (int64_t)it.slot * S.slot + cell_off(S, it.s0[0] + rx, it.s0[1] + ry, it.s0[2] + rz);
+        dst[k] = arena + D.pop + (int64_t)it.slot * D.slot + cell_off(D, dx, dy, dz);
+        v[k] = mem_ld<true>(src);
     }
-    const Raw *src = arena + S.pop + (int64_t)it.slot * S.slot + cell_off(S, it.s0[0] + rx, it.s0[1] + ry, it.s0[2] + rz);
-    Raw *dst = arena + D.pop + (int64_t)it.slot * D.slot + cell_off(D, dx, dy, dz);
-    if constexpr (ADD)
-        atomicAdd(dst, *src);
-    else
-        mem_st<true>(dst, mem_ld<true>(src));
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!dst[k]) continue;
+        if constexpr (ADD)
+            atomicAdd(dst[k], v[k]);
+        else
+            mem_st<true>(dst[k], v[k]);
+    }
 }
 
 // ---------------------------------------------------------------------------

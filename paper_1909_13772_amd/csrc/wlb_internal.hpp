@@ -62,8 +62,10 @@ struct TileHost {
 // Exchange work item: copy population `slot` over a rectangular region of
 // cells from block sb (coordinates s0 + r) to block db (coordinates d0 + r),
 // r over the linear cell range [start, start + count) of a region with
-// extents (ex, ey, *).  chk >= 0: skip cells whose destination mask has bit
-// chk or the solid bit set (used after the odd sweep).
+// extents (ex, ey, *), count <= kXChunk.  chk >= 0: skip cells whose
+// destination mask has bit chk or the solid bit set (used after the odd
+// sweep).
+constexpr int kXChunk = 4 * kWG;
 struct XItem {
     int32_t sb, db;
     int32_t slot, chk;
