@@ -246,6 +246,8 @@ typedef struct {
     int32_t overlap;        /* 1: sweeps split into interior and frontier, exchange overlapped */
     int32_t nt_even;        /* 1: the even sweep's population accesses are non-temporal */
     int32_t nt_odd;         /* 1: the odd sweep's population accesses are non-temporal */
+    int32_t n_class_tiles;  /* classes of x-runs (by y extent) whose tile shape the autotuner
+                               set apart from `tile` (0: one shape for every run) */
 } wlb_info_t;
 int wlb_info(wlb_blocks_t h, wlb_info_t *out);
 
@@ -259,9 +261,21 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *out);
  * (no lanes on solid cells; needs a preceding wlb_lbm_init with solid cells
  * and blocks of at most 1024 x 1024 x 4096 cells), all other passes over
  * whole-row tiles.
+ * The shape applies to every x-run (it replaces per-class shapes that the
+ * autotuner may have chosen).
  * Errors: WLB_ERR_ARG (shape above 256 cells, grid < -1, more tiles than the
  * arena's tile table holds), WLB_ERR_STATE (tx = -1 without fluid lists). */
 int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t grid);
+
+/* Tile shape of one class of x-runs (Sec. 4.1: blocks of different sizes in
+ * one launch): every x-run whose y extent is `y_extent` gets box tiles of
+ * (tx, ty, tz) (tx = 0: whole rows), the others keep theirs; the grid and
+ * the odd-sweep choice stay.  The autotuner makes the same per-class choice.
+ * Results do not depend on it.
+ * Errors: WLB_ERR_ARG (null handle, shape above 256 cells or negative, no
+ * x-run of that y extent, more tiles than the tile table holds),
+ * WLB_ERR_STATE (fluid-cell list tiles in use). */
+int wlb_set_class_tiles(wlb_blocks_t h, int32_t y_extent, int32_t tx, int32_t ty, int32_t tz);
 
 /* Odd-sweep kernel (Eq. 2 and the AA scheme of Sec. 4.1 are the same in all
  * three; results are bitwise identical):

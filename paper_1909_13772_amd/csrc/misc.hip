@@ -109,13 +109,15 @@ hipError_t launch_reduce_sum8(const double *partials, int n, double *out8, hipSt
     return hipGetLastError();
 }
 
-// Plain streaming copy, one 16-byte vector per thread over a grid that
-// covers the buffer (measured on MI355X as the fastest simple copy form):
-// the library's own measure of achievable HBM bandwidth.
-__global__ __launch_bounds__(kWG) void copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n)
+// Streaming copy, one 16-byte vector per thread over a grid that covers the
+// buffer, non-temporal loads and stores (the fastest simple copy form
+// measured on MI355X): the library's own measure of achievable HBM
+// bandwidth.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kWG) void copy_kernel(u32x4_t *__restrict__ dst, const u32x4_t *__restrict__ src, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (i < n) dst[i] = src[i];
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
@@ -124,7 +126,7 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
     const int64_t grid = (n + kWG - 1) / kWG;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(copy_kernel, dim3((unsigned)(grid > 0 ? grid : 1)), dim3(kWG), 0, st,
-                       reinterpret_cast<uint4 *>(dst), reinterpret_cast<const uint4 *>(src), n);
+                       reinterpret_cast<u32x4_t *>(dst), reinterpret_cast<const u32x4_t *>(src), n);
     return hipGetLastError();
 }
 

@@ -95,6 +95,9 @@ struct wlb_blocks {
     std::vector<int4> ltiles;
     int last_sweep = -1;  // parity of the last sweep (-1: none since init / set)
     int shape[3] = {0, 0, 0};
+    // per-run tile shape set by the autotuner for classes of runs (runs of
+    // one y extent); empty: `shape` for every run
+    std::vector<std::array<int, 3>> run_shape;
     int grid = 0;
     bool lds_stage = false;  // odd sweep stages x-shifted populations in LDS (autotuner candidate)
     // odd sweep over whole rows with 16-byte vectors per lane (autotuner
@@ -184,9 +187,10 @@ void tile_region(const HostBlock &B, int b, int tx, int ty, int tz, int y0, int 
             }
 }
 
-// Sweep tiles of every block.  split: interior tiles first (their count in
+// Sweep tiles of every x-run.  split: interior tiles first (their count in
 // *nint), then the frontier, each group in longest-processing-time order
-// for the persistent (grid-stride) launch.
+// for the persistent (grid-stride) launch.  Box tiles (tx >= 0) take the
+// run's own shape where the autotuner set one (h->run_shape).
 void build_tiles(const wlb_blocks *h, int tx, int ty, int tz, std::vector<TileHost> &out, bool split = false,
                  int *nint = nullptr)
 {
@@ -195,21 +199,27 @@ void build_tiles(const wlb_blocks *h, int tx, int ty, int tz, std::vector<TileHo
     for (int r = 0; r < (int)h->rhost.size(); ++r) {
         const HostBlock &B = h->rhost[r];
         const int b = h->nblk + r;
+        int sx = tx, sy = ty, sz = tz;
+        if (!h->run_shape.empty() && tx >= 0) {
+            sx = h->run_shape[r][0];
+            sy = h->run_shape[r][1];
+            sz = h->run_shape[r][2];
+        }
         if (!split) {
-            tile_region(B, b, tx, ty, tz, 0, B.n[1], 0, B.n[2], out);
+            tile_region(B, b, sx, sy, sz, 0, B.n[1], 0, B.n[2], out);
             continue;
         }
         int y0, y1, z0, z1;
         interior_rows(B, y0, y1, z0, z1);
-        tile_region(B, b, tx, ty, tz, y0, y1, z0, z1, out);
-        if (y0 >= y1) {  // no interior: the whole block is frontier
-            tile_region(B, b, tx, ty, tz, 0, B.n[1], 0, B.n[2], outer);
+        tile_region(B, b, sx, sy, sz, y0, y1, z0, z1, out);
+        if (y0 >= y1) {  // no interior: the whole run is frontier
+            tile_region(B, b, sx, sy, sz, 0, B.n[1], 0, B.n[2], outer);
             continue;
         }
-        tile_region(B, b, tx, ty, tz, 0, B.n[1], 0, z0, outer);
-        tile_region(B, b, tx, ty, tz, 0, B.n[1], z1, B.n[2], outer);
-        tile_region(B, b, tx, ty, tz, 0, y0, z0, z1, outer);
-        tile_region(B, b, tx, ty, tz, y1, B.n[1], z0, z1, outer);
+        tile_region(B, b, sx, sy, sz, 0, B.n[1], 0, z0, outer);
+        tile_region(B, b, sx, sy, sz, 0, B.n[1], z1, B.n[2], outer);
+        tile_region(B, b, sx, sy, sz, 0, y0, z0, z1, outer);
+        tile_region(B, b, sx, sy, sz, y1, B.n[1], z0, z1, outer);
     }
     auto lpt = [](const TileHost &a, const TileHost &b) { return a.ex * a.ey * a.ez > b.ex * b.ey * b.ez; };
     std::stable_sort(out.begin(), out.end(), lpt);
@@ -689,6 +699,7 @@ int time_pairs(wlb_blocks *h, int reps, float *ms_out)
 
 int autotune(wlb_blocks *h)
 {
+    h->run_shape.clear();
     h->overlap = false;  // candidates first without the overlap
     h->nt_even = h->nt_odd = true;
     float best = 1e30f;
@@ -766,7 +777,49 @@ int autotune(wlb_blocks *h)
     h->vec_want = blds == 2;
     h->overlap = false;
     int rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
-    if (rc || (h->pull.empty() && h->push.empty())) return rc;
+    if (rc) return rc;
+    // classes of x-runs (by y extent): every other box shape for one class
+    // at a time, the other runs keeping the best shape; kept for a clear gain
+    if (bs[0] >= 0 && h->rhost.size() > 1) {
+        std::vector<int> ext;
+        for (const HostBlock &R : h->rhost) ext.push_back(R.n[1]);
+        std::sort(ext.begin(), ext.end());
+        ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
+        if (ext.size() > 1) {
+            const std::array<int, 3> glob = {bs[0], bs[1], bs[2]};
+            h->run_shape.assign(h->rhost.size(), glob);
+            for (int e : ext) {
+                std::array<int, 3> keep = glob;
+                for (const auto &c : kShapes) {
+                    const std::array<int, 3> cand = {c[0], c[1], c[2]};
+                    if (cand == glob) continue;
+                    for (size_t r = 0; r < h->rhost.size(); ++r)
+                        if (h->rhost[r].n[1] == e) h->run_shape[r] = cand;
+                    if (count_tiles(h, bs[0], bs[1], bs[2]) > h->tile_cap) continue;
+                    rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
+                    if (rc) return rc;
+                    float ms = 0.f;
+                    rc = time_pairs(h, reps, &ms);
+                    if (rc) return rc;
+                    if (log)
+                        fprintf(stderr, "[wlb autotune] runs of y extent %d: tile %d,%d,%d: %.4f ms per two steps\n", e,
+                                cand[0], cand[1], cand[2], ms);
+                    if (ms < 0.99f * best) {
+                        best = ms;
+                        keep = cand;
+                    }
+                }
+                for (size_t r = 0; r < h->rhost.size(); ++r)
+                    if (h->rhost[r].n[1] == e) h->run_shape[r] = keep;
+            }
+            bool same = true;
+            for (const auto &x : h->run_shape) same = same && x == glob;
+            if (same) h->run_shape.clear();
+            rc = set_tiles(h, bs[0], bs[1], bs[2], bg);
+            if (rc) return rc;
+        }
+    }
+    if (h->pull.empty() && h->push.empty()) return WLB_OK;
     // the best configuration once more with the exchange overlapped
     rc = ensure_stream2(h);
     if (rc) return rc;
@@ -1526,6 +1579,13 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
     o->n_fluid = h->inited ? h->nfluid : h->ncells;
     o->n_tiles = (int32_t)(h->list_mode ? h->ltiles.size() : h->tiles.size());
     for (int a = 0; a < 3; ++a) o->tile[a] = h->shape[a];
+    {
+        std::vector<int> cls;
+        for (size_t r = 0; r < h->run_shape.size(); ++r)
+            if (h->run_shape[r] != std::array<int, 3>{h->shape[0], h->shape[1], h->shape[2]}) cls.push_back(h->rhost[r].n[1]);
+        std::sort(cls.begin(), cls.end());
+        o->n_class_tiles = (int32_t)(std::unique(cls.begin(), cls.end()) - cls.begin());
+    }
     o->grid = h->grid;
     o->lds_staging = (h->args.vec_odd && h->esize == 8) ? 2 : (h->args.lds_stride > 0 ? 1 : 0);
     o->overlap = split_sweeps(h) ? 1 : 0;
@@ -1545,7 +1605,29 @@ int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t gr
     if (grid < -1) return fail(WLB_ERR_ARG, "grid must be -1, 0 or a workgroup count");
     if (tx > 0 && (ty < 1 || tz < 1 || (int64_t)tx * ty * tz > kWG))
         return fail(WLB_ERR_ARG, "tile shape must have at most %d cells", kWG);
+    h->run_shape.clear();
     return set_tiles(h, tx, ty, tz, grid);
+}
+
+int wlb_set_class_tiles(wlb_blocks_t h, int32_t y_extent, int32_t tx, int32_t ty, int32_t tz)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (tx < 0 || ty < 0 || tz < 0) return fail(WLB_ERR_ARG, "negative tile shape");
+    if (tx > 0 && (int64_t)tx * std::max(ty, 1) * std::max(tz, 1) > kWG)
+        return fail(WLB_ERR_ARG, "tile shape must have at most %d cells", kWG);
+    if (h->list_mode || h->shape[0] < 0) return fail(WLB_ERR_STATE, "fluid-cell list tiles are in use");
+    bool any = false;
+    for (const HostBlock &R : h->rhost) any = any || R.n[1] == y_extent;
+    if (!any) return fail(WLB_ERR_ARG, "no x-run has y extent %d", y_extent);
+    std::vector<std::array<int, 3>> prev = h->run_shape;
+    if (h->run_shape.empty()) h->run_shape.assign(h->rhost.size(), {h->shape[0], h->shape[1], h->shape[2]});
+    for (size_t r = 0; r < h->rhost.size(); ++r)
+        if (h->rhost[r].n[1] == y_extent) h->run_shape[r] = {tx, ty, tz};
+    if (count_tiles(h, h->shape[0], h->shape[1], h->shape[2], h->overlap) > h->tile_cap) {
+        h->run_shape.swap(prev);
+        return fail(WLB_ERR_ARG, "these tile shapes yield more tiles than the tile table holds");
+    }
+    return set_tiles(h, h->shape[0], h->shape[1], h->shape[2], h->grid);
 }
 
 int wlb_set_nontemporal(wlb_blocks_t h, int32_t even, int32_t odd)

@@ -82,6 +82,7 @@ class wlb_info_t(C.Structure):
         ("overlap", C.c_int32),
         ("nt_even", C.c_int32),
         ("nt_odd", C.c_int32),
+        ("n_class_tiles", C.c_int32),
     ]
 
 
@@ -117,6 +118,7 @@ _sig = {
     "wlb_set_graph": (C.c_int, [_h, C.c_int32]),
     "wlb_set_lds_staging": (C.c_int, [_h, C.c_int32]),
     "wlb_set_nontemporal": (C.c_int, [_h, C.c_int32, C.c_int32]),
+    "wlb_set_class_tiles": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "wlb_set_overlap": (C.c_int, [_h, C.c_int32]),
     "wlb_set_kernel_timing": (C.c_int, [_h, C.c_int32]),
     "wlb_kernel_times": (C.c_int, [_h, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -404,6 +406,9 @@ class Blocks:
 
     def set_nontemporal(self, even, odd):
         _check(_lib.wlb_set_nontemporal(self.h, int(bool(even)), int(bool(odd))))
+
+    def set_class_tiles(self, y_extent, tx, ty, tz):
+        _check(_lib.wlb_set_class_tiles(self.h, int(y_extent), int(tx), int(ty), int(tz)))
 
     def set_overlap(self, on):
         wlb_set_overlap(self.h, on)

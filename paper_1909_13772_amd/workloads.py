@@ -96,6 +96,7 @@ def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0
         "roofline_frac": bytes_launch / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "tile": list(info.tile), "grid": info.grid, "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems,
         "overlap": int(info.overlap), "lds_staging": int(info.lds_staging),
+        "nontemporal": [int(info.nt_even), int(info.nt_odd)], "class_tiles": int(info.n_class_tiles),
         "flux_x_mean": float(flux.mean()), "flux_x_spread": float((flux.max() - flux.min()) / abs(flux.mean())),
         "max_u": float(tot[5]),
         "drag_on_spheres": [float(v) for v in force[:3]], "solid_links": int(force[6]),

@@ -3,8 +3,9 @@ parity, with the exchange after it, every population slot of every fluid
 cell is written exactly once and no solid cell is written.  The check runs
 the sweep and exchange kernels themselves with stores that count
 (wlb_debug_write_coverage), over uneven blocks with spheres and density
-faces, a block that wraps onto itself in x, every tile mode, the LDS-staged
-odd sweep, the interior/frontier overlap and all four velocity sets."""
+faces, a block that wraps onto itself in x, every tile mode (also per class
+of x-runs), the LDS-staged odd sweep, the interior/frontier overlap and all
+four velocity sets."""
 import numpy as np
 import pytest
 
@@ -17,7 +18,9 @@ wlb = pytest.importorskip("paper_1909_13772_amd.wlb", reason="libwlb.so not buil
 MODES = [dict(), dict(tiles=(16, 4, 4, 0)), dict(tiles=(64, 4, 1, 7)), dict(tiles=(8, 8, 4, 3)),
          dict(lds=True), dict(lds=True, tiles=(16, 4, 4, 0)), dict(tiles=(-1, 0, 0, 0)),
          dict(tiles=(-1, 0, 0, -1)), dict(overlap=True), dict(overlap=True, tiles=(-1, 0, 0, 0)),
-         dict(overlap=True, lds=True)]
+         dict(overlap=True, lds=True),
+         # per-class tile shapes: x-runs of y extent 10 and 6 (the porous case) tiled differently
+         dict(classes={10: (16, 4, 4), 6: (8, 8, 4)}), dict(classes={6: (64, 4, 1)}, overlap=True)]
 
 
 def _case(name):
@@ -49,6 +52,9 @@ def test_every_fluid_slot_is_written_exactly_once(q, coll, odd, case):
             B.set_lds_staging(kw.get("lds", False))
             if kw.get("overlap"):
                 B.set_overlap(True)
+            for e, shape in kw.get("classes", {}).items():
+                if case == "porous":
+                    B.set_class_tiles(e, *shape)
             c = B.write_coverage(odd)
             info = B.info()
         finally:

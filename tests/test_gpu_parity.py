@@ -387,6 +387,38 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
             assert np.array_equal(d, ref), kw
 
 
+def test_tile_shape_per_class_of_runs_is_bitwise_invariant():
+    """x-runs of different y extents swept with different tile shapes (the
+    autotuner's per-class choice) give the populations of one shape for all."""
+    say("case per-class tiles")
+    dom = (40, 36, 20)
+    solid, rho, u = _porous_inputs(dom, seed=6)
+    blocks = inputs.rectilinear_blocks([16, 24], [24, 12], [12, 8])[0]
+    p = wlb.make_params(tau=0.66, magic=3 / 16, force=(1e-5, 0, 0))
+    ref = None
+    for shapes, kw in (({}, {}), ({24: (16, 4, 4), 12: (8, 8, 4)}, {}), ({12: (32, 8, 1)}, dict(overlap=True)),
+                       ({24: (64, 4, 1)}, dict(lds=True)), ({24: (8, 8, 4), 12: (16, 4, 4)}, dict(nt=(0, 0)))):
+        B = wlb.Blocks(blocks, dom, (1, 1, 0), stencil=19, storage=wlb.F32)
+        try:
+            B.init(wlb.TRT, p, rho, u, solid)
+            B.set_lds_staging(kw.get("lds", False))
+            if kw.get("overlap"):
+                B.set_overlap(True)
+            if "nt" in kw:
+                B.set_nontemporal(*kw["nt"])
+            for e, s in shapes.items():
+                B.set_class_tiles(e, *s)
+            assert B.info().n_class_tiles == len(shapes), shapes
+            B.step(13)
+            d = B.pdfs_get()
+        finally:
+            B.close()
+        if ref is None:
+            ref = d
+        else:
+            assert np.array_equal(d, ref), (shapes, kw)
+
+
 def test_fluid_list_tiles_need_solid_cells():
     say("case list tiles without solids")
     dom = (16, 12, 10)
