@@ -275,6 +275,8 @@ def main():
                     help="with --no-autotune: 'tx,ty,tz,grid' launch configuration of the porous workload")
     ap.add_argument("--variant", type=str, default="f32_mlp_closure",
                     help="with --workload variant: the variant configuration to run alone")
+    ap.add_argument("--porous-geometry", choices=["spheres", "empty", "one_block"], default="spheres",
+                    help="with --workload porous: spheres (default), the blocks without spheres, or one block")
     ap.add_argument("--workload", choices=["channel", "porous", "turbulence", "closures", "entropic", "matrix",
                                            "variant"],
                     default="channel",
@@ -313,7 +315,8 @@ def main():
             tiles = None if args.tiles is None else [int(v) for v in args.tiles.split(",")]
             nt = None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")]
             r = workloads.porous(wlb, steps=args.steps, warmup=args.warmup, autotune=not args.no_autotune,
-                                 tiles=tiles if args.no_autotune else None, nt=nt if args.no_autotune else None)
+                                 tiles=tiles if args.no_autotune else None, nt=nt if args.no_autotune else None,
+                                 geometry=args.porous_geometry)
         elif args.workload == "turbulence":
             r = workloads.turbulence_precision(wlb, steps=args.steps, tau=args.tau)
         elif args.workload == "entropic":

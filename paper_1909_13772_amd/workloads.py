@@ -44,15 +44,23 @@ def _timed_steps(B, steps, warmup, kernel_steps=None):
 
 
 def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0, seed_spheres=1, overlap=None,
-           tiles=None, nt=None):
+           tiles=None, nt=None, geometry="spheres"):
     """512 uneven blocks (rectilinear 8x8x8, edges from {16,24,32,48,64}),
     random spheres (radius 3-8, solid fraction >= 0.3), D3Q27 MRT, tau 0.8,
-    density faces on x (1.0005 / 0.9995), periodic y/z, FP32 storage."""
+    density faces on x (1.0005 / 0.9995), periodic y/z, FP32 storage.
+    geometry "empty": the same blocks without spheres; "one_block": the same
+    domain without spheres in one block (the cost of the spheres and of the
+    decomposition, measured apart)."""
     storage = wlb.F32 if storage is None else storage
     eb = wlb.ELEM_BYTES[storage]
     blocks, dom = inputs.uneven_blocks(seed_blocks)
-    solid, frac, nsph = inputs.spheres(dom, seed=seed_spheres, rmin=3.0, rmax=8.0, solid_fraction=0.3,
-                                       periodic=(0, 1, 1), clear_x=4)
+    if geometry == "spheres":
+        solid, frac, nsph = inputs.spheres(dom, seed=seed_spheres, rmin=3.0, rmax=8.0, solid_fraction=0.3,
+                                           periodic=(0, 1, 1), clear_x=4)
+    else:
+        solid, frac, nsph = None, 0.0, 0
+        if geometry == "one_block":
+            blocks = wlb.single_block(dom)
     rho, u = inputs.uniform_state(dom)
     p = wlb.make_params(tau=0.8, omega_bulk=1.0, omega_higher=1.0, pressure_axis=0, rho_in=1.0005,
                         rho_out=0.9995, autotune=1 if autotune else 0)
@@ -87,11 +95,13 @@ def porous(wlb, steps=500, warmup=10, storage=None, autotune=True, seed_blocks=0
     bytes_launch = nfl * 2 * 27 * eb + ncell * 4
     flux = (r * uu[0]).sum(axis=(0, 1))
     return {
-        "workload": "porous medium, 512 uneven blocks, D3Q27 MRT",
+        "workload": "porous medium, 512 uneven blocks, D3Q27 MRT" if geometry == "spheres" else
+                    f"porous-medium domain without spheres ({'512 uneven blocks' if geometry == 'empty' else 'one block'}), D3Q27 MRT",
         "domain": list(dom), "cells": ncell, "fluid_cells": nfl, "solid_fraction": float(frac),
         "spheres": int(nsph), "storage": wlb.STORAGE_NAMES[storage], "steps": steps,
         "mlups": ncell * steps / secs / 1e6, "mflups": nfl * steps / secs / 1e6,
         "ms_per_step": secs * 1e3 / steps, "sweep_ms": sweep_ms, "exchange_ms": xchg_ms,
+        "even_ms": ms[0] / max(1, cnt[0]), "odd_ms": ms[1] / max(1, cnt[1]),
         "achieved_gbs": bytes_launch / (sweep_ms * 1e-3) / 1e9,
         "roofline_frac": bytes_launch / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "tile": list(info.tile), "grid": info.grid, "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems,
