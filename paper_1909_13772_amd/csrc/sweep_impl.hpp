@@ -190,8 +190,7 @@ using AccOf = std::conditional_t<std::is_same_v<ST, float>, double, typename Cod
 // of four of the cell's incoming populations (which change every step) and
 // its global index, so that the rounding is reproducible and the same
 // whatever the tiles, blocks, launch order or kernel variant.  Per
-// population the bits are mixed once more with the population's index, and
-// the high half is folded into the low half, which the conversion uses.
+// population the bits are mixed once more with the population's index.
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -218,9 +217,11 @@ __device__ __forceinline__ uint32_t pop_bits(uint32_t h, int i)
 {
     // 24-bit multiply: full rate, where a 32-bit integer multiply issues at
     // a quarter of the rate; the cell hash is uniform in every bit, so its
-    // low 24 bits carry the mix
-    const uint32_t r = __umul24(h ^ (0x9e3779b9u * (uint32_t)(i + 1)), 0xebca6bu);
-    return r ^ (r >> 16);
+    // low 24 bits carry the mix.  The conversions take their random bits
+    // from the high end of the word (a value half an ulp above a
+    // representable one is lifted by bit 31 alone and by no lower bit, as
+    // measured on gfx950), which is where a multiply mixes best.
+    return __umul24(h ^ (0x9e3779b9u * (uint32_t)(i + 1)), 0xebca6bu);
 }
 
 // Raw bits of a collision result for storage (stochastic rounding for
