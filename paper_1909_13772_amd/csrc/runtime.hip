@@ -1101,80 +1101,96 @@ int wlb_blocks_create(const wlb_block_desc *d, int32_t n, const int32_t domain[3
     h->off_vtiles = off;
     off += round_up(h->vtile_cap * sizeof(int4), 256);
     // --- exchange work lists
-    for (int b = 0; b < n; ++b) {
-        const HostBlock &A = h->blocks[b];
+    // Items of one y/z face (or edge) direction k of descriptor a (extent
+    // and neighbour flags A) with neighbour descriptor nbd (extent Bn).
+    auto add_items = [&](const HostBlock &A, int a_id, const HostBlock &Bn, int nb_id, int k) {
         // x neighbours (the block itself or another) are addressed directly
         // by the kernels: no x items, and y/z regions reach the x ends of
         // the rows on every side that has a neighbour
         const bool xlo = A.nbr[12] >= 0, xhi = A.nbr[14] >= 0;
-        for (int k = 0; k < 27; ++k) {
-            const int nb = A.nbr[k];
-            if (nb < 0) continue;
-            const HostBlock &Bn = h->blocks[nb];
-            const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
-            if (o[0] != 0) continue;
-            for (int j = 1; j < stencil; ++j) {
-                bool in = true;
-                for (int a = 0; a < 3; ++a)
-                    if (o[a] != 0 && ccq(stencil, j, a) != o[a]) in = false;
-                if (!in) continue;
-                // Cells of the ghost region on side o for which population j
-                // is used: the cell g - c_j that reads it (after the even
-                // sweep) or writes it (after the odd sweep) must be an
-                // interior cell of A.  Along the shared axes (o_a = 0) this
-                // shrinks the region by one cell on the side c_j points from;
-                // it also makes every interior (cell, slot) of B the target
-                // of exactly one copy after the odd sweep.
-                int ext[3], ghost0[3], inner0[3];
+        const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+        for (int j = 1; j < stencil; ++j) {
+            bool in = true;
+            for (int a = 0; a < 3; ++a)
+                if (o[a] != 0 && ccq(stencil, j, a) != o[a]) in = false;
+            if (!in) continue;
+            // Cells of the ghost region on side o for which population j is
+            // used: the cell g - c_j that reads it (after the even sweep) or
+            // writes it (after the odd sweep) must be an interior cell of A.
+            // Along the shared axes (o_a = 0) this shrinks the region by one
+            // cell on the side c_j points from; it also makes every interior
+            // (cell, slot) of the neighbour the target of exactly one copy
+            // after the odd sweep.
+            int ext[3], ghost0[3], inner0[3];
+            for (int a = 0; a < 3; ++a) {
+                if (o[a] != 0) {
+                    ext[a] = 1;
+                    ghost0[a] = o[a] < 0 ? -1 : A.n[a];
+                    inner0[a] = o[a] < 0 ? Bn.n[a] - 1 : 0;
+                } else if (a == 0) {
+                    // the reader / writer g - c_j may sit across an x face
+                    // with a neighbour; only a face without one limits the range
+                    const int lo = (ccq(stencil, j, 0) > 0 && !xlo) ? 1 : 0;
+                    const int hi = (ccq(stencil, j, 0) < 0 && !xhi) ? A.n[0] - 1 : A.n[0];
+                    ext[a] = hi - lo;
+                    ghost0[a] = lo;
+                    inner0[a] = lo;
+                } else {
+                    const int lo = std::max(0, ccq(stencil, j, a)), hi = std::min(A.n[a], A.n[a] + ccq(stencil, j, a));
+                    ext[a] = hi - lo;
+                    ghost0[a] = lo;
+                    inner0[a] = lo;
+                }
+            }
+            const int cells = ext[0] * ext[1] * ext[2];
+            for (int s0 = 0; s0 < cells; s0 += kXChunk) {
+                XItem it;
+                it.slot = j;
+                it.ex = ext[0];
+                it.ey = ext[1];
+                it.start = s0;
+                it.count = std::min(kXChunk, cells - s0);
+                // after the even sweep: neighbour interior -> own ghost layer
+                it.sb = nb_id;
+                it.db = a_id;
+                it.chk = -1;
                 for (int a = 0; a < 3; ++a) {
-                    if (o[a] != 0) {
-                        ext[a] = 1;
-                        ghost0[a] = o[a] < 0 ? -1 : A.n[a];
-                        inner0[a] = o[a] < 0 ? Bn.n[a] - 1 : 0;
-                    } else if (a == 0) {
-                        // the reader / writer g - c_j may sit across an x face
-                        // with a neighbour; only a face without one limits the range
-                        const int lo = (ccq(stencil, j, 0) > 0 && !xlo) ? 1 : 0;
-                        const int hi = (ccq(stencil, j, 0) < 0 && !xhi) ? A.n[0] - 1 : A.n[0];
-                        ext[a] = hi - lo;
-                        ghost0[a] = lo;
-                        inner0[a] = lo;
-                    } else {
-                        const int lo = std::max(0, ccq(stencil, j, a)), hi = std::min(A.n[a], A.n[a] + ccq(stencil, j, a));
-                        ext[a] = hi - lo;
-                        ghost0[a] = lo;
-                        inner0[a] = lo;
-                    }
+                    it.s0[a] = inner0[a];
+                    it.d0[a] = ghost0[a];
                 }
-                const int cells = ext[0] * ext[1] * ext[2];
-                for (int s0 = 0; s0 < cells; s0 += kXChunk) {
-                    XItem it;
-                    it.slot = j;
-                    it.ex = ext[0];
-                    it.ey = ext[1];
-                    it.start = s0;
-                    it.count = std::min(kXChunk, cells - s0);
-                    // after the even sweep: neighbour interior -> own ghost layer
-                    it.sb = nb;
-                    it.db = b;
-                    it.chk = -1;
-                    for (int a = 0; a < 3; ++a) {
-                        it.s0[a] = inner0[a];
-                        it.d0[a] = ghost0[a];
-                    }
-                    h->pull.push_back(it);
-                    // after the odd sweep: own ghost layer -> neighbour interior,
-                    // unless the writer (neighbour cell - c_j) is solid
-                    it.sb = b;
-                    it.db = nb;
-                    it.chk = opp(j);
-                    for (int a = 0; a < 3; ++a) {
-                        it.s0[a] = ghost0[a];
-                        it.d0[a] = inner0[a];
-                    }
-                    h->push.push_back(it);
-                    h->xchg_elems += it.count;
+                h->pull.push_back(it);
+                // after the odd sweep: own ghost layer -> neighbour interior,
+                // unless the writer (neighbour cell - c_j) is solid
+                it.sb = a_id;
+                it.db = nb_id;
+                it.chk = opp(j);
+                for (int a = 0; a < 3; ++a) {
+                    it.s0[a] = ghost0[a];
+                    it.d0[a] = inner0[a];
                 }
+                h->push.push_back(it);
+                h->xchg_elems += it.count;
+            }
+        }
+    };
+    // Per x-run and direction: where the neighbour of every block of the run
+    // is the block at the same place in one other run (a rectilinear grid),
+    // the run exchanges whole domain rows through the run descriptors;
+    // otherwise each block exchanges its own piece.
+    for (size_t r = 0; r < runs.size(); ++r) {
+        const std::vector<int> &mem = runs[r];
+        for (int k = 0; k < 27; ++k) {
+            if (k % 3 != 1) continue;  // o_x = 0: y/z faces and y-z edges only
+            const int nb0 = h->blocks[mem.front()].nbr[k];
+            bool whole = nb0 >= 0 && runs[run_of[nb0]].size() == mem.size();
+            for (size_t i = 0; i < mem.size() && whole; ++i)
+                whole = h->blocks[mem[i]].nbr[k] == runs[run_of[nb0]][i];
+            if (whole) {
+                const int r2 = run_of[nb0];
+                add_items(h->rhost[r], n + (int)r, h->rhost[r2], n + r2, k);
+            } else {
+                for (int m : mem)
+                    if (h->blocks[m].nbr[k] >= 0) add_items(h->blocks[m], m, h->blocks[h->blocks[m].nbr[k]], h->blocks[m].nbr[k], k);
             }
         }
     }

@@ -130,6 +130,25 @@ def test_porous_uneven_blocks_pressure_fp64(q, coll, steps):
     _compare(f"porous q{q} c{coll}", wlb.F64, q, gpu, orc, solid, np.prod(dom))
 
 
+@pytest.mark.parametrize("q,coll,storage", [(27, 2, 0), (19, 1, 0), (27, 2, 1), (19, 1, 1)])
+def test_porous_uneven_blocks_long_run(q, coll, storage):
+    """The porous case over 400 steps (the density difference drives the flow
+    through the spheres until it develops), autotuned as the workload runs:
+    FP64 element-wise to 1e-12 on the populations, FP32 to its velocity
+    bounds."""
+    say(f"case porous long q{q} coll{coll} storage{storage}")
+    blocks, dom = inputs.rectilinear_blocks([8, 12, 6], [10, 6], [7, 9])
+    solid, frac, _ = inputs.spheres(dom, seed=3, rmin=2.0, rmax=4.0, solid_fraction=0.2, clear_x=2)
+    rho, u = inputs.uniform_state(dom)
+    p = wlb.make_params(tau=0.8, magic=3 / 16, omega_bulk=1.2, omega_higher=1.0, pressure_axis=0,
+                        rho_in=1.002, rho_out=0.998, autotune=1)
+    gpu = gpu_run(blocks, dom, (0, 1, 1), q, storage, coll, p, rho, u, solid, steps=400)
+    op = oracle_params(q, coll, 0.8, 3 / 16, (0, 1, 1), pressure_axis=0, rho_in=1.002, rho_out=0.998,
+                       omega_bulk=1.2, omega_higher=1.0)
+    orc = oracle_run(op, dom, rho, u, solid, 400)
+    _compare(f"porous long q{q} c{coll}", storage, q, gpu, orc, solid, np.prod(dom))
+
+
 @pytest.mark.parametrize("q,coll", [(19, 1), (27, 2), (9, 1), (15, 1)])
 def test_porous_uneven_blocks_lds_staged_odd_sweep_fp64(q, coll):
     """The porous case with the odd sweep staged in LDS: x-neighbour blocks
