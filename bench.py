@@ -125,7 +125,7 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
         info = B.info()
         res = {"seconds": t1 - t0, "tile": list(info.tile), "grid": info.grid,
                "n_tiles": info.n_tiles, "xchg_elems": info.xchg_elems, "lds_staging": int(info.lds_staging),
-               "nt": [int(info.nt_even), int(info.nt_odd)]}
+               "nt": [int(info.nt_even), int(info.nt_odd)], "slot_round_kib": int(info.slot_round_kib)}
         if check:
             r, uu, tot = B.moments()
             nu = (TAU - 0.5) / 3
@@ -383,7 +383,8 @@ def main():
                    "cells": N ** 3, "stencil": "D3Q19", "collision": "TRT", "storage": "f64",
                    "tile": res["tile"], "grid": res["grid"],
                    "odd_sweep": "lds-staged" if res["lds_staging"] else "direct",
-                   "nontemporal": {"even": res["nt"][0], "odd": res["nt"][1]}},
+                   "nontemporal": {"even": res["nt"][0], "odd": res["nt"][1]},
+                   "slot_round_kib": res["slot_round_kib"]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["frac"], 4), "traffic": traffic,
                      "kernel": "sweep_kernel<19,TRT,double> (even AA sweep) and " +

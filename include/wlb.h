@@ -248,6 +248,9 @@ typedef struct {
     int32_t nt_odd;         /* 1: the odd sweep's population accesses are non-temporal */
     int32_t n_class_tiles;  /* classes of x-runs (by y extent) whose tile shape the autotuner
                                set apart from `tile` (0: one shape for every run) */
+    int32_t slot_round_kib; /* population slots of 64 MiB or more start on multiples of this
+                               many KiB (0: 256-byte alignment only); chosen by the autotuner,
+                               16384 otherwise */
 } wlb_info_t;
 int wlb_info(wlb_blocks_t h, wlb_info_t *out);
 

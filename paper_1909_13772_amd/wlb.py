@@ -83,6 +83,7 @@ class wlb_info_t(C.Structure):
         ("nt_even", C.c_int32),
         ("nt_odd", C.c_int32),
         ("n_class_tiles", C.c_int32),
+        ("slot_round_kib", C.c_int32),
     ]
 
 
