@@ -95,7 +95,7 @@ def poiseuille_series(H, nu, g, T, s):
 
 
 def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, autotune=True, q=19, coll=None, lds=None,
-               nt=None):
+               nt=None, slot_round=None):
     import numpy as np
     import torch
 
@@ -108,6 +108,8 @@ def run_config(wlb, inputs, storage, steps, warmup, closure=0, check=False, auto
                         mlp=mlp, autotune=1 if autotune else 0)
     B = wlb.Blocks(wlb.single_block(shape), shape, (1, 0, 1), stencil=q, storage=storage)
     try:
+        if slot_round is not None:  # fixed slot stride (profiler runs without the autotuner)
+            B.set_slot_round(slot_round)
         B.init(wlb.TRT if coll is None else coll, p, rho, u)
         if lds is not None:  # fixed odd-sweep choice (profiler runs without the autotuner)
             B.set_lds_staging(int(lds))
@@ -268,6 +270,9 @@ def main():
                     help="use the default tile shape (for profiler runs that should hold only the timed launches)")
     ap.add_argument("--lds-staging", type=int, choices=[0, 1, 2], default=None,
                     help="with --no-autotune: odd sweep direct (0), staged in LDS (1) or over row vectors (2)")
+    ap.add_argument("--slot-round", type=int, choices=[16384, 2048, 0], default=None,
+                    help="with --no-autotune: slot stride rounding in KiB of the population slots of 64 MiB or more "
+                         "(headline and variant runs)")
     ap.add_argument("--nontemporal", type=str, default=None,
                     help="with --no-autotune: 'E,O' non-temporal accesses (1) or cached (0) in the even / odd sweep "
                          "(headline and variant runs)")
@@ -302,7 +307,8 @@ def main():
         st, eb, cl, q, coll = cfg[args.variant]
         nt = None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")]
         r = run_config(wlb, inputs, st, args.steps, args.warmup, closure=cl, autotune=not args.no_autotune, q=q,
-                       coll=coll, lds=args.lds_staging, nt=nt if args.no_autotune else None)
+                       coll=coll, lds=args.lds_staging, nt=nt if args.no_autotune else None,
+                       slot_round=args.slot_round if args.no_autotune else None)
         sm = summarize(r, st, args.steps, eb, q=q)
         print(json.dumps({"workload": f"channel 256^3 variant {args.variant}", "steps": args.steps,
                           "mlups": sm["mlups"], "even_ms": sm["even_ms"], "odd_ms": sm["odd_ms"],
@@ -329,8 +335,7 @@ def main():
         return
     head_nt = None if args.nontemporal is None else [int(v) for v in args.nontemporal.split(",")]
     res = run_config(wlb, inputs, wlb.F64, args.steps, args.warmup, check=True, autotune=not args.no_autotune,
-                     lds=args.lds_staging,
-                     nt=head_nt)
+                     lds=args.lds_staging, nt=head_nt, slot_round=args.slot_round if args.no_autotune else None)
     head = summarize(res, wlb.F64, args.steps, 8)
     print(f"[bench] f64: {head['mlups']:.0f} MLUPS, sweep {head['sweep_ms']:.3f} ms, "
           f"{head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
@@ -342,7 +347,8 @@ def main():
         p64 = r64["profile"]
         for name, st, eb, cl, q, coll in VARIANTS(wlb):
             r = run_config(wlb, inputs, st, args.variant_steps, args.warmup, closure=cl, autotune=not args.no_autotune,
-                           q=q, coll=coll, check=True, nt=head_nt if args.no_autotune else None)
+                           q=q, coll=coll, check=True, nt=head_nt if args.no_autotune else None,
+                           slot_round=args.slot_round if args.no_autotune else None)
             sm = summarize(r, st, args.variant_steps, eb, q=q)
             variants[name] = {"mlups": round(sm["mlups"], 1), "roofline_frac": round(sm["frac"], 4),
                               "achieved_gbs": round(sm["achieved_gbs"], 1), "sweep_ms": round(sm["sweep_ms"], 4),

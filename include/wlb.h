@@ -280,6 +280,16 @@ int wlb_set_tiles(wlb_blocks_t h, int32_t tx, int32_t ty, int32_t tz, int32_t gr
  * WLB_ERR_STATE (fluid-cell list tiles in use). */
 int wlb_set_class_tiles(wlb_blocks_t h, int32_t y_extent, int32_t tx, int32_t ty, int32_t tz);
 
+/* Slot stride of the population storage (Sec. 4.2: the layout of the
+ * fields): slots of 64 MiB or more start on multiples of `kib` KiB (16384,
+ * 2048, or 0 = 256-byte alignment only); smaller slots are only aligned.
+ * The arena is sized for 16384, the default.  Call after wlb_blocks_bind and
+ * before wlb_lbm_init; an init with the autotuner chooses the stride again.
+ * Results do not depend on it.
+ * Errors: WLB_ERR_ARG (null handle, another value), WLB_ERR_STATE (the
+ * populations are already initialised). */
+int wlb_set_slot_round(wlb_blocks_t h, int32_t kib);
+
 /* Odd-sweep kernel (Eq. 2 and the AA scheme of Sec. 4.1 are the same in all
  * three; results are bitwise identical):
  *   0 (default) direct: every lane reads and writes its cell's x-shifted

@@ -1719,6 +1719,21 @@ int wlb_set_class_tiles(wlb_blocks_t h, int32_t y_extent, int32_t tx, int32_t ty
     return set_tiles(h, h->shape[0], h->shape[1], h->shape[2], h->grid);
 }
 
+int wlb_set_slot_round(wlb_blocks_t h, int32_t kib)
+{
+    if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (kib != 16384 && kib != 2048 && kib != 0) return fail(WLB_ERR_ARG, "slot rounding must be 16384, 2048 or 0 KiB");
+    if (h->inited) return fail(WLB_ERR_STATE, "the slot stride is set before wlb_lbm_init");
+    relayout_slots(h, (size_t)kib << 10);
+    if (h->bound) {
+        HIPCHK(hipMemcpyAsync(h->arena + h->off_blocks, h->dev.data(), h->dev.size() * sizeof(DevBlock),
+                              hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->graph_valid = false;
+    return WLB_OK;
+}
+
 int wlb_set_nontemporal(wlb_blocks_t h, int32_t even, int32_t odd)
 {
     if (!h) return fail(WLB_ERR_ARG, "null handle");

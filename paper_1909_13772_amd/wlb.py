@@ -120,6 +120,7 @@ _sig = {
     "wlb_set_lds_staging": (C.c_int, [_h, C.c_int32]),
     "wlb_set_nontemporal": (C.c_int, [_h, C.c_int32, C.c_int32]),
     "wlb_set_class_tiles": (C.c_int, [_h, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "wlb_set_slot_round": (C.c_int, [_h, C.c_int32]),
     "wlb_set_overlap": (C.c_int, [_h, C.c_int32]),
     "wlb_set_kernel_timing": (C.c_int, [_h, C.c_int32]),
     "wlb_kernel_times": (C.c_int, [_h, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -219,6 +220,10 @@ def wlb_info(h) -> wlb_info_t:
 
 def wlb_set_tiles(h, tx, ty, tz, grid):
     _check(_lib.wlb_set_tiles(h, tx, ty, tz, grid))
+
+
+def wlb_set_slot_round(h, kib):
+    _check(_lib.wlb_set_slot_round(h, int(kib)))
 
 
 def wlb_set_lds_staging(h, on):
@@ -410,6 +415,9 @@ class Blocks:
 
     def set_class_tiles(self, y_extent, tx, ty, tz):
         _check(_lib.wlb_set_class_tiles(self.h, int(y_extent), int(tx), int(ty), int(tz)))
+
+    def set_slot_round(self, kib):
+        _check(_lib.wlb_set_slot_round(self.h, int(kib)))
 
     def set_overlap(self, on):
         wlb_set_overlap(self.h, on)

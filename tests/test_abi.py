@@ -83,6 +83,26 @@ def test_exchange_counts_multi_block_periodic_x():
         wlb.wlb_blocks_destroy(h)
 
 
+def test_slot_round_choices_fit_the_arena():
+    # 256 x 256 x 256 FP32 with walls in y: a slot of 256 x 256 x 258 cells
+    # (64.5 MiB) takes the rounding; every choice fits the arena sized for
+    # 16 MiB multiples, other values are refused
+    n = 256
+    h, nbytes = wlb.wlb_blocks_create([((0, 0, 0), (n, n, n))], (n, n, n), (1, 0, 1), 19, wlb.F32)
+    try:
+        info = wlb.wlb_info(h)
+        assert info.slot_round_kib == 16384
+        assert info.pop_bytes == 19 * (80 << 20)
+        for kib in (2048, 0, 16384):
+            wlb.wlb_set_slot_round(h, kib)
+            assert wlb.wlb_info(h).slot_round_kib == kib
+            assert wlb.wlb_info(h).pop_bytes == 19 * (80 << 20)
+        with pytest.raises(wlb.WlbError):
+            wlb.wlb_set_slot_round(h, 4096)
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
 def test_walls_get_no_ghost_rows():
     # walls on both y faces: no ghost rows (nothing is read or written beyond
     # a wall); x wraps (no x ghosts), z periodic (ghost planes)

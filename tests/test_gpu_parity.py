@@ -438,6 +438,34 @@ def test_tile_shape_per_class_of_runs_is_bitwise_invariant():
             assert np.array_equal(d, ref), (shapes, kw)
 
 
+def test_slot_stride_is_bitwise_invariant():
+    """256^3 FP32 channel (64.5 MiB slots, so the rounding applies): the
+    three slot strides give bitwise the same moments, with and without the
+    autotuner choosing one."""
+    import hashlib
+    say("case slot strides")
+    n = 256
+    dom = (n, n, n)
+    rho, u = inputs.uniform_state(dom)
+    digests = {}
+    for kib, auto in ((16384, 0), (2048, 0), (0, 0), (None, 1)):
+        p = wlb.make_params(tau=0.8, magic=3 / 16, force=(1e-6, 0, 0), autotune=auto)
+        B = wlb.Blocks(wlb.single_block(dom), dom, (1, 0, 1), stencil=19, storage=wlb.F32)
+        try:
+            if kib is not None:
+                B.set_slot_round(kib)
+            B.init(wlb.TRT, p, rho, u)
+            if kib is not None:
+                assert B.info().slot_round_kib == kib
+            B.step(5)
+            r, uu, tot = B.moments()
+            digests[(kib, auto)] = hashlib.sha1(r.tobytes() + uu.tobytes()).hexdigest()
+            del r, uu
+        finally:
+            B.close()
+    assert len(set(digests.values())) == 1, digests
+
+
 def test_fluid_list_tiles_need_solid_cells():
     say("case list tiles without solids")
     dom = (16, 12, 10)
