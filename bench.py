@@ -369,7 +369,8 @@ def main():
         print(f"[bench] host I/O probe failed: {e}", file=sys.stderr)
         host_io = None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
-    access = ("lds-staged" if res["lds_staging"] else "direct") + "; non-temporal even %d odd %d" % tuple(res["nt"])
+    access = (("direct", "lds-staged", "row-vector")[res["lds_staging"]] + "; non-temporal even %d odd %d" % tuple(res["nt"])
+              + "; slot rounding %d KiB" % res["slot_round_kib"])
     traffic = load_traffic("f64", access)
     out = {
         "metric": "MLUPS + % HBM roofline: plain FP64 vs FP32/FP16-store vs learned closure",
@@ -388,7 +389,7 @@ def main():
                                "bounce-back walls in y, periodic x/z, Guo force fx=1e-6, tau=0.8, from rest",
                    "cells": N ** 3, "stencil": "D3Q19", "collision": "TRT", "storage": "f64",
                    "tile": res["tile"], "grid": res["grid"],
-                   "odd_sweep": "lds-staged" if res["lds_staging"] else "direct",
+                   "odd_sweep": ("direct", "lds-staged", "row-vector")[res["lds_staging"]],
                    "nontemporal": {"even": res["nt"][0], "odd": res["nt"][1]},
                    "slot_round_kib": res["slot_round_kib"]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
