@@ -747,7 +747,6 @@ int autotune(wlb_blocks *h)
         h->graph_valid = false;
     }
     h->overlap = false;  // candidates first without the overlap
-    h->nt_even = h->nt_odd = true;
     float best = 1e30f;
     int bs[3] = {0, 0, 0}, bg = 0;
     // repetitions scaled so each candidate runs ~ 2e8 cell updates at most
@@ -755,6 +754,34 @@ int autotune(wlb_blocks *h)
     // WLB_AUTOTUNE_LOG=1 prints every candidate's time to stderr
     const char *env = getenv("WLB_AUTOTUNE_LOG");
     const bool log = env && env[0] == '1';
+    // the cache hints first, on whole-row tiles with the direct odd sweep, so
+    // that the shapes are compared under hints close to the final ones (the
+    // hints can change a sweep's time by a third)
+    {
+        h->lds_stage = false;
+        h->vec_want = false;
+        bool pe = true, po = true;
+        float bt = 1e30f;
+        for (int v = 0; v < 4; ++v) {
+            h->nt_even = (v & 1) == 0;
+            h->nt_odd = (v & 2) == 0;
+            int rc = set_tiles(h, 0, 0, 0, 0);
+            if (rc) return rc;
+            float ms = 0.f;
+            rc = time_pairs(h, reps, &ms);
+            if (rc) return rc;
+            if (log)
+                fprintf(stderr, "[wlb autotune] hints first: nt %d,%d: %.4f ms per two steps\n", h->nt_even ? 1 : 0,
+                        h->nt_odd ? 1 : 0, ms);
+            if (ms < kTuneMargin * bt) {
+                bt = ms;
+                pe = h->nt_even;
+                po = h->nt_odd;
+            }
+        }
+        h->nt_even = pe;
+        h->nt_odd = po;
+    }
     int blds = 0;  // odd-sweep mode: 0 direct, 1 LDS-staged, 2 row vectors
     for (int lds = 0; lds <= 2; ++lds) {
         if (lds == 2 && !(h->vec_ok && h->esize == 8)) continue;
@@ -790,13 +817,14 @@ int autotune(wlb_blocks *h)
             }
         }
     }
-    // the best shape and grid once more with each choice of the non-temporal
-    // hint per parity, with and without LDS staging
-    bool bne = true, bno = true;
+    // the best shape and grid once more with each other choice of the
+    // non-temporal hint per parity, for every odd-sweep kernel
+    const bool ne0 = h->nt_even, no0 = h->nt_odd;  // the hints of the search above
+    bool bne = ne0, bno = no0;
     for (int lds = 0; lds <= 2; ++lds)
         for (int v = 0; v < 4; ++v) {
             const bool ne = (v & 1) == 0, no = (v & 2) == 0;
-            if (ne && no) continue;  // measured above
+            if (ne == ne0 && no == no0) continue;  // measured above
             if (lds == 2 && !(h->vec_ok && h->esize == 8)) continue;
             h->lds_stage = lds == 1;
             h->vec_want = lds == 2;

@@ -1351,21 +1351,43 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         const DevBlock B = a.blocks[tv.x];
         uint32_t mask = 0;
         if (B.mask >= 0) mask = a.masks[B.mask + (int64_t)c.z * B.mplane + c.y * B.mpitch + c.x];
-        if (mask & kSolidBit) continue;
+        // The even sweep loads and stores a solid cell's slots along with the
+        // fluid cells' (no collision, each value back into its own slot), so
+        // that every load and store of the wavefront covers whole lines in
+        // one instruction, which the non-temporal hint needs (a line split
+        // between two instructions is fetched twice).  The odd sweep, whose
+        // stores go to the neighbours, leaves solid cells alone.
+        constexpr bool kMoveSolid = !ODD && !std::is_same_v<ST, cover_t>;
+        const bool solid = (mask & kSolidBit) != 0;
+        if (!kMoveSolid && solid) continue;
         const Links<Q> L = classify<Q>(mask, B, c.x, c.y, c.z, a);
         const uint32_t off = cell_off(B, c.x, c.y, c.z);
         const uint32_t special = L.bb | L.alo | L.ahi;
         T f[Q];
         gather<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f);
         const uint32_t h = kStochastic<ST> ? state_hash<Q, T>(f, global_cell(a, B, c.x, c.y, c.z)) : 0u;
-        const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
-        if (L.alo | L.ahi) {
-            const T rin = (T)a.rho_in, rout = (T)a.rho_out;
-            const T drin = (T)(a.rho_in - 1.0), drout = (T)(a.rho_out - 1.0);
+        if (!solid) {
+            const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
+            if (L.alo | L.ahi) {
+                const T rin = (T)a.rho_in, rout = (T)a.rho_out;
+                const T drin = (T)(a.rho_in - 1.0), drout = (T)(a.rho_out - 1.0);
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
+                    if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout, lo ? drin : drout);
+                });
+            }
+        } else {
+            // the store of link i goes to slot opp(i): swap each pair so that
+            // slot opp(i) gets its own value back (the codecs reproduce a
+            // decoded value exactly, stochastic rounding included)
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                const bool lo = (L.alo >> i) & 1u, hi = (L.ahi >> i) & 1u;
-                if (lo | hi) f[i] = abb_value<Q, i, T>(f[i], m, lo ? rin : rout, lo ? drin : drout);
+                if constexpr (i < opp(i)) {
+                    const T t = f[i];
+                    f[i] = f[opp(i)];
+                    f[opp(i)] = t;
+                }
             });
         }
         scatter<Q, ST, ODD, NT>(a, fresh_bases(B), off, c.x, c.y, c.z, special, f, h);
