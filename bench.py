@@ -395,7 +395,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(head["frac"], 4), "traffic": traffic,
                      "kernel": "sweep_kernel<19,TRT,double> (even AA sweep) and " +
-                               ("sweep_odd_lds_kernel<19,TRT,double>" if res["lds_staging"] else
+                               (("sweep_odd_lds_kernel<19,TRT,double>", "sweep_odd_vec_kernel<19,TRT,double>")
+                                [res["lds_staging"] - 1] if res["lds_staging"] else
+                                "sweep_odd_aligned_nt_kernel<19,TRT,double>" if res["nt"][1] == 2 else
                                 "sweep_kernel<19,TRT,double>") + " (odd AA sweep)",
                      "algorithmic_bytes_per_launch": head["bytes_per_launch"],
                      "avg_launch_ms": round(head["sweep_ms"], 5), "even_launch_ms": round(head["even_ms"], 5),

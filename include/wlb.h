@@ -245,7 +245,8 @@ typedef struct {
     size_t pop_bytes;       /* bytes of population storage incl. ghosts */
     int32_t overlap;        /* 1: sweeps split into interior and frontier, exchange overlapped */
     int32_t nt_even;        /* 1: the even sweep's population accesses are non-temporal */
-    int32_t nt_odd;         /* 1: the odd sweep's population accesses are non-temporal */
+    int32_t nt_odd;         /* 1: the odd sweep's population accesses are non-temporal; 2: only
+                               its aligned ones (populations with c_x = 0) */
     int32_t n_class_tiles;  /* classes of x-runs (by y extent) whose tile shape the autotuner
                                set apart from `tile` (0: one shape for every run) */
     int32_t slot_round_kib; /* population slots of 64 MiB or more start on multiples of this
@@ -328,13 +329,16 @@ int wlb_set_lds_staging(wlb_blocks_t h, int32_t on);
 int wlb_set_overlap(wlb_blocks_t h, int32_t on);
 
 /* Non-temporal hint (1, default) or ordinary cached accesses (0) for the
- * population loads and stores of the even and of the odd sweep.  Streamed
- * once per sweep, the populations usually gain from the hint; accesses one
- * element off the row alignment, and short rows whose cache lines neighbouring
- * waves share, can gain from the cache instead.  Results are bitwise identical
- * either way.  The autotuner tries all four settings (with and without LDS
- * staging) for the best tile configuration.
- * Errors: WLB_ERR_ARG for a null handle. */
+ * population loads and stores of the even and of the odd sweep; for the odd
+ * sweep also 2: the hint on its aligned accesses only (the populations with
+ * c_x = 0, whole lines per wavefront), the others cached.  Streamed once per
+ * sweep, the populations usually gain from the hint; accesses one element
+ * off the row alignment, and short rows whose cache lines neighbouring waves
+ * share, can gain from the cache instead.  Results are bitwise identical
+ * either way.  The autotuner tries all six settings (with and without LDS
+ * staging; 2 and 1 are the same for the LDS-staged and row-vector odd
+ * sweeps, whose accesses are all aligned) for the best tile configuration.
+ * Errors: WLB_ERR_ARG for a null handle or an odd-sweep hint outside 0..2. */
 int wlb_set_nontemporal(wlb_blocks_t h, int32_t even, int32_t odd);
 
 /* Use (1) or bypass (0) the captured HIP graph in wlb_lbm_step. */

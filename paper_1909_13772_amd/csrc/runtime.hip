@@ -116,7 +116,10 @@ struct wlb_blocks {
     // stream while the interior runs on the bound stream (autotuner candidate)
     bool overlap = false;
     bool cover = false;   // sweeps and exchanges count writes (wlb_debug_write_coverage)
-    bool nt_even = true, nt_odd = true;  // non-temporal population accesses per parity (autotuner candidate)
+    // non-temporal population accesses per parity (autotuner candidates); the
+    // odd sweep: 0 none, 1 every access, 2 its aligned accesses only
+    bool nt_even = true;
+    int nt_odd = 1;
     int nint_tiles = 0;   // interior box tiles come first in `tiles` when split
     int nint_ltiles = 0;  // interior fluid-cell tiles come first in `ltiles`
     bool tiles_split = false;
@@ -385,7 +388,7 @@ int launch_grid(const wlb_blocks *h)
 hipError_t sweep_launch(const wlb_blocks *h, bool odd, const SweepArgs &args, int g, hipStream_t st)
 {
     SweepArgs a = args;
-    a.nt = (odd ? h->nt_odd : h->nt_even) ? 1 : 0;
+    a.nt = odd ? h->nt_odd : (h->nt_even ? 1 : 0);
     // the row-vector odd sweep exists for FP64 storage (and the counting
     // storage of the write-coverage check); other storage runs the direct one
     if (a.vec_odd && !(h->esize == 8 || h->cover)) a.vec_odd = 0;
@@ -735,6 +738,9 @@ int time_pairs(wlb_blocks *h, int reps, float *ms_out)
 
 // Factor by which a candidate must beat the best time so far to replace it.
 constexpr float kTuneMargin = 0.995f;
+// Cache-hint choices of the odd sweep in the order the autotuner tries them
+// (non-temporal on every access, on none, on the aligned accesses only).
+constexpr int kOddHints[3] = {1, 0, 2};
 
 int autotune(wlb_blocks *h)
 {
@@ -760,11 +766,12 @@ int autotune(wlb_blocks *h)
     {
         h->lds_stage = false;
         h->vec_want = false;
-        bool pe = true, po = true;
+        bool pe = true;
+        int po = 1;
         float bt = 1e30f;
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 6; ++v) {
             h->nt_even = (v & 1) == 0;
-            h->nt_odd = (v & 2) == 0;
+            h->nt_odd = kOddHints[v >> 1];
             int rc = set_tiles(h, 0, 0, 0, 0);
             if (rc) return rc;
             float ms = 0.f;
@@ -772,7 +779,7 @@ int autotune(wlb_blocks *h)
             if (rc) return rc;
             if (log)
                 fprintf(stderr, "[wlb autotune] hints first: nt %d,%d: %.4f ms per two steps\n", h->nt_even ? 1 : 0,
-                        h->nt_odd ? 1 : 0, ms);
+                        h->nt_odd, ms);
             if (ms < kTuneMargin * bt) {
                 bt = ms;
                 pe = h->nt_even;
@@ -819,12 +826,16 @@ int autotune(wlb_blocks *h)
     }
     // the best shape and grid once more with each other choice of the
     // non-temporal hint per parity, for every odd-sweep kernel
-    const bool ne0 = h->nt_even, no0 = h->nt_odd;  // the hints of the search above
-    bool bne = ne0, bno = no0;
+    const bool ne0 = h->nt_even;  // the hints of the search above
+    const int no0 = h->nt_odd;
+    bool bne = ne0;
+    int bno = no0;
     for (int lds = 0; lds <= 2; ++lds)
-        for (int v = 0; v < 4; ++v) {
-            const bool ne = (v & 1) == 0, no = (v & 2) == 0;
+        for (int v = 0; v < 6; ++v) {
+            const bool ne = (v & 1) == 0;
+            const int no = kOddHints[v >> 1];
             if (ne == ne0 && no == no0) continue;  // measured above
+            if (lds != 0 && no == 2) continue;  // every access of those odd sweeps is aligned: same as 1
             if (lds == 2 && !(h->vec_ok && h->esize == 8)) continue;
             h->lds_stage = lds == 1;
             h->vec_want = lds == 2;
@@ -839,7 +850,7 @@ int autotune(wlb_blocks *h)
             if (rc) return rc;
             if (log)
                 fprintf(stderr, "[wlb autotune] tile %d,%d,%d grid %d lds %d nt %d,%d: %.4f ms per two steps\n", bs[0],
-                        bs[1], bs[2], bg, lds, ne ? 1 : 0, no ? 1 : 0, ms);
+                        bs[1], bs[2], bg, lds, ne ? 1 : 0, no, ms);
             if (ms < kTuneMargin * best) {
                 best = ms;
                 blds = lds;
@@ -1707,7 +1718,7 @@ int wlb_info(wlb_blocks_t h, wlb_info_t *o)
     o->lds_staging = (h->args.vec_odd && h->esize == 8) ? 2 : (h->args.lds_stride > 0 ? 1 : 0);
     o->overlap = split_sweeps(h) ? 1 : 0;
     o->nt_even = h->nt_even ? 1 : 0;
-    o->nt_odd = h->nt_odd ? 1 : 0;
+    o->nt_odd = h->nt_odd;
     o->n_xchg_items = (int32_t)h->pull.size();
     o->xchg_elems = h->xchg_elems;
     o->arena_bytes = h->arena_bytes;
@@ -1765,8 +1776,9 @@ int wlb_set_slot_round(wlb_blocks_t h, int32_t kib)
 int wlb_set_nontemporal(wlb_blocks_t h, int32_t even, int32_t odd)
 {
     if (!h) return fail(WLB_ERR_ARG, "null handle");
+    if (odd < 0 || odd > 2) return fail(WLB_ERR_ARG, "odd-sweep hint must be 0, 1 or 2");
     h->nt_even = even != 0;
-    h->nt_odd = odd != 0;
+    h->nt_odd = odd;
     h->graph_valid = false;  // the captured launches hold the old arguments
     return WLB_OK;
 }

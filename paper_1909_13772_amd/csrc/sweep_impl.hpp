@@ -1163,11 +1163,23 @@ __device__ __forceinline__ uint32_t xshift(const XOff &o)
     return dx < 0 ? o.left : (dx > 0 ? o.right : o.at);
 }
 
+// Hint of an x-shifted (odd-sweep / swapped-layout) access of a population
+// with x velocity cx.  AO (aligned only): the non-temporal hint goes to the
+// accesses of populations with cx = 0, which cover whole lines per
+// wavefront; those with cx != 0 sit one element off the row alignment and
+// share their edge lines with the neighbouring wavefronts, which meet in L2
+// only without the hint.
+template <bool NT, int cx, bool AO>
+__device__ __forceinline__ constexpr bool nt_shifted()
+{
+    return NT && (!AO || cx == 0);
+}
+
 // Gather the populations f_i(x) of a fluid cell for the current layout:
 // natural (after an odd sweep / init) reads slot i of x; swapped (after an
 // even sweep) reads slot opp(i) of x - c_i, or slot i of x on bounce-back /
 // anti-bounce-back links.
-template <int Q, typename ST, bool SWAPPED, bool NT = true>
+template <int Q, typename ST, bool SWAPPED, bool NT = true, bool AO = false>
 __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, int y, int z,
                                        uint32_t special, typename Codec<ST>::T (&f)[Q])
 {
@@ -1179,13 +1191,13 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const Alt<ST> p = alt_in<Q, ST, i>(a, B);
-                f[i] = ldv<Q, ST, NT>(at<ST>(p.base + p.add_reg, xshift<-cx<Q>(i)>(o)), i);
+                f[i] = ldv<Q, ST, nt_shifted<NT, cx<Q>(i), AO>()>(at<ST>(p.base + p.add_reg, xshift<-cx<Q>(i)>(o)), i);
             });
         } else {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const Alt<ST> p = alt_in<Q, ST, i>(a, B);
-                f[i] = ldv<Q, ST, NT>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
+                f[i] = ldv<Q, ST, nt_shifted<NT, cx<Q>(i), AO>()>(at<ST>(p.base, ((special >> opp(i)) & 1u) ? o.at + p.add_sp
                                                                              : xshift<-cx<Q>(i)>(o) + p.add_reg),
                                       i);
             });
@@ -1227,7 +1239,7 @@ __device__ __forceinline__ void gather(const SweepArgs &a, const DevBlock &B, ui
 // Store the post-collision populations of a fluid cell: even sweep into
 // slot opp(i) of x; odd sweep into slot i of x + c_i, or slot opp(i) of x on
 // bounce-back / anti-bounce-back links.
-template <int Q, typename ST, bool ODD, bool NT = true>
+template <int Q, typename ST, bool ODD, bool NT = true, bool AO = false>
 __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, uint32_t off, int x, int y, int z,
                                         uint32_t special, const typename Codec<ST>::T (&f)[Q], uint32_t h)
 {
@@ -1237,13 +1249,13 @@ __device__ __forceinline__ void scatter(const SweepArgs &a, const DevBlock &B, u
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-                stv_sr<Q, ST, NT>(at<ST>(p.base + p.add_reg, xshift<cx<Q>(i)>(o)), f[i], i, h);
+                stv_sr<Q, ST, nt_shifted<NT, cx<Q>(i), AO>()>(at<ST>(p.base + p.add_reg, xshift<cx<Q>(i)>(o)), f[i], i, h);
             });
         } else {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 const Alt<ST> p = alt_out<Q, ST, i>(a, B);
-                stv_sr<Q, ST, NT>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg),
+                stv_sr<Q, ST, nt_shifted<NT, cx<Q>(i), AO>()>(at<ST>(p.base, ((special >> i) & 1u) ? o.at + p.add_sp : xshift<cx<Q>(i)>(o) + p.add_reg),
                                   f[i], i, h);
             });
         }
@@ -1338,9 +1350,9 @@ __device__ __forceinline__ void store_regular_out(const SweepArgs &a, const DevB
 #endif
 // NT: the population accesses carry the non-temporal hint (the autotuner
 // chooses it per parity).
-template <int Q, int COLL, typename ST, bool ODD, bool NT>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_PER_EU, 8))) void sweep_kernel(
-    const SweepArgs a)
+// AO: the odd sweep's hint on its aligned accesses only (nt_shifted).
+template <int Q, int COLL, typename ST, bool ODD, bool NT, bool AO>
+__device__ __forceinline__ void sweep_tiles(const SweepArgs &a)
 {
     using T = typename Codec<ST>::T;
     for (int t = first_tile(a); t < a.nstiles; t += gridDim.x) {
@@ -1364,7 +1376,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
         const uint32_t off = cell_off(B, c.x, c.y, c.z);
         const uint32_t special = L.bb | L.alo | L.ahi;
         T f[Q];
-        gather<Q, ST, ODD, NT>(a, B, off, c.x, c.y, c.z, special, f);
+        gather<Q, ST, ODD, NT, AO>(a, B, off, c.x, c.y, c.z, special, f);
         const uint32_t h = kStochastic<ST> ? state_hash<Q, T>(f, global_cell(a, B, c.x, c.y, c.z)) : 0u;
         if (!solid) {
             const Macro<Q, T> m = collide<Q, COLL, T, AccOf<ST>>(f, cp);
@@ -1390,8 +1402,25 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_P
                 }
             });
         }
-        scatter<Q, ST, ODD, NT>(a, fresh_bases(B), off, c.x, c.y, c.z, special, f, h);
+        scatter<Q, ST, ODD, NT, AO>(a, fresh_bases(B), off, c.x, c.y, c.z, special, f, h);
     }
+}
+
+template <int Q, int COLL, typename ST, bool ODD, bool NT>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_PER_EU, 8))) void sweep_kernel(
+    const SweepArgs a)
+{
+    sweep_tiles<Q, COLL, ST, ODD, NT, false>(a);
+}
+
+// Odd sweep with the non-temporal hint on its aligned accesses only (the
+// populations with c_x = 0); an autotuner candidate beside the odd sweep
+// with the hint on every access and the one without it.
+template <int Q, int COLL, typename ST>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WLB_WAVES_PER_EU, 8))) void sweep_odd_aligned_nt_kernel(
+    const SweepArgs a)
+{
+    sweep_tiles<Q, COLL, ST, true, true, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -2214,6 +2243,12 @@ static hipError_t sweep_qn(bool odd, const SweepArgs &a, int grid, hipStream_t s
             hipLaunchKernelGGL((sweep_odd_lds_kernel<Q, COLL, WLB_STORAGE, false, NT>), dim3(grid), dim3(kWG), bytes, st,
                                a);
         return hipGetLastError();
+    }
+    if constexpr (NT && !std::is_same_v<WLB_STORAGE, cover_t>) {
+        if (odd && a.nt == 2) {  // the hint on the aligned accesses only
+            hipLaunchKernelGGL((sweep_odd_aligned_nt_kernel<Q, COLL, WLB_STORAGE>), dim3(grid), dim3(kWG), 0, st, a);
+            return hipGetLastError();
+        }
     }
     if (odd)
         hipLaunchKernelGGL((sweep_kernel<Q, COLL, WLB_STORAGE, true, NT>), dim3(grid), dim3(kWG), 0, st, a);

@@ -98,7 +98,8 @@ struct SweepArgs {
     int32_t lds_stride;    // > 0: odd sweep stages x-shifted populations in LDS rows of this many elements
     int32_t lds_ring;      // 1: every tile is a whole row of a self-wrapping block (staged sweep without halos)
     int32_t xcd_map;       // 1: one workgroup per tile, each XCD takes a contiguous range of tiles
-    int32_t nt;            // 1: the sweep's population accesses carry the non-temporal hint
+    int32_t nt;            // 1: the sweep's population accesses carry the non-temporal hint; 2 (odd
+                           // sweep): only its aligned ones (populations with c_x = 0)
     int32_t vec_odd;       // 1: the odd sweep moves whole rows as 16-byte vectors per lane (vtiles)
     int32_t nvtiles;
     const int4 *vtiles;    // row tiles of the vector odd sweep: {block, 0 | n0 << 16, y0 | ey << 16, z0 | ez << 16}

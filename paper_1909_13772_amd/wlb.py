@@ -411,7 +411,8 @@ class Blocks:
         wlb_set_lds_staging(self.h, on)
 
     def set_nontemporal(self, even, odd):
-        _check(_lib.wlb_set_nontemporal(self.h, int(bool(even)), int(bool(odd))))
+        # odd: 0 cached, 1 non-temporal, 2 non-temporal on the aligned accesses only
+        _check(_lib.wlb_set_nontemporal(self.h, int(bool(even)), int(odd)))
 
     def set_class_tiles(self, y_extent, tx, ty, tz):
         _check(_lib.wlb_set_class_tiles(self.h, int(y_extent), int(tx), int(ty), int(tz)))

@@ -204,6 +204,23 @@ def test_create_rejects_bad_block_lists(bad):
     assert e.value.code == wlb.WLB_ERR_ARG
 
 
+def test_nontemporal_hint_values():
+    """The odd sweep takes hint 0, 1 or 2 (non-temporal on its aligned
+    accesses only); other values are rejected and leave the setting alone."""
+    h, _ = wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 19, wlb.F64)
+    try:
+        for odd in (0, 1, 2):
+            wlb._check(wlb._lib.wlb_set_nontemporal(h, 1, odd))
+            assert wlb.wlb_info(h).nt_odd == odd
+        for odd in (-1, 3):
+            with pytest.raises(wlb.WlbError) as e:
+                wlb._check(wlb._lib.wlb_set_nontemporal(h, 1, odd))
+            assert e.value.code == wlb.WLB_ERR_ARG
+        assert wlb.wlb_info(h).nt_odd == 2
+    finally:
+        wlb.wlb_blocks_destroy(h)
+
+
 def test_create_rejects_bad_enums():
     with pytest.raises(wlb.WlbError):
         wlb.wlb_blocks_create([((0, 0, 0), (8, 8, 8))], (8, 8, 8), (1, 1, 1), 13, wlb.F64)

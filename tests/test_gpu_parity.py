@@ -160,10 +160,11 @@ def test_porous_uneven_blocks_lds_staged_odd_sweep_fp64(q, coll):
 
 
 @pytest.mark.parametrize("q,coll", [(19, 1), (27, 2)])
-@pytest.mark.parametrize("nt,lds", [((0, 0), False), ((0, 0), True), ((1, 0), False)])
+@pytest.mark.parametrize("nt,lds", [((0, 0), False), ((0, 0), True), ((1, 0), False), ((1, 2), False)])
 def test_porous_uneven_blocks_cached_accesses_fp64(q, coll, nt, lds):
     """The porous case with ordinary (cached) instead of non-temporal
-    population accesses in one or both sweeps."""
+    population accesses in one or both sweeps, or the odd sweep's hint on
+    its aligned accesses only."""
     say(f"case porous nt{nt} lds{lds} q{q} coll{coll}")
     gpu, orc, solid, dom = _porous_case(q, coll, wlb.F64, 11, nt=nt, lds=lds)
     i = gpu[4].info()
@@ -392,9 +393,11 @@ def test_tiles_grid_graph_and_split_are_bitwise_invariant():
             dict(overlap=True, tiles=(16, 4, 4, -1)), dict(overlap=True, tiles=(64, 4, 1, 7)),
             dict(overlap=True, tiles=(-1, 0, 0, 0)), dict(overlap=True, tiles=(-1, 0, 0, -1), graph=False),
             dict(overlap=True, lds=True),
-            # cached instead of non-temporal population accesses
+            # cached instead of non-temporal population accesses, and the odd
+            # sweep's hint on its aligned accesses only
             dict(nt=(0, 0)), dict(nt=(1, 0), lds=True), dict(nt=(0, 1), tiles=(-1, 0, 0, 0)),
-            dict(nt=(0, 0), overlap=True)]
+            dict(nt=(0, 0), overlap=True), dict(nt=(1, 2)), dict(nt=(0, 2), tiles=(-1, 0, 0, 0)),
+            dict(nt=(1, 2), overlap=True), dict(nt=(1, 2), lds=True)]
     ref = None
     for kw in runs:
         d, r, uu, tot, B = gpu_run(blocks, dom, (1, 1, 0), 19, wlb.F32, wlb.TRT, p, rho, u, solid, steps=13, **kw)
@@ -439,7 +442,7 @@ def test_tile_shape_per_class_of_runs_is_bitwise_invariant():
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
-@pytest.mark.parametrize("nt", [(1, 0), (0, 0), (1, 1)])
+@pytest.mark.parametrize("nt", [(1, 0), (0, 0), (1, 1), (1, 2)])
 def test_solid_cells_keep_their_populations(storage, nt):
     """The even sweep stores each solid cell's values back into their own
     slots (in the same instructions as the fluid cells): over many steps the
